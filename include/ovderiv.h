@@ -1,0 +1,181 @@
+/*
+ * libovderiv -- two-sided Lanczos approximation of sgn(H(mu)) b, its
+ * derivative by the block-matrix method, generalised deflation and the
+ * gradient of <x|sgn(H)|b>, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Puhr & Buividovich, "A method to compute derivatives of functions
+ * of large complex matrices" (Lattice 2016, arXiv:1611.00195).
+ *   Sec. 1, eq. 1   kernel H(mu) = gamma5 Dw(mu) of the overlap operator;
+ *   Sec. 2          only the action y = f(A) x is needed; d_t y = (d_t f(A)) x;
+ *   Sec. 2, eq. 6-7 f([[A, dA], [0, A]]) (0; x) = (d_t f(A) x ; f(A) x);
+ *   Sec. 2 (end)    two-sided Lanczos (TSL) for the sign of a non-Hermitian matrix;
+ *   Sec. 3, eq. 8   standard deflation;  eq. 9-11  generalised deflation.
+ *
+ * Conventions shared by every call
+ *   Lattice dims = {Lx, Ly, Lz, Lt}; site index s = x + Lx*(y + Ly*(z + Lz*t)).
+ *   Spinor field: complex128 (interleaved re, im) [V][4 spin][3 colour],
+ *     component index 3*spin + colour.  Chiral basis, gamma5 = diag(1,1,-1,-1).
+ *   Link field:   complex128 [4][V][3][3], direction order x, y, z, t,
+ *     row-major 3x3.  The time boundary factor t_bc (-1 antiperiodic) is
+ *     applied by the stencil on the hops crossing t = Lt-1 <-> 0, never
+ *     stored in the links.
+ *   Dw(mu) psi(x) = (m0 + 4r) psi(x) - 1/2 sum_nu [ e^{mu d_nu4} (r - gamma_nu) U_nu(x) psi(x+nu)
+ *                    + e^{-mu d_nu4} (r + gamma_nu) U_nu(x-nu)^dag psi(x-nu) ].
+ *   Only r = 1 is supported on the GPU path (the spin-projection trick).
+ *
+ * Memory and streams
+ *   Every array argument marked "device" is a device pointer owned by the
+ *   caller (for example a torch tensor on the handle's device); "host"
+ *   pointers are ordinary host memory.  Work is enqueued on the stream given
+ *   at creation (NULL = the null stream).  Calls that return host scalars
+ *   (xdy, s, ds_dmu, stats) synchronise that stream before returning; the
+ *   others return after enqueueing.  The handle owns its workspaces, a copy
+ *   of the links and the deflation data, all freed by ovd_destroy.
+ *
+ * Errors
+ *   Every call returns an ovd_status; on failure ovd_last_error(h) holds a
+ *   message.  A handle is not thread-safe: use one handle per host thread.
+ */
+#ifndef OVDERIV_H
+#define OVDERIV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ovd_lattice* ovd_h;
+
+typedef enum {
+    OVD_OK = 0,
+    OVD_EINVAL = -1,      /* bad argument (sizes, null pointers, unsupported r, ...) */
+    OVD_ENOMEM = -2,      /* device allocation failed */
+    OVD_EHIP = -3,        /* a HIP runtime call failed */
+    OVD_EBREAKDOWN = -4,  /* serious Lanczos breakdown: |w^dag v| <= tau |w| |v| */
+    OVD_ENODEFL = -5,     /* deflation requested for a mu with no deflation set */
+    OVD_ENAN = -6         /* non-finite value detected in the recurrence */
+} ovd_status;
+
+enum { OVD_FP64 = 0, OVD_MIXED = 1 };        /* precision of Krylov vectors and stencil */
+enum { OVD_LEFT_SUM = 0, OVD_LEFT_SAME = 1 };  /* left start of the block system */
+enum { OVD_DIR_MU = 0, OVD_DIR_LINK = 1 };     /* derivative direction t */
+enum { OVD_OP_H = 0, OVD_OP_DW = 1, OVD_OP_DH_DMU = 2, OVD_OP_DH_DLINK = 3 };
+
+typedef struct {
+    int precision;          /* OVD_FP64 (default) or OVD_MIXED: FP32 vectors, links and
+                               stencil arithmetic; FP64 inner products, Lanczos scalars,
+                               T_k, sgn(T_k) and deflation */
+    int left_start;         /* left start of the block system, see ovd_sign_apply_deriv */
+    double breakdown_tol;   /* tau, default 1e-14 */
+    double quad_step;       /* first refined step of the trapezoidal rule in log(y) used for
+                               sgn(T_k) e_1 (halved until two levels agree to 1e-10),
+                               default 0.1 */
+} ovd_options;
+
+typedef struct {
+    int kind;               /* OVD_DIR_MU or OVD_DIR_LINK */
+    const void* dU;         /* OVD_DIR_LINK: device complex128 [4][V][3][3], dU = dU/dt
+                               (e.g. X U for U -> exp(tX) U); ignored for OVD_DIR_MU */
+} ovd_dir;
+
+typedef struct {
+    int k;                  /* Krylov steps taken */
+    int breakdown_step;     /* first step with a serious breakdown, -1 if none */
+    double min_margin;      /* min over steps and right-hand sides of |w^dag v|/(|w||v|) */
+    double sign_check;      /* error estimate of sgn(T_k) e_1: max difference between the last two
+                               refinement levels of the quadrature (see quad_step) */
+    double ms_lanczos;      /* device time of the Lanczos steps (HIP events) */
+    double ms_small_sign;   /* device time of the sgn(T_k) e_1 solve */
+    double ms_total;        /* device time of the whole call */
+} ovd_stats;
+
+/* Create a handle for one lattice.  Sec. 4 lattices are Lt x Ls^3 (e.g. 14 x 14^3).
+ *   dims      host int[4] = {Lx, Ly, Lz, Lt}, each >= 2
+ *   m0, r     Wilson mass and Wilson parameter (r must be 1)
+ *   t_bc      +1 periodic or -1 antiperiodic time boundary
+ *   opt       host, nullable (defaults above)
+ *   stream    hipStream_t to enqueue on (NULL = null stream)
+ *   out       host, receives the handle */
+ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc,
+                              const ovd_options* opt, void* stream, ovd_h* out);
+ovd_status ovd_destroy(ovd_h h);
+const char* ovd_last_error(ovd_h h);
+ovd_status ovd_set_stream(ovd_h h, void* stream);
+
+/* Upload a gauge configuration (Sec. 4: the derivative is taken on SU(3)
+ * configurations).  U: device complex128 [4][V][3][3].  The handle keeps an
+ * FP64 copy and, for OVD_MIXED, an FP32 copy in its own layout. */
+ovd_status ovd_set_links(ovd_h h, const void* U);
+
+/* Apply one operator to nrhs spinor fields (used for stencil checks and the
+ * Dw.v bandwidth measurement).
+ *   op    OVD_OP_H: H(mu) = gamma5 Dw(mu) (eq. 1; its adjoint is H(-mu));
+ *         OVD_OP_DW: Dw(mu);  OVD_OP_DH_DMU: dH/dmu;
+ *         OVD_OP_DH_DLINK: dH/dt along dir->dU.
+ *   in, out  device complex128 [nrhs][V][4][3]; must not alias.
+ *   ms    host, nullable: device time of the stencil kernel alone. */
+ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs,
+                        const void* in, void* out, double* ms);
+
+/* Deflation set for one mu (Sec. 3, eq. 8 and eq. 10-11).  Replaces any set
+ * stored for the same mu.
+ *   m        number of eigenpairs of H(mu) used by ovd_sign_apply (eq. 8)
+ *   lam      host complex128 [m] eigenvalues, closest to zero first
+ *   R, L     device complex128 [m][V][4][3] right / left eigenvectors with
+ *            L_i^dag R_j = delta_ij (checked; OVD_EINVAL if violated by > 1e-8)
+ *   l        number of Jordan blocks of B deflated by ovd_sign_apply_deriv
+ *            (0 <= l <= m; only the first l pairs are used there)
+ *   dR, dL   device complex128 [l][V][4][3], t-derivatives of the first l
+ *            R_i, L_i along dir, gauge L_i^dag dR_i = 0 = dL_i^dag R_i; may be
+ *            NULL when l = 0
+ *   dir      the direction dR, dL belong to (nullable when l = 0) */
+ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam,
+                             const void* R, const void* L, int l,
+                             const void* dR, const void* dL, const ovd_dir* dir);
+ovd_status ovd_clear_deflation(ovd_h h);
+
+/* y = sgn(H(mu)) b by k steps of two-sided Lanczos with left start equal to
+ * the (deflated) source, y ~ |b'| V_k sgn(T_k) e_1 + exact part (eq. 8 when a
+ * deflation set for mu exists).  Batched over nrhs independent systems.
+ *   mu    host double[nrhs] (each mu must have a deflation set, or none at all)
+ *   b, y  device complex128 [nrhs][V][4][3]
+ *   st    host, nullable */
+ovd_status ovd_sign_apply(ovd_h h, int nrhs, const double* mu, int k,
+                          const void* b, void* y, ovd_stats* st);
+
+/* Derivative along dir of sgn(H(mu)) b by the block method (eq. 6-7): k steps
+ * of two-sided Lanczos on B = [[H, dH], [0, H]] with source psi = (0; b),
+ * deflated by eq. 11 with the first l pairs of the deflation set for mu when
+ * one exists.  Left start (not fixed by the paper): OVD_LEFT_SUM uses
+ * (psi_t + psi_b; psi_b), OVD_LEFT_SAME uses psi.
+ *   b         device complex128 [nrhs][V][4][3]
+ *   y, dy     device complex128 [nrhs][V][4][3] or NULL: sgn(H) b and its derivative
+ *   x         device complex128 [nrhs][V][4][3] or NULL
+ *   xdy       host complex128 [nrhs] or NULL: <x|d sgn(H) b>; when y and dy are both
+ *             NULL the Krylov basis is never stored (storage-free scalar mode) */
+ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir,
+                                int k, const void* b, void* y, void* dy,
+                                const void* x, double* xdy, ovd_stats* st);
+
+/* Gradient of s = <x|sgn(H(mu))|b> (the bilinear the paper's currents and
+ * fermionic force are built from, Sec. 1): two-sided Lanczos with right start
+ * b and left start x, s ~ (x^dag b)[sgn(T_k)]_11, and with
+ * M_k = L_sgn(T_k, e_1 e_1^T) the derivative ds/dt ~ (x^dag b) tr(M_k W_k^dag dH V_k).
+ *   x, b      device complex128 [V][4][3]
+ *   s, ds_dmu host complex128 [1], nullable
+ *   F         device complex128 [4][V][3][3] or NULL: per-link force with
+ *             ds/dt = tr(F_nu(y) X) for U_nu(y) -> exp(tX) U_nu(y)
+ * Deflation is not applied. */
+ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b,
+                              double* s, double* ds_dmu, void* F, ovd_stats* st);
+
+/* Lanczos coefficients of the last Lanczos run (for parity checks), right-hand
+ * side rhs: host complex128 arrays alpha[k], beta[k], delta[k].  T_k has
+ * diagonal alpha[0..k-1], super-diagonal beta[1..k-1] and sub-diagonal
+ * delta[1..k-1]; delta[0] = |psi| and beta[0] = phi^dag psi / |psi| are the
+ * start-vector normalisations. */
+ovd_status ovd_get_tridiag(ovd_h h, int rhs, int k, double* alpha, double* beta, double* delta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OVDERIV_H */

@@ -1,0 +1,536 @@
+// C ABI of libovderiv and the host-side driver of the two-sided Lanczos
+// pipeline (see include/ovderiv.h for the contract of every entry point).
+//
+// Pipeline of one call (all on the handle's stream, no host round trip until
+// the end):
+//   1. pack the AoS complex128 inputs into the internal [12][Vp] layout and
+//      form the right / left start vectors (block system: (0; b) and, for the
+//      left start, (b; b));
+//   2. k fused Lanczos steps (one kernel each, one grid reduction each; the
+//      scalar recurrence advances on the device);
+//   3. sgn(T_k) e_1 by the resolvent quadrature (FP64);
+//   4. |psi| V_k sgn(T_k) e_1 from the stored basis, or the storage-free
+//      scalar |psi| sum_j c_j <x|v_j>.
+#include "ovd_internal.h"
+#include "../../include/ovderiv.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+using namespace ovd;
+
+struct DeflSet {
+    double mu = 0;
+    int m = 0, l = 0;
+    std::vector<c64> lam;
+    c64* R = nullptr;   // SoA [m][12][Vp] FP64
+    c64* L = nullptr;
+    c64* dR = nullptr;  // [l][12][Vp]
+    c64* dL = nullptr;
+};
+
+struct ovd_lattice {
+    Geom g{};
+    double m0 = -1.5, r = 1.0;
+    ovd_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    c64* U64 = nullptr;
+    c32* U32 = nullptr;
+    c64* dU64 = nullptr;
+    c32* dU32 = nullptr;
+    bool links_set = false;
+    std::map<std::string, std::pair<void*, size_t>> ws;
+    std::vector<DeflSet> defl;
+    // coefficients of the last Lanczos run
+    int last_nrhs = 0, last_k = 0;
+    TslCoeffs last_co{};
+};
+
+namespace {
+
+ovd_status fail(ovd_h h, ovd_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(h, OVD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// grow-only named workspace
+void* ws_get(ovd_h h, const std::string& name, size_t bytes, ovd_status* st) {
+    auto it = h->ws.find(name);
+    if (it != h->ws.end() && it->second.second >= bytes) return it->second.first;
+    if (it != h->ws.end()) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(it->second.first);
+        h->ws.erase(it);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+        *st = fail(h, OVD_ENOMEM, "hipMalloc of workspace '" + name + "' (" + std::to_string(bytes) + " bytes) failed");
+        return nullptr;
+    }
+    h->ws[name] = {p, bytes};
+    return p;
+}
+
+#define WS(var, type, name, count)                                                   \
+    type* var = (type*)ws_get(h, name, sizeof(type) * (size_t)(count), &wst);        \
+    if (!var) return wst;
+
+struct Timer {
+    hipEvent_t a{}, b{};
+    bool ok = false;
+    void start(hipStream_t s) {
+        ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+        if (ok) (void)hipEventRecord(a, s);
+    }
+    void stop(hipStream_t s) {
+        if (ok) (void)hipEventRecord(b, s);
+    }
+    double ms() {
+        float t = 0.f;
+        if (ok && hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
+        return t;
+    }
+    ~Timer() {
+        if (ok) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    }
+};
+
+// fill per-rhs coefficient vector coef[r][j] = delta[r][0] * c[r][j] / delta[r][j]
+__global__ void make_coef_kernel(int k, TslCoeffs co, const c64* __restrict__ c, c64* __restrict__ coef) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= k) return;
+    const double d0 = co.delta[(size_t)r * co.kmax].re;
+    const double dj = co.delta[(size_t)r * co.kmax + j].re;
+    coef[(size_t)r * k + j] = (d0 / dj) * c[(size_t)r * k + j];
+}
+
+// left start of the block system: dst = (src_top + src_bot; src_bot)
+template <typename T>
+__global__ void left_sum_kernel(Geom g, const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst, long long stride) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= g.V) return;
+    const size_t HALF = (size_t)12 * g.Vp;
+    const cpx<T>* a = src + r * stride;
+    cpx<T>* o = dst + r * stride;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const size_t i = (size_t)c * g.Vp + s;
+        const cpx<T> t = a[i], b = a[HALF + i];
+        o[i] = t + b;
+        o[HALF + i] = b;
+    }
+}
+
+ovd_status check_handle(ovd_h h) {
+    if (!h) return OVD_EINVAL;
+    if (!h->links_set) return fail(h, OVD_EINVAL, "links not set (call ovd_set_links first)");
+    return OVD_OK;
+}
+
+// Core two-sided Lanczos run on nrhs systems.
+//   dir 0: A = H;  dir 1/2: A = B (d/dmu, d/dlink).
+//   src_v/src_w: SoA start vectors (stride fsz per rhs).  xproj: SoA (stride 12*Vp) or null.
+//   basis: if non-null, V-hat_1..V-hat_k are kept there ([rhs][k][fsz]).
+template <typename T>
+ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cpx<T>* src_v,
+                   const cpx<T>* src_w, const cpx<T>* xproj, cpx<T>* basis, c64* c_out, ovd_stats* stats) {
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    const int halves = dir == 0 ? 1 : 2;
+    const long long fsz = (long long)halves * 12 * g.Vp;
+    const cpx<T>* U = std::is_same<T, double>::value ? (const cpx<T>*)h->U64 : (const cpx<T>*)h->U32;
+    const cpx<T>* dU = std::is_same<T, double>::value ? (const cpx<T>*)h->dU64 : (const cpx<T>*)h->dU32;
+    const int ngroups = (g.V + 63) / 64;
+    const int nb = (ngroups + 7) / 8 * 8;
+
+    WS(ring, cpx<T>, "tsl_ring", (size_t)10 * nrhs * fsz);
+    WS(st, TslState, "tsl_state", nrhs);
+    WS(coef, c64, "tsl_coef", (size_t)4 * nrhs * k);
+    WS(partials, double, "tsl_partials", (size_t)nrhs * nb * 8);
+    WS(counters, unsigned, "tsl_counters", nrhs);
+    HIPCHK(hipMemsetAsync(counters, 0, sizeof(unsigned) * nrhs, h->stream));
+    HIPCHK(hipMemsetAsync(coef, 0, sizeof(c64) * 4 * nrhs * k, h->stream));
+    std::vector<TslState> hs(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        TslState s{};
+        s.emu = std::exp(mu[r]);
+        s.emu_inv = std::exp(-mu[r]);
+        s.min_margin = 1e300;
+        hs[r] = s;
+    }
+    HIPCHK(hipMemcpyAsync(st, hs.data(), sizeof(TslState) * nrhs, hipMemcpyHostToDevice, h->stream));
+    TslCoeffs co{coef, coef + (size_t)nrhs * k, coef + (size_t)2 * nrhs * k, coef + (size_t)3 * nrhs * k, k};
+
+    // rotating buffers: V-hat x3, U-hat x2, W-hat x3, Z-hat x2
+    auto slot = [&](int base, int i) { return ring + (size_t)(base + i) * nrhs * fsz; };
+    auto Vs = [&](int i) -> cpx<T>* { return basis ? basis + (size_t)(i - 1) * fsz : slot(0, i % 3); };
+    auto Us = [&](int i) -> cpx<T>* { return slot(3, i % 2); };
+    auto Ws = [&](int i) -> cpx<T>* { return slot(5, i % 3); };
+    auto Zs = [&](int i) -> cpx<T>* { return slot(8, i % 2); };
+    const long long sV = basis ? (long long)k * fsz : fsz;
+
+    Timer tl, ts;
+    tl.start(h->stream);
+    const double md = h->m0 + 4.0 * h->r;
+    for (int j = 0; j < k; ++j) {
+        StepPtrs p{};
+        int nt;
+        if (j == 0) {
+            nt = 0;
+            p.Xv = p.Yv = p.Zv = src_v;
+            p.Xw = p.Yw = p.Zw = src_w;
+            p.sXv = p.sYv = p.sZv = fsz;
+            p.sXw = p.sYw = p.sZw = fsz;
+        } else {
+            nt = (j == 1) ? 2 : 3;
+            p.Xv = Us(j); p.sXv = fsz;
+            p.Yv = Vs(j); p.sYv = sV;
+            p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
+            p.Xw = Zs(j); p.sXw = fsz;
+            p.Yw = Ws(j); p.sYw = fsz;
+            p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = fsz;
+        }
+        p.outV = Vs(j + 1); p.sV = sV;
+        p.outU = Us(j + 1); p.sU = fsz;
+        p.outW = Ws(j + 1); p.sW = fsz;
+        p.outZ = Zs(j + 1); p.sZ = fsz;
+        p.xproj = xproj;
+        p.sx = (long long)12 * g.Vp;
+        launch_tsl_step<T>(g, dir, nrhs, nt, p, U, dU, md, st, co, partials, counters, j,
+                           h->opt.breakdown_tol, h->stream);
+    }
+    HIPCHK(hipGetLastError());
+    tl.stop(h->stream);
+
+    // state check (synchronises)
+    HIPCHK(hipMemcpyAsync(hs.data(), st, sizeof(TslState) * nrhs, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double minm = 1e300;
+    int bstep = -1;
+    int bad = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        if (hs[r].min_margin < minm) minm = hs[r].min_margin;
+        if (hs[r].flag) {
+            bad = hs[r].flag;
+            bstep = hs[r].bstep;
+        }
+    }
+    h->last_nrhs = nrhs;
+    h->last_k = k;
+    h->last_co = co;
+    if (stats) {
+        stats->k = k;
+        stats->breakdown_step = bstep;
+        stats->min_margin = minm;
+        stats->ms_lanczos = tl.ms();
+    }
+    if (bad == 1) return fail(h, OVD_EBREAKDOWN, "two-sided Lanczos breakdown at step " + std::to_string(bstep));
+    if (bad == 2) return fail(h, OVD_ENAN, "non-finite value in the Lanczos recurrence at step " + std::to_string(bstep));
+
+    // sgn(T_k) e_1
+    const size_t ne = small_sign_scratch_elems(nrhs, k, h->opt.quad_step);
+    WS(scr, c64, "small_scratch", ne);
+    ts.start(h->stream);
+    double chk = 0.0;
+    launch_small_sign(nrhs, k, co, h->opt.quad_step, scr, ne, c_out, &chk, h->stream);
+    HIPCHK(hipGetLastError());
+    ts.stop(h->stream);
+    if (stats) {
+        stats->ms_small_sign = ts.ms();
+        stats->sign_check = chk;
+    }
+    return OVD_OK;
+}
+
+template <typename T>
+ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const void* b, void* y, ovd_stats* stats) {
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    const long long fsz = (long long)12 * g.Vp;
+    WS(src, cpx<T>, "src_v", (size_t)nrhs * fsz);
+    WS(basis, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
+    WS(c, c64, "ritz_c", (size_t)nrhs * k);
+    WS(cf, c64, "ritz_coef", (size_t)nrhs * k);
+    Timer tt;
+    tt.start(h->stream);
+    launch_pack_spinor<T>(g, nrhs, b, src, fsz, h->stream);
+    ovd_status s = run_tsl<T>(h, nrhs, k, 0, mu, src, src, nullptr, basis, c, stats);
+    if (s != OVD_OK) return s;
+    dim3 grid((k + 127) / 128, nrhs);
+    make_coef_kernel<<<grid, 128, 0, h->stream>>>(k, h->last_co, c, cf);
+    launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, y, h->stream);
+    HIPCHK(hipGetLastError());
+    tt.stop(h->stream);
+    if (stats) stats->ms_total = tt.ms();
+    return OVD_OK;
+}
+
+template <typename T>
+ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, const void* b, void* y, void* dy,
+                      const void* x, double* xdy, ovd_stats* stats) {
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    const long long half = (long long)12 * g.Vp;
+    const long long fsz = 2 * half;
+    const bool need_vec = (y != nullptr) || (dy != nullptr);
+    WS(srcv, cpx<T>, "src_v", (size_t)nrhs * fsz);
+    WS(srcw, cpx<T>, "src_w", (size_t)nrhs * fsz);
+    cpx<T>* xp = nullptr;
+    if (x) {
+        WS(xb, cpx<T>, "xproj", (size_t)nrhs * half);
+        xp = xb;
+    }
+    cpx<T>* basis = nullptr;
+    if (need_vec) {
+        WS(bb, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
+        basis = bb;
+    }
+    WS(c, c64, "ritz_c", (size_t)nrhs * k);
+    Timer tt;
+    tt.start(h->stream);
+    // psi = (0; b)
+    HIPCHK(hipMemsetAsync(srcv, 0, sizeof(cpx<T>) * nrhs * fsz, h->stream));
+    for (int r = 0; r < nrhs; ++r)
+        launch_pack_spinor<T>(g, 1, (const c64*)b + (size_t)r * g.V * 12, srcv + r * fsz + half, fsz, h->stream);
+    if (h->opt.left_start == OVD_LEFT_SAME) {
+        HIPCHK(hipMemcpyAsync(srcw, srcv, sizeof(cpx<T>) * nrhs * fsz, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        dim3 grid((g.V + 255) / 256, nrhs);
+        left_sum_kernel<T><<<grid, 256, 0, h->stream>>>(g, srcv, srcw, fsz);
+    }
+    if (xp) launch_pack_spinor<T>(g, nrhs, x, xp, half, h->stream);
+    HIPCHK(hipGetLastError());
+    ovd_status s = run_tsl<T>(h, nrhs, k, dirk, mu, srcv, srcw, xp, basis, c, stats);
+    if (s != OVD_OK) return s;
+    if (need_vec) {
+        WS(cf, c64, "ritz_coef", (size_t)nrhs * k);
+        dim3 grid((k + 127) / 128, nrhs);
+        make_coef_kernel<<<grid, 128, 0, h->stream>>>(k, h->last_co, c, cf);
+        if (dy) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, dy, h->stream);
+        if (y) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 1, cf, k, y, h->stream);
+    }
+    if (xdy) {
+        WS(outd, c64, "scalar_out", nrhs);
+        launch_scalar_dot(nrhs, k, c, h->last_co.proj, k, h->last_co.delta, outd, h->stream);
+        HIPCHK(hipMemcpyAsync(xdy, outd, sizeof(c64) * nrhs, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipGetLastError());
+    tt.stop(h->stream);
+    if (stats) stats->ms_total = tt.ms();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return OVD_OK;
+}
+
+ovd_status upload_dir(ovd_h h, const ovd_dir* dir, int* dirk) {
+    ovd_status wst = OVD_OK;
+    if (!dir || dir->kind == OVD_DIR_MU) {
+        *dirk = 1;
+        return OVD_OK;
+    }
+    if (dir->kind != OVD_DIR_LINK || !dir->dU) return fail(h, OVD_EINVAL, "bad derivative direction");
+    const size_t n = (size_t)4 * 9 * h->g.Vp;
+    WS(d64, c64, "dU64", n);
+    c32* d32 = nullptr;
+    if (h->opt.precision == OVD_MIXED) {
+        WS(t32, c32, "dU32", n);
+        d32 = t32;
+    }
+    launch_pack_links(h->g, dir->dU, d64, d32, h->stream);
+    HIPCHK(hipGetLastError());
+    h->dU64 = d64;
+    h->dU32 = d32;
+    *dirk = 2;
+    return OVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, const ovd_options* opt,
+                              void* stream, ovd_h* out) {
+    if (!dims || !out) return OVD_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 2) return OVD_EINVAL;
+    if (r != 1.0) return OVD_EINVAL;
+    if (t_bc != 1 && t_bc != -1) return OVD_EINVAL;
+    const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    if (V > (1LL << 28)) return OVD_EINVAL;
+    ovd_lattice* h = new ovd_lattice();
+    for (int i = 0; i < 4; ++i) h->g.L[i] = dims[i];
+    h->g.V = (int)V;
+    h->g.Vp = (int)((V + 63) / 64 * 64);
+    h->g.bc_t = t_bc;
+    h->m0 = m0;
+    h->r = r;
+    h->opt.precision = OVD_FP64;
+    h->opt.left_start = OVD_LEFT_SUM;
+    h->opt.breakdown_tol = 1e-14;
+    h->opt.quad_step = 0.1;
+    if (opt) {
+        h->opt = *opt;
+        if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
+        if (h->opt.quad_step <= 0) h->opt.quad_step = 0.1;
+        if (h->opt.precision != OVD_FP64 && h->opt.precision != OVD_MIXED) {
+            delete h;
+            return OVD_EINVAL;
+        }
+    }
+    h->stream = (hipStream_t)stream;
+    *out = h;
+    return OVD_OK;
+}
+
+ovd_status ovd_destroy(ovd_h h) {
+    if (!h) return OVD_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& kv : h->ws) (void)hipFree(kv.second.first);
+    if (h->U64) (void)hipFree(h->U64);
+    if (h->U32) (void)hipFree(h->U32);
+    for (auto& d : h->defl) {
+        (void)hipFree(d.R);
+        (void)hipFree(d.L);
+        if (d.dR) (void)hipFree(d.dR);
+        if (d.dL) (void)hipFree(d.dL);
+    }
+    delete h;
+    return OVD_OK;
+}
+
+const char* ovd_last_error(ovd_h h) { return h ? h->err.c_str() : "null handle"; }
+
+ovd_status ovd_set_stream(ovd_h h, void* stream) {
+    if (!h) return OVD_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return OVD_OK;
+}
+
+ovd_status ovd_set_links(ovd_h h, const void* U) {
+    if (!h) return OVD_EINVAL;
+    if (!U) return fail(h, OVD_EINVAL, "null link pointer");
+    const size_t n = (size_t)4 * 9 * h->g.Vp;
+    if (!h->U64) HIPCHK(hipMalloc(&h->U64, n * sizeof(c64)));
+    if (h->opt.precision == OVD_MIXED && !h->U32) HIPCHK(hipMalloc(&h->U32, n * sizeof(c32)));
+    launch_pack_links(h->g, U, h->U64, h->U32, h->stream);
+    HIPCHK(hipGetLastError());
+    h->links_set = true;
+    return OVD_OK;
+}
+
+ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs, const void* in, void* out,
+                        double* ms) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (!in || !out || nrhs < 1 || op < 0 || op > 3) return fail(h, OVD_EINVAL, "bad ovd_apply_op arguments");
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    if (op == OVD_OP_DH_DLINK) {
+        if (!dir || dir->kind != OVD_DIR_LINK) return fail(h, OVD_EINVAL, "OVD_OP_DH_DLINK needs a link direction");
+        int dk;
+        s = upload_dir(h, dir, &dk);
+        if (s != OVD_OK) return s;
+    }
+    const long long fsz = (long long)12 * g.Vp;
+    WS(emu, double, "emu", 2 * nrhs);
+    std::vector<double> he(2 * nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        he[2 * r] = std::exp(mu);
+        he[2 * r + 1] = std::exp(-mu);
+    }
+    HIPCHK(hipMemcpyAsync(emu, he.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, h->stream));
+    Timer t;
+    if (h->opt.precision == OVD_MIXED) {
+        WS(a, c32, "op_in", (size_t)nrhs * fsz);
+        WS(b, c32, "op_out", (size_t)nrhs * fsz);
+        launch_pack_spinor<float>(g, nrhs, in, a, fsz, h->stream);
+        t.start(h->stream);
+        launch_apply_op<float>(g, op, nrhs, emu, h->U32, h->dU32, h->m0 + 4 * h->r, a, b, h->stream);
+        t.stop(h->stream);
+        launch_unpack_spinor<float>(g, nrhs, b, fsz, out, h->stream);
+    } else {
+        WS(a, c64, "op_in", (size_t)nrhs * fsz);
+        WS(b, c64, "op_out", (size_t)nrhs * fsz);
+        launch_pack_spinor<double>(g, nrhs, in, a, fsz, h->stream);
+        t.start(h->stream);
+        launch_apply_op<double>(g, op, nrhs, emu, h->U64, h->dU64, h->m0 + 4 * h->r, a, b, h->stream);
+        t.stop(h->stream);
+        launch_unpack_spinor<double>(g, nrhs, b, fsz, out, h->stream);
+    }
+    HIPCHK(hipGetLastError());
+    if (ms) *ms = t.ms();
+    return OVD_OK;
+}
+
+ovd_status ovd_sign_apply(ovd_h h, int nrhs, const double* mu, int k, const void* b, void* y, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !b || !y) return fail(h, OVD_EINVAL, "bad ovd_sign_apply arguments");
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (h->opt.precision == OVD_MIXED) return sign_apply_impl<float>(h, nrhs, mu, k, b, y, st);
+    return sign_apply_impl<double>(h, nrhs, mu, k, b, y, st);
+}
+
+ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* b,
+                                void* y, void* dy, const void* x, double* xdy, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !b) return fail(h, OVD_EINVAL, "bad ovd_sign_apply_deriv arguments");
+    if (!y && !dy && !(x && xdy)) return fail(h, OVD_EINVAL, "no output requested");
+    if (xdy && !x) return fail(h, OVD_EINVAL, "xdy requested without x");
+    if (st) std::memset(st, 0, sizeof(*st));
+    int dirk = 1;
+    s = upload_dir(h, dir, &dirk);
+    if (s != OVD_OK) return s;
+    if (h->opt.precision == OVD_MIXED) return deriv_impl<float>(h, nrhs, mu, dirk, k, b, y, dy, x, xdy, st);
+    return deriv_impl<double>(h, nrhs, mu, dirk, k, b, y, dy, x, xdy, st);
+}
+
+ovd_status ovd_get_tridiag(ovd_h h, int rhs, int k, double* alpha, double* beta, double* delta) {
+    if (!h) return OVD_EINVAL;
+    if (rhs < 0 || rhs >= h->last_nrhs || k < 1 || k > h->last_k)
+        return fail(h, OVD_EINVAL, "no such Lanczos run / rhs / k");
+    const TslCoeffs& co = h->last_co;
+    const size_t off = (size_t)rhs * co.kmax;
+    if (alpha) HIPCHK(hipMemcpy(alpha, co.alpha + off, sizeof(c64) * k, hipMemcpyDeviceToHost));
+    if (beta) HIPCHK(hipMemcpy(beta, co.beta + off, sizeof(c64) * k, hipMemcpyDeviceToHost));
+    if (delta) HIPCHK(hipMemcpy(delta, co.delta + off, sizeof(c64) * k, hipMemcpyDeviceToHost));
+    return OVD_OK;
+}
+
+ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const void* R, const void* L, int l,
+                             const void* dR, const void* dL, const ovd_dir* dir) {
+    (void)mu; (void)m; (void)lam; (void)R; (void)L; (void)l; (void)dR; (void)dL; (void)dir;
+    return fail(h, OVD_EINVAL, "deflation is not available in this build");
+}
+
+ovd_status ovd_clear_deflation(ovd_h h) {
+    if (!h) return OVD_EINVAL;
+    return OVD_OK;
+}
+
+ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b, double* s, double* ds_dmu,
+                              void* F, ovd_stats* st) {
+    (void)mu; (void)k; (void)x; (void)b; (void)s; (void)ds_dmu; (void)F; (void)st;
+    return fail(h, OVD_EINVAL, "vjp is not available in this build");
+}
+
+}  // extern "C"

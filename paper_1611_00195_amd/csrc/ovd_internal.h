@@ -1,0 +1,143 @@
+// Internal declarations of libovderiv: device complex arithmetic, the
+// lattice geometry passed to kernels, and the host-side launchers that the
+// C ABI in api.hip calls.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace ovd {
+
+// ---------------------------------------------------------------------------
+// complex numbers (interleaved re, im; 16-byte aligned in FP64, 8 in FP32)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <typename T> __host__ __device__ inline cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
+template <typename T> __host__ __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __host__ __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __host__ __device__ inline cpx<T> operator-(cpx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __host__ __device__ inline cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __host__ __device__ inline cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __host__ __device__ inline cpx<T>& operator+=(cpx<T>& a, cpx<T> b) { a.re += b.re; a.im += b.im; return a; }
+template <typename T> __host__ __device__ inline cpx<T>& operator-=(cpx<T>& a, cpx<T> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <typename T> __host__ __device__ inline cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+template <typename T> __host__ __device__ inline T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+// conj(a) * b
+template <typename T> __host__ __device__ inline cpx<T> cdot(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// a / b, scaled to avoid overflow (Smith's algorithm)
+template <typename T> __host__ __device__ inline cpx<T> cdiv(cpx<T> a, cpx<T> b) {
+    T ar = b.re < 0 ? -b.re : b.re, ai = b.im < 0 ? -b.im : b.im;
+    if (ar >= ai) {
+        T r = b.im / b.re, d = b.re + b.im * r;
+        return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    } else {
+        T r = b.re / b.im, d = b.re * r + b.im;
+        return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+    }
+}
+template <typename T> __host__ __device__ inline T cabs1(cpx<T> a) {
+    return (a.re < 0 ? -a.re : a.re) + (a.im < 0 ? -a.im : a.im);
+}
+template <typename D, typename S> __host__ __device__ inline cpx<D> cast(cpx<S> a) {
+    return {static_cast<D>(a.re), static_cast<D>(a.im)};
+}
+
+using c64 = cpx<double>;
+using c32 = cpx<float>;
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct Geom {
+    int L[4];     // Lx, Ly, Lz, Lt
+    int V;        // sites
+    int Vp;       // padded site stride of the internal field layout (multiple of 64)
+    int bc_t;     // +1 periodic, -1 antiperiodic time boundary
+};
+
+// Internal field layout ("SoA"): a spinor field is [12][Vp] complex, a block
+// vector (top, bottom) is [2][12][Vp], links are [4][9][Vp].  Right-hand sides
+// are stacked with an explicit stride.
+
+// Per-right-hand-side scalar state of the Lanczos recurrence, FP64.
+struct TslState {
+    c64 av, bv, cv;       // next vhat = av*X + bv*Y + cv*Z   (v side)
+    c64 aw, bw, cw;       // next what = aw*X + bw*Y + cw*Z   (w side)
+    c64 beta_prev;        // beta_j of the last completed step
+    double delta_prev;    // delta_j
+    double min_margin;    // min |omega| / (|v||w|)
+    double emu, emu_inv;  // e^{mu}, e^{-mu}
+    int step;             // number of completed reductions
+    int flag;             // 0 ok, 1 breakdown, 2 non-finite
+    int bstep;            // step of the breakdown
+    int pad;
+};
+
+// Per-step coefficient arrays, [rhs][kmax] complex each.
+struct TslCoeffs {
+    c64* alpha;
+    c64* beta;
+    c64* delta;   // real, stored complex for uniformity
+    c64* proj;    // <x|v_j> (normalised v_j); only for the scalar mode
+    int kmax;
+};
+
+// Kernel arguments of one fused Lanczos step.
+struct StepPtrs {
+    const void* Xv; const void* Yv; const void* Zv;   // v side inputs
+    const void* Xw; const void* Yw; const void* Zw;   // w side inputs
+    void* outV; void* outU;                          // vhat, A vhat
+    void* outW; void* outZ;                          // what, A^dag what
+    const void* xproj;                               // projection vector or null
+    long long sXv, sYv, sZv, sXw, sYw, sZw, sV, sU, sW, sZ, sx;   // rhs strides (elements)
+};
+
+// ---------------------------------------------------------------------------
+// launchers (kernels_*.hip)
+// ---------------------------------------------------------------------------
+// links: AoS complex128 [4][V][3][3] -> SoA [4][9][Vp] (double and/or float)
+void launch_pack_links(const Geom& g, const void* U_aos, c64* U64, c32* U32, hipStream_t s);
+// spinors: AoS complex128 [n][V][12] <-> SoA [n][12][Vp] (stride per rhs)
+template <typename T>
+void launch_pack_spinor(const Geom& g, int n, const void* in_aos, cpx<T>* out, long long stride, hipStream_t s);
+template <typename T>
+void launch_unpack_spinor(const Geom& g, int n, const cpx<T>* in, long long stride, void* out_aos, hipStream_t s);
+
+// standalone operator: out = op(in) on SoA fields, per-rhs mu
+template <typename T>
+void launch_apply_op(const Geom& g, int op, int nrhs, const double* d_emu, const cpx<T>* U,
+                     const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s);
+
+// fused Lanczos step.  dir: 0 plain H, 1 block with d/dmu, 2 block with d/dlink.
+// nterms: 0 (raw X), 1 (a X), 2 (a X + b Y), 3 (a X + b Y + c Z).
+template <typename T>
+void launch_tsl_step(const Geom& g, int dir, int nrhs, int nterms, const StepPtrs& p,
+                     const cpx<T>* U, const cpx<T>* dU, double m_diag, TslState* st,
+                     TslCoeffs co, double* partials, unsigned* counters, int j, double tau,
+                     hipStream_t s);
+
+// sgn(T_k) e_1 for nrhs tridiagonal matrices by the resolvent quadrature.
+void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scratch,
+                       size_t scratch_elems, c64* c_out, double* check, hipStream_t s);
+size_t small_sign_scratch_elems(int nrhs, int k, double quad_step);
+
+// y = sum_j coef[rhs][j] * basis[rhs][j]  (top/bottom halves selected by half_off)
+template <typename T>
+void launch_reconstruct(const Geom& g, int nrhs, int k, const cpx<T>* basis, long long s_rhs,
+                        long long s_j, int half, const c64* coef, int coef_ld, void* out_aos,
+                        hipStream_t s);
+
+// scalar result: out[rhs] = scale[rhs] * sum_j c[rhs][j] * proj[rhs][j]
+void launch_scalar_dot(int nrhs, int k, const c64* c, const c64* proj, int ld,
+                       const c64* scale, c64* out, hipStream_t s);
+
+}  // namespace ovd

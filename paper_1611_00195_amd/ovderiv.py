@@ -1,0 +1,251 @@
+"""Python binding of libovderiv (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor shapes,
+dtypes and devices, passes device pointers and the current torch stream, and
+turns status codes into exceptions.  PyTorch provides device memory and
+streams only.  If the library has not been built the import fails loudly:
+there is no CPU fallback.
+
+Names follow the C ABI (include/ovderiv.h): ``create_lattice``, ``set_links``,
+``set_deflation``, ``sign_apply``, ``sign_apply_deriv``, ``sign_apply_vjp``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libovderiv.so")
+
+OVD_OK, OVD_EINVAL, OVD_ENOMEM, OVD_EHIP, OVD_EBREAKDOWN, OVD_ENODEFL, OVD_ENAN = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+LEFT_SUM, LEFT_SAME = 0, 1
+DIR_MU, DIR_LINK = 0, 1
+OP_H, OP_DW, OP_DH_DMU, OP_DH_DLINK = 0, 1, 2, 3
+
+EXPORTS = [
+    "ovd_create_lattice", "ovd_destroy", "ovd_last_error", "ovd_set_stream", "ovd_set_links",
+    "ovd_apply_op", "ovd_set_deflation", "ovd_clear_deflation", "ovd_sign_apply",
+    "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag",
+]
+
+
+class OvdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libovderiv status {status}: {msg}")
+        self.status = status
+
+
+class Breakdown(OvdError):
+    pass
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("left_start", ctypes.c_int),
+                ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double)]
+
+
+class _Dir(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dU", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("breakdown_step", ctypes.c_int), ("min_margin", ctypes.c_double),
+                ("sign_check", ctypes.c_double), ("ms_lanczos", ctypes.c_double),
+                ("ms_small_sign", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+@dataclass
+class Stats:
+    k: int
+    breakdown_step: int
+    min_margin: float
+    sign_check: float
+    ms_lanczos: float
+    ms_small_sign: float
+    ms_total: float
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libovderiv is not built ({path} missing); run python -m paper_1611_00195_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "ovd_create_lattice": (i, [ctypes.POINTER(ctypes.c_int), d, d, i, ctypes.POINTER(_Options), vp, ctypes.POINTER(vp)]),
+        "ovd_destroy": (i, [vp]),
+        "ovd_last_error": (ctypes.c_char_p, [vp]),
+        "ovd_set_stream": (i, [vp, vp]),
+        "ovd_set_links": (i, [vp, vp]),
+        "ovd_apply_op": (i, [vp, i, d, ctypes.POINTER(_Dir), i, vp, vp, dp]),
+        "ovd_set_deflation": (i, [vp, d, i, dp, vp, vp, i, vp, vp, ctypes.POINTER(_Dir)]),
+        "ovd_clear_deflation": (i, [vp]),
+        "ovd_sign_apply": (i, [vp, i, dp, i, vp, vp, ctypes.POINTER(_Stats)]),
+        "ovd_sign_apply_deriv": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, vp, dp, ctypes.POINTER(_Stats)]),
+        "ovd_sign_apply_vjp": (i, [vp, d, i, vp, vp, dp, dp, vp, ctypes.POINTER(_Stats)]),
+        "ovd_get_tridiag": (i, [vp, i, i, dp, dp, dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_field(t, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _dbl(arr):
+    a = (ctypes.c_double * len(arr))(*arr)
+    return a
+
+
+class Lattice:
+    """One lattice handle (``ovd_create_lattice``); links, deflation data and
+    workspaces live on the current device."""
+
+    def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
+                 breakdown_tol=1e-14, quad_step=0.1, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = 1
+        for d in self.dims:
+            self.V *= d
+        self.precision = precision
+        self._lib = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        opt = _Options(precision, left_start, breakdown_tol, quad_step)
+        h = ctypes.c_void_p()
+        dims_c = (ctypes.c_int * 4)(*self.dims)
+        st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
+                                          ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != OVD_OK:
+            raise OvdError(st, "ovd_create_lattice failed (check dims >= 2, r == 1, t_bc = +-1)")
+        self._h = h
+
+    # -- helpers --
+    def _raise(self, st):
+        msg = self._lib.ovd_last_error(self._h).decode()
+        if st == OVD_EBREAKDOWN:
+            raise Breakdown(st, msg)
+        raise OvdError(st, msg)
+
+    def _call(self, name, *args):
+        st = getattr(self._lib, name)(self._h, *args)
+        if st != OVD_OK:
+            self._raise(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ovd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stats(s):
+        return Stats(s.k, s.breakdown_step, s.min_margin, s.sign_check, s.ms_lanczos, s.ms_small_sign, s.ms_total)
+
+    def _dir(self, direction, dU):
+        if direction in (None, "mu", DIR_MU):
+            return _Dir(DIR_MU, None), None
+        if dU is None:
+            raise ValueError("link direction needs dU")
+        _check_field(dU, (4, self.V, 3, 3), "dU")
+        return _Dir(DIR_LINK, ctypes.c_void_p(dU.data_ptr())), dU
+
+    # -- API --
+    def set_links(self, U):
+        _check_field(U, (4, self.V, 3, 3), "U")
+        self._call("ovd_set_links", _ptr(U))
+        self._U = U
+
+    def apply_op(self, op, mu, inp, dU=None):
+        """op in {OP_H, OP_DW, OP_DH_DMU, OP_DH_DLINK}; inp [n, V, 4, 3] complex128."""
+        n = inp.shape[0]
+        _check_field(inp, (n, self.V, 4, 3), "input")
+        out = torch.empty_like(inp)
+        d, keep = self._dir("link" if op == OP_DH_DLINK else None, dU)
+        ms = ctypes.c_double(0.0)
+        self._call("ovd_apply_op", op, float(mu), ctypes.byref(d), n, _ptr(inp), _ptr(out), ctypes.byref(ms))
+        self.last_ms = ms.value
+        return out
+
+    def sign_apply(self, b, mu, k):
+        """sgn(H(mu)) b by k steps of two-sided Lanczos; b [n, V, 4, 3]; mu scalar or list of n."""
+        n = b.shape[0]
+        _check_field(b, (n, self.V, 4, 3), "b")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        y = torch.empty_like(b)
+        st = _Stats()
+        self._call("ovd_sign_apply", n, _dbl(mus), int(k), _ptr(b), _ptr(y), ctypes.byref(st))
+        self.last_stats = self._stats(st)
+        return y
+
+    def sign_apply_deriv(self, b, mu, k, direction="mu", dU=None, want_vectors=True, x=None):
+        """Derivative of sgn(H(mu)) b along mu or a link tangent dU (eq. 6-7).
+
+        Returns (y, dy, xdy): y = sgn(H) b and dy = d/dt sgn(H) b when
+        want_vectors, xdy = <x|dy> (one complex per source) when x is given;
+        without want_vectors the Krylov basis is never stored."""
+        n = b.shape[0]
+        _check_field(b, (n, self.V, 4, 3), "b")
+        if x is not None:
+            _check_field(x, (n, self.V, 4, 3), "x")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        d, keep = self._dir(direction, dU)
+        y = torch.empty_like(b) if want_vectors else None
+        dy = torch.empty_like(b) if want_vectors else None
+        xdy = (ctypes.c_double * (2 * n))() if x is not None else None
+        st = _Stats()
+        self._call("ovd_sign_apply_deriv", n, _dbl(mus), ctypes.byref(d), int(k), _ptr(b), _ptr(y), _ptr(dy),
+                   _ptr(x), xdy, ctypes.byref(st))
+        self.last_stats = self._stats(st)
+        s = None
+        if xdy is not None:
+            s = [complex(xdy[2 * i], xdy[2 * i + 1]) for i in range(n)]
+        return y, dy, s
+
+    def get_tridiag(self, k, rhs=0):
+        """(alpha, beta, delta) of the last Lanczos run as lists of complex."""
+        a = (ctypes.c_double * (2 * k))()
+        b = (ctypes.c_double * (2 * k))()
+        d = (ctypes.c_double * (2 * k))()
+        self._call("ovd_get_tridiag", int(rhs), int(k), a, b, d)
+        cv = lambda arr: [complex(arr[2 * i], arr[2 * i + 1]) for i in range(k)]
+        return cv(a), cv(b), cv(d)
+
+
+def create_lattice(dims, **kw) -> Lattice:
+    return Lattice(dims, **kw)

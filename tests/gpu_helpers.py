@@ -1,0 +1,37 @@
+"""Shared helpers of the GPU parity tests (inputs from synth, references from oracle)."""
+import numpy as np
+import torch
+
+import synth
+from oracle import dirac
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def ops(U, dims, mu, dU=None):
+    """Oracle operators on flat vectors: H, H^dag, dH, dH^dag (mu or link direction)."""
+    h = lambda v: dirac.flat(dirac.apply_h(U, v, dims, mu))
+    hd = lambda v: dirac.flat(dirac.apply_hdag(U, v, dims, mu))
+    if dU is None:
+        dh = lambda v: dirac.flat(dirac.apply_dh_dmu(U, v, dims, mu))
+        dhd = lambda v: -dirac.flat(dirac.apply_dh_dmu(U, v, dims, -mu))
+    else:
+        dh = lambda v: dirac.flat(dirac.apply_dh_dlink(dU, v, dims, mu))
+        dhd = lambda v: dirac.flat(dirac.apply_dh_dlink(dU, v, dims, -mu))
+    return h, hd, dh, dhd
+
+
+def print_case(**kw):
+    print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)

@@ -1,0 +1,198 @@
+"""GPU parity of the two-sided Lanczos pipeline against the oracle (through the C ABI).
+
+Tolerances: FP64 results 1e-10 relative (the Lanczos recurrence amplifies
+rounding differences; both sides run the same algorithm with a different
+summation order and a different, equally accurate evaluation of sgn(T_k) e_1);
+mixed precision (FP32 vectors and stencil, FP64 scalars) is checked against a
+per-result bound measured here and stated in the assertion.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, matfun, tsl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _setup(dims, eps, seed, prec=0, **kw):
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev
+    U = synth.make_links(dims, eps, seed)
+    lat = ovderiv.Lattice(dims, precision=prec, **kw)
+    lat.set_links(dev(U))
+    return U, lat
+
+
+@pytest.mark.parametrize("dims,k", [((4, 4, 4, 4), 64), ((5, 3, 4, 6), 48)])
+def test_sign_apply_parity(dims, k):
+    from gpu_helpers import dev, host, ops, print_case, rel
+    print_case(test="sign_apply", dims=dims, k=k)
+    mu = 0.3
+    U, lat = _setup(dims, 0.5, 201)
+    b = synth.make_sources(dims, 2, 202)
+    y = host(lat.sign_apply(dev(b), mu, k))
+    h, hd, _, _ = ops(U, dims, mu)
+    for r in range(2):
+        ref, L = tsl.krylov_sign(h, hd, b[r].ravel(), b[r].ravel(), k)
+        assert rel(y[r], ref) < 1e-10
+    # Lanczos coefficients of the last right-hand side, step by step
+    a, be, de = lat.get_tridiag(k, rhs=1)
+    assert np.abs(np.array(a) - L["alpha"]).max() < 1e-10
+    assert np.abs(np.array(be[1:]) - L["beta"][1:k]).max() < 1e-10
+    assert np.abs(np.array(de[1:]) - L["delta"][1:k]).max() < 1e-10
+    assert abs(de[0] - np.linalg.norm(b[1])) < 1e-13
+
+
+def test_sign_apply_batched_mu():
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k = (4, 4, 4, 6), 40
+    print_case(test="sign_apply_batched", dims=dims, k=k)
+    mus = [0.0, 0.2, 0.4]
+    U, lat = _setup(dims, 0.5, 203)
+    b = synth.make_sources(dims, 3, 204)
+    y = host(lat.sign_apply(dev(b), mus, k))
+    for r, mu in enumerate(mus):
+        h, hd, _, _ = ops(U, dims, mu)
+        ref, _ = tsl.krylov_sign(h, hd, b[r].ravel(), b[r].ravel(), k)
+        assert rel(y[r], ref) < 1e-10
+
+
+@pytest.mark.parametrize("dims,k", [((4, 4, 4, 4), 64), ((3, 5, 2, 7), 50)])
+def test_deriv_mu_parity(dims, k):
+    from gpu_helpers import dev, host, ops, print_case, rel
+    print_case(test="deriv_mu", dims=dims, k=k)
+    mu = 0.3
+    U, lat = _setup(dims, 0.5, 205)
+    b = synth.make_sources(dims, 1, 206)
+    x = synth.make_sources(dims, 1, 207)
+    y, dy, s = lat.sign_apply_deriv(dev(b), mu, k, x=dev(x))
+    h, hd, dh, dhd = ops(U, dims, mu)
+    dref, yref, L = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[0].ravel(), k)
+    assert rel(host(dy)[0], dref) < 1e-10
+    assert rel(host(y)[0], yref) < 1e-10
+    assert abs(s[0] - np.vdot(x[0].ravel(), dref)) < 1e-10 * np.linalg.norm(dref)
+    a, be, de = lat.get_tridiag(k)
+    assert np.abs(np.array(a) - L["alpha"]).max() < 1e-10
+
+
+def test_deriv_scalar_storage_free():
+    """Storage-free scalar mode equals <x|dy> of the vector mode."""
+    from gpu_helpers import dev, host, ops, print_case
+    dims, k = (4, 4, 4, 6), 60
+    print_case(test="deriv_scalar", dims=dims, k=k)
+    U, lat = _setup(dims, 0.5, 208)
+    b = synth.make_sources(dims, 2, 209)
+    x = synth.make_sources(dims, 2, 210)
+    _, _, s = lat.sign_apply_deriv(dev(b), [0.1, 0.3], k, x=dev(x), want_vectors=False)
+    h0 = ops(U, dims, 0.1)
+    h1 = ops(U, dims, 0.3)
+    for r, o in enumerate((h0, h1)):
+        val, _ = tsl.krylov_sign_scalar(*tsl.block_ops(*o, b[r].size),
+                                        np.concatenate([np.zeros(b[r].size), b[r].ravel()]),
+                                        np.concatenate([b[r].ravel(), b[r].ravel()]), k,
+                                        np.concatenate([x[r].ravel(), np.zeros(b[r].size)]))
+        assert abs(s[r] - val) < 1e-10 * max(1.0, abs(val))
+
+
+def test_deriv_link_parity():
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k = (4, 4, 4, 4), 48
+    print_case(test="deriv_link", dims=dims, k=k)
+    mu = 0.2
+    U, lat = _setup(dims, 0.5, 211)
+    X = synth.make_su3_direction(dims, 212)
+    dU = dirac.link_tangent(X, U)
+    b = synth.make_sources(dims, 1, 213)
+    y, dy, _ = lat.sign_apply_deriv(dev(b), mu, k, direction="link", dU=dev(dU))
+    h, hd, dh, dhd = ops(U, dims, mu, dU)
+    dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[0].ravel(), k)
+    assert rel(host(dy)[0], dref) < 1e-10
+    assert rel(host(y)[0], yref) < 1e-10
+
+
+def test_mixed_precision_bounds():
+    """Mixed precision against the FP64 oracle: bounds measured and stated here."""
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k = (4, 4, 4, 4), 64
+    print_case(test="mixed", dims=dims, k=k)
+    mu = 0.3
+    U, lat = _setup(dims, 0.5, 214, prec=1)
+    b = synth.make_sources(dims, 1, 215)
+    y = host(lat.sign_apply(dev(b), mu, k))
+    h, hd, dh, dhd = ops(U, dims, mu)
+    ref, _ = tsl.krylov_sign(h, hd, b[0].ravel(), b[0].ravel(), k)
+    e1 = rel(y[0], ref)
+    y2, dy2, _ = lat.sign_apply_deriv(dev(b), mu, k)
+    dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[0].ravel(), k)
+    e2 = rel(host(dy2)[0], dref)
+    print(f"mixed precision errors: sign {e1:.2e}  derivative {e2:.2e}")
+    assert e1 < 1e-4
+    assert e2 < 1e-3
+
+
+def test_small_k_edge_cases():
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims = (2, 2, 2, 2)
+    print_case(test="small_k", dims=dims)
+    U, lat = _setup(dims, 0.5, 216)
+    b = synth.make_sources(dims, 1, 217)
+    h, hd, dh, dhd = ops(U, dims, 0.3)
+    for k in (1, 2, 3):
+        y = host(lat.sign_apply(dev(b), 0.3, k))
+        ref, _ = tsl.krylov_sign(h, hd, b[0].ravel(), b[0].ravel(), k)
+        assert rel(y[0], ref) < 1e-10
+
+
+def test_zero_source_is_an_error():
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, print_case
+    dims = (4, 4, 4, 4)
+    print_case(test="zero_source", dims=dims)
+    U, lat = _setup(dims, 0.5, 218)
+    b = np.zeros((1, 256, 4, 3), dtype=np.complex128)
+    with pytest.raises(ovderiv.OvdError):
+        lat.sign_apply(dev(b), 0.3, 8)
+
+
+def test_left_same_breaks_down_or_diverges():
+    """Left start psi for the block system: an error or a useless derivative, never a hang."""
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k = (4, 2, 2, 2), 160
+    print_case(test="left_same", dims=dims, k=k)
+    U, lat = _setup(dims, 0.5, 21, left_start=ovderiv.LEFT_SAME)
+    b = synth.make_sources(dims, 1, 22)
+    try:
+        _, dy, _ = lat.sign_apply_deriv(dev(b), 0.3, k)
+    except ovderiv.OvdError:
+        return
+    H = dirac.dense_h(U, dims, 0.3)
+    dH = dirac.dense_dh_dmu(U, dims, 0.3)
+    dref = matfun.frechet_sign_block(H, dH) @ b[0].ravel()
+    assert rel(host(dy)[0], dref) > 1e-3
+
+
+def test_free_field_converges_at_headline_size():
+    """14^4, gauge-rotated unit links (random-looking, exact answer known): the
+    Krylov-Ritz result at k = 400 approaches the exact sgn(H) b."""
+    from gpu_helpers import dev, host, print_case, rel
+    from oracle import freefield
+    dims, k = (14, 14, 14, 14), 400
+    print_case(test="free_field_14", dims=dims, k=k)
+    from paper_1611_00195_amd import ovderiv
+    U, g = synth.gauge_rotated_unit_links(dims, 219)
+    lat = ovderiv.Lattice(dims)
+    lat.set_links(dev(U))
+    b = synth.make_sources(dims, 1, 220)
+    y, dy, _ = lat.sign_apply_deriv(dev(b), 0.3, k)
+    gb = np.einsum("vba,vsb->vsa", np.conj(g), b[0])
+    ey, edy = freefield.sign_apply(gb.ravel(), dims, 0.3, deriv=True)
+    ey = np.einsum("vab,vsb->vsa", g, ey.reshape(-1, 4, 3))
+    edy = np.einsum("vab,vsb->vsa", g, edy.reshape(-1, 4, 3))
+    e_f = rel(host(y)[0], ey)
+    e_d = rel(host(dy)[0], edy)
+    print(f"free field 14^4 k={k}: sign error {e_f:.2e}, derivative error {e_d:.2e}")
+    assert e_f < 1e-6
+    assert e_d < 1e-4
