@@ -25,23 +25,82 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "d⟨x|sgn(H(μ))|b⟩/dμ evals/s at 14^4,k=400; Dw·v HBM GB/s vs peak"
 
 
-def step_bytes_per_site(prec_bytes: int, nrhs: int) -> float:
-    """Algorithmic HBM bytes per lattice site per fused Lanczos step (block system).
+def stencil_bytes_per_site(prec_bytes: int, nrhs: int) -> float:
+    """Algorithmic HBM bytes per lattice site per stencil launch (block system).
 
-    Per right-hand side: 3 inputs x 2 sides x 2 halves x 12 complex read (the
-    Lanczos update a X + b Y + c Z), 2 outputs x 2 sides x 2 halves x 12 complex
-    written, the projection vector x (12 complex) read; the 4 x 9 complex links
-    once per site per launch.  Complex = 2 * prec_bytes.
+    Per right-hand side: vhat and what (2 halves each, 12 complex per half)
+    read, A vhat and A^dag what written, the projection vector x (12 complex)
+    read; the 4 x 9 complex links once per site per launch.  Complex =
+    2 * prec_bytes.
     """
     c = 2 * prec_bytes
-    per_rhs = (3 * 2 * 2 * 12 + 2 * 2 * 2 * 12 + 12) * c
-    links = 4 * 9 * c
-    return per_rhs + links / nrhs
+    per_rhs = (2 * 2 * 12 + 2 * 2 * 12 + 12) * c
+    return per_rhs + 4 * 9 * c / nrhs
+
+
+def update_bytes_per_site(prec_bytes: int) -> float:
+    """Three-term update, per site and right-hand side: 3 inputs read and 1
+    output written on both sides, 2 halves of 12 complex each."""
+    return 2 * (3 + 1) * 2 * 12 * 2 * prec_bytes
+
+
+def measured_traffic(pb: int, nrhs: int):
+    """HBM bytes per stencil launch from the committed rocprofv3 counter
+    summary, if it was taken on the current stencil source and this workload;
+    else None."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1611_00195_amd", "csrc", "kernels_stencil.hip")
+    path = os.path.join(ROOT, "profiles", "tsl_stencil_14x14cubed_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            a, b = line.split(":", 1)
+            kv[a.strip()] = b.strip()
+    key = f"bytes_per_launch_{'fp64' if pb == 8 else 'fp32'}_nrhs{nrhs}"
+    if kv.get("kernels_stencil_sha256_16") != digest or key not in kv:
+        return None
+    return float(kv[key])
 
 
 def dwv_bytes_per_site(prec_bytes: int) -> float:
     """Dw.v: read 12 complex + 4 x 9 link complex, write 12 complex per site."""
     return (12 + 36 + 12) * 2 * prec_bytes
+
+
+def time_form(args, U, prec, n, steps, warmup, V):
+    """Time `steps` batched derivative evaluations of n sources at one precision."""
+    import torch
+
+    import synth
+    from paper_1611_00195_amd import ovderiv
+
+    dims = tuple(args.dims)
+    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+    lat.set_links(U)
+    b = torch.from_numpy(synth.make_sources(dims, n, 4000)).cuda()
+    x = torch.from_numpy(synth.make_sources(dims, n, 5000)).cuda()
+    mus = [args.mu] * n
+    for _ in range(warmup):
+        lat.sign_apply_deriv(b, mus, args.k, x=x, want_vectors=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = {"ms_lanczos": 0.0, "ms_small_sign": 0.0, "ms_stencil": 0.0, "ms_update": 0.0}
+    vals = None
+    for _ in range(steps):
+        _, _, vals = lat.sign_apply_deriv(b, mus, args.k, x=x, want_vectors=False)
+        st = lat.last_stats
+        for key in acc:
+            acc[key] += getattr(st, key)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = {key: v / steps for key, v in acc.items()}
+    res.update(evals_per_s=n * steps / dt, ms_per_step=1e3 * dt / steps, vals=vals,
+               min_margin=lat.last_stats.min_margin, sign_check=lat.last_stats.sign_check)
+    lat.close()
+    return res
 
 
 def run_gpu(args):
@@ -54,59 +113,62 @@ def run_gpu(args):
     dims = tuple(args.dims)
     V = int(np.prod(dims))
     torch.cuda.set_device(0)
-    U = synth.make_links(dims, args.eps, 1611)
+    Uh = synth.make_links(dims, args.eps, 1611)
+    U = torch.from_numpy(Uh).cuda()
     prec = ovderiv.MIXED if args.precision == "mixed" else ovderiv.FP64
-    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
-    lat.set_links(torch.from_numpy(U).cuda())
     n = args.nrhs
-    b = torch.from_numpy(synth.make_sources(dims, n, 4000)).cuda()
-    x = torch.from_numpy(synth.make_sources(dims, n, 5000)).cuda()
-    mus = [args.mu] * n
-    for _ in range(args.warmup):
-        lat.sign_apply_deriv(b, mus, args.k, x=x, want_vectors=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms_lanczos = 0.0
-    ms_sign = 0.0
-    vals = None
-    for _ in range(args.steps):
-        _, _, vals = lat.sign_apply_deriv(b, mus, args.k, x=x, want_vectors=False)
-        ms_lanczos += lat.last_stats.ms_lanczos
-        ms_sign += lat.last_stats.ms_small_sign
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    evals = n * args.steps / dt
+    main = time_form(args, U, prec, n, args.steps, args.warmup, V)
     pb = 4 if prec == ovderiv.MIXED else 8
-    per_launch_ms = ms_lanczos / (args.steps * args.k)
-    bytes_launch = step_bytes_per_site(pb, n) * V * n
-    achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    st_ms = main["ms_stencil"] / args.k                   # average stencil launch
+    up_ms = main["ms_update"] / (args.k - 1)              # average update launch
+    bytes_launch = stencil_bytes_per_site(pb, n) * V * n
+    achieved = bytes_launch / (st_ms * 1e-3) / 1e9
+    up_bytes = update_bytes_per_site(pb) * V * n
     out = {
-        "evals_per_s": evals,
-        "ms_per_step": 1e3 * dt / args.steps,
-        "ms_lanczos_per_step": ms_lanczos / args.steps,
-        "ms_small_sign_per_step": ms_sign / args.steps,
+        "evals_per_s": main["evals_per_s"],
+        "ms_per_step": main["ms_per_step"],
+        "ms_lanczos_per_step": main["ms_lanczos"],
+        "ms_small_sign_per_step": main["ms_small_sign"],
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "tsl_step_kernel",
+            "traffic": measured_traffic(pb, n),
+            "kernel": "tsl_stencil_kernel",
             "bytes_per_launch": bytes_launch,
-            "us_per_launch": round(per_launch_ms * 1e3, 2),
+            "us_per_launch": round(st_ms * 1e3, 2),
         },
-        "xdy0": [vals[0].real, vals[0].imag],
-        "min_margin": lat.last_stats.min_margin,
-        "sign_check": lat.last_stats.sign_check,
+        "update_kernel": {"bytes_per_launch": up_bytes, "us_per_launch": round(up_ms * 1e3, 2),
+                          "gbs": round(up_bytes / (up_ms * 1e-3) / 1e9, 1)},
+        "xdy0": [main["vals"][0].real, main["vals"][0].imag],
+        "min_margin": main["min_margin"],
+        "sign_check": main["sign_check"],
     }
+    # the other forms: single-source FP64 (the plain path), and the batched
+    # form in the other precision, with its error against FP64 on the same inputs
+    forms = {}
+    if not args.skip_forms:
+        other = ovderiv.FP64 if prec == ovderiv.MIXED else ovderiv.MIXED
+        single = time_form(args, U, ovderiv.FP64, 1, max(1, args.steps // 2), 1, V)
+        oth = time_form(args, U, other, n, max(1, args.steps // 2), 1, V)
+        ref = main["vals"] if prec == ovderiv.FP64 else oth["vals"]
+        mix = oth["vals"] if prec == ovderiv.FP64 else main["vals"]
+        err = max(abs(a - b) / abs(b) for a, b in zip(mix, ref))
+        forms = {
+            "fp64_single_evals_per_s": round(single["evals_per_s"], 3),
+            ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}_evals_per_s": round(oth["evals_per_s"], 3),
+            "mixed_vs_fp64_max_rel_err_xdy": err,
+        }
+    out["forms"] = forms
     # Dw.v bandwidth: nrhs fields per launch so that the traffic exceeds the 256 MB MALL
     nd = args.dwv_nrhs
     src = torch.from_numpy(synth.make_sources(dims, 1, 6000)).cuda().repeat(nd, 1, 1, 1).contiguous()
     dw = {}
     for pname, pv in (("fp64", ovderiv.FP64), ("fp32", ovderiv.MIXED)):
         l2 = ovderiv.Lattice(dims, m0=args.m0, precision=pv)
-        l2.set_links(torch.from_numpy(U).cuda())
+        l2.set_links(U)
         l2.apply_op(ovderiv.OP_DW, args.mu, src)
         ms = []
         for _ in range(5):
@@ -114,13 +176,33 @@ def run_gpu(args):
             ms.append(l2.last_ms)
         ms_med = sorted(ms)[len(ms) // 2]
         pbb = 8 if pv == ovderiv.FP64 else 4
-        byt = nd * V * (24 * 2 * pbb) + 36 * 2 * pbb * V
+        byt = nd * V * dwv_bytes_per_site(pbb) - (nd - 1) * V * 36 * 2 * pbb
         dw[pname] = {"gbs": round(byt / (ms_med * 1e-3) / 1e9, 1), "ms": round(ms_med, 4), "nrhs": nd,
                      "bytes": byt, "frac": round(byt / (ms_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         l2.close()
     out["dw_v"] = dw
-    lat.close()
     return out
+
+
+def counters_run(args):
+    """The workload of the committed counter summaries: the bench lattice and
+    sources, 8 right-hand sides, 20 Lanczos steps, FP64 then mixed."""
+    import torch
+
+    import synth
+    from paper_1611_00195_amd import ovderiv
+
+    dims = tuple(args.dims)
+    U = torch.from_numpy(synth.make_links(dims, args.eps, 1611)).cuda()
+    for prec in (ovderiv.FP64, ovderiv.MIXED):
+        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+        lat.set_links(U)
+        b = torch.from_numpy(synth.make_sources(dims, 8, 4000)).cuda()
+        x = torch.from_numpy(synth.make_sources(dims, 8, 5000)).cuda()
+        lat.sign_apply_deriv(b, [args.mu] * 8, 20, x=x, want_vectors=False)
+        lat.close()
+    torch.cuda.synchronize()
+    print("counters run done", flush=True)
 
 
 def run_cpu_baseline(args, nsteps):
@@ -182,11 +264,18 @@ def main():
     ap.add_argument("--dwv-nrhs", type=int, default=48)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-forms", action="store_true")
+    ap.add_argument("--counters-run", action="store_true",
+                    help="short fixed workload for rocprofv3 --pmc runs (8 sources, 20 Lanczos steps, "
+                         "FP64 then mixed); prints one line and no JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU form "
               "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.counters_run:
+        counters_run(args)
+        return
     g = run_gpu(args)
     cpu = None if args.no_cpu_baseline else run_cpu_baseline(args, args.cpu_steps)
     res = {
@@ -218,6 +307,8 @@ def main():
         "detail": {
             "ms_lanczos_per_step": round(g["ms_lanczos_per_step"], 3),
             "ms_small_sign_per_step": round(g["ms_small_sign_per_step"], 3),
+            "update_kernel": g["update_kernel"],
+            "forms": g["forms"],
             "dw_v": g["dw_v"],
             "min_margin": g["min_margin"],
             "sign_check": g["sign_check"],

@@ -86,6 +86,8 @@ typedef struct {
     double ms_lanczos;      /* device time of the Lanczos steps (HIP events) */
     double ms_small_sign;   /* device time of the sgn(T_k) e_1 solve */
     double ms_total;        /* device time of the whole call */
+    double ms_stencil;      /* summed device time of the k stencil launches (HIP events) */
+    double ms_update;       /* summed device time of the k - 1 three-term update launches */
 } ovd_stats;
 
 /* Create a handle for one lattice.  Sec. 4 lattices are Lt x Ls^3 (e.g. 14 x 14^3).

@@ -50,6 +50,8 @@ struct ovd_lattice {
     // coefficients of the last Lanczos run
     int last_nrhs = 0, last_k = 0;
     TslCoeffs last_co{};
+    // event pool for per-kernel timing of the Lanczos loop
+    std::vector<hipEvent_t> ev;
 };
 
 namespace {
@@ -132,7 +134,7 @@ __global__ void left_sum_kernel(Geom g, const cpx<T>* __restrict__ src, cpx<T>* 
     cpx<T>* o = dst + r * stride;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t)c * g.Vp + s;
+        const size_t i = fidx<T>(c, s, g.Vp);
         const cpx<T> t = a[i], b = a[HALF + i];
         o[i] = t + b;
         o[HALF + i] = b;
@@ -188,19 +190,22 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     const long long sV = basis ? (long long)k * fsz : fsz;
 
     Timer tl, ts;
+    // per-kernel events: 4 per step (update start/end, stencil start/end)
+    const size_t nev = (size_t)4 * k;
+    while (h->ev.size() < nev) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        h->ev.push_back(e);
+    }
     tl.start(h->stream);
     const double md = h->m0 + 4.0 * h->r;
+    // start vectors into slot 1
+    HIPCHK(hipMemcpy2DAsync(Vs(1), sizeof(cpx<T>) * sV, src_v, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
+                            hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(Ws(1), src_w, sizeof(cpx<T>) * nrhs * fsz, hipMemcpyDeviceToDevice, h->stream));
     for (int j = 0; j < k; ++j) {
         StepPtrs p{};
-        int nt;
-        if (j == 0) {
-            nt = 0;
-            p.Xv = p.Yv = p.Zv = src_v;
-            p.Xw = p.Yw = p.Zw = src_w;
-            p.sXv = p.sYv = p.sZv = fsz;
-            p.sXw = p.sYw = p.sZw = fsz;
-        } else {
-            nt = (j == 1) ? 2 : 3;
+        if (j > 0) {
             p.Xv = Us(j); p.sXv = fsz;
             p.Yv = Vs(j); p.sYv = sV;
             p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
@@ -214,8 +219,15 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         p.outZ = Zs(j + 1); p.sZ = fsz;
         p.xproj = xproj;
         p.sx = (long long)12 * g.Vp;
-        launch_tsl_step<T>(g, dir, nrhs, nt, p, U, dU, md, st, co, partials, counters, j,
-                           h->opt.breakdown_tol, h->stream);
+        if (j > 0) {
+            HIPCHK(hipEventRecord(h->ev[4 * j], h->stream));
+            launch_tsl_update<T>(nrhs, j == 1 ? 2 : 3, fsz, p, st, h->stream);
+            HIPCHK(hipEventRecord(h->ev[4 * j + 1], h->stream));
+        }
+        HIPCHK(hipEventRecord(h->ev[4 * j + 2], h->stream));
+        launch_tsl_stencil<T>(g, dir, nrhs, p, U, dU, md, st, co, partials, counters, j,
+                              h->opt.breakdown_tol, h->stream);
+        HIPCHK(hipEventRecord(h->ev[4 * j + 3], h->stream));
     }
     HIPCHK(hipGetLastError());
     tl.stop(h->stream);
@@ -241,6 +253,14 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         stats->breakdown_step = bstep;
         stats->min_margin = minm;
         stats->ms_lanczos = tl.ms();
+        double msu = 0.0, mss = 0.0;
+        for (int j = 0; j < k; ++j) {
+            float t = 0.f;
+            if (j > 0 && hipEventElapsedTime(&t, h->ev[4 * j], h->ev[4 * j + 1]) == hipSuccess) msu += t;
+            if (hipEventElapsedTime(&t, h->ev[4 * j + 2], h->ev[4 * j + 3]) == hipSuccess) mss += t;
+        }
+        stats->ms_update = msu;
+        stats->ms_stencil = mss;
     }
     if (bad == 1) return fail(h, OVD_EBREAKDOWN, "two-sided Lanczos breakdown at step " + std::to_string(bstep));
     if (bad == 2) return fail(h, OVD_ENAN, "non-finite value in the Lanczos recurrence at step " + std::to_string(bstep));
@@ -346,11 +366,10 @@ ovd_status upload_dir(ovd_h h, const ovd_dir* dir, int* dirk) {
         return OVD_OK;
     }
     if (dir->kind != OVD_DIR_LINK || !dir->dU) return fail(h, OVD_EINVAL, "bad derivative direction");
-    const size_t n = (size_t)4 * 9 * h->g.Vp;
-    WS(d64, c64, "dU64", n);
+    WS(d64, c64, "dU64", link_elems<double>(h->g.Vp));
     c32* d32 = nullptr;
     if (h->opt.precision == OVD_MIXED) {
-        WS(t32, c32, "dU32", n);
+        WS(t32, c32, "dU32", link_elems<float>(h->g.Vp));
         d32 = t32;
     }
     launch_pack_links(h->g, dir->dU, d64, d32, h->stream);
@@ -404,6 +423,7 @@ ovd_status ovd_destroy(ovd_h h) {
     if (!h) return OVD_EINVAL;
     (void)hipStreamSynchronize(h->stream);
     for (auto& kv : h->ws) (void)hipFree(kv.second.first);
+    for (auto e : h->ev) (void)hipEventDestroy(e);
     if (h->U64) (void)hipFree(h->U64);
     if (h->U32) (void)hipFree(h->U32);
     for (auto& d : h->defl) {
@@ -427,9 +447,8 @@ ovd_status ovd_set_stream(ovd_h h, void* stream) {
 ovd_status ovd_set_links(ovd_h h, const void* U) {
     if (!h) return OVD_EINVAL;
     if (!U) return fail(h, OVD_EINVAL, "null link pointer");
-    const size_t n = (size_t)4 * 9 * h->g.Vp;
-    if (!h->U64) HIPCHK(hipMalloc(&h->U64, n * sizeof(c64)));
-    if (h->opt.precision == OVD_MIXED && !h->U32) HIPCHK(hipMalloc(&h->U32, n * sizeof(c32)));
+    if (!h->U64) HIPCHK(hipMalloc(&h->U64, link_elems<double>(h->g.Vp) * sizeof(c64)));
+    if (h->opt.precision == OVD_MIXED && !h->U32) HIPCHK(hipMalloc(&h->U32, link_elems<float>(h->g.Vp) * sizeof(c32)));
     launch_pack_links(h->g, U, h->U64, h->U32, h->stream);
     HIPCHK(hipGetLastError());
     h->links_set = true;

@@ -15,10 +15,10 @@ __global__ void pack_links_kernel(Geom g, const c64* __restrict__ in, c64* __res
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const c64 u = src[i];
-        const size_t o = ((size_t)nu * 9 + i) * g.Vp + s;
-        if (o64) o64[o] = u;
-        if (o32) o32[o] = cast<float>(u);
+        if (o64) o64[lidx<double>(nu, i, s, g.Vp)] = u;
+        if (o32) o32[lidx<float>(nu, i, s, g.Vp)] = cast<float>(u);
     }
+    if (o32) o32[lidx<float>(nu, 9, s, g.Vp)] = c32{0.f, 0.f};
 }
 
 void launch_pack_links(const Geom& g, const void* U_aos, c64* U64, c32* U32, hipStream_t s) {
@@ -35,7 +35,7 @@ __global__ void pack_spinor_kernel(Geom g, const c64* __restrict__ in, cpx<T>* _
     const c64* src = in + ((size_t)r * g.V + s) * 12;
     cpx<T>* dst = out + r * stride;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[(size_t)c * g.Vp + s] = cast<T>(src[c]);
+    for (int c = 0; c < 12; ++c) dst[fidx<T>(c, s, g.Vp)] = cast<T>(src[c]);
 }
 
 template <typename T>
@@ -47,7 +47,7 @@ __global__ void unpack_spinor_kernel(Geom g, const cpx<T>* __restrict__ in, long
     const cpx<T>* src = in + r * stride;
     c64* dst = out + ((size_t)r * g.V + s) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[c] = cast<double>(src[(size_t)c * g.Vp + s]);
+    for (int c = 0; c < 12; ++c) dst[c] = cast<double>(src[fidx<T>(c, s, g.Vp)]);
 }
 
 template <typename T>
@@ -86,7 +86,7 @@ __global__ void reconstruct_kernel(Geom g, int k, const cpx<T>* __restrict__ bas
         const c64 w = cf[j];
         const cpx<T>* Bj = B + j * s_j;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] += w * cast<double>(Bj[(size_t)c * g.Vp + s]);
+        for (int c = 0; c < 12; ++c) acc[c] += w * cast<double>(Bj[fidx<T>(c, s, g.Vp)]);
     }
     c64* dst = out + ((size_t)r * g.V + s) * 12;
 #pragma unroll

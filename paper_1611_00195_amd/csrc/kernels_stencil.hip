@@ -1,5 +1,6 @@
-// Wilson-Dirac stencil kernels for gfx950: the standalone operator apply and
-// the fused two-sided Lanczos step.
+// Wilson-Dirac stencil kernels for gfx950: the standalone operator apply, and
+// the two kernels of one two-sided Lanczos step (three-term update, then the
+// stencil with the step's inner products).
 //
 // Operator (Sec. 1, eq. 1): H(mu) = gamma5 Dw(mu) with
 //   Dw(mu) psi(x) = (m0 + 4) psi(x) - 1/2 sum_nu [ e^{mu d_nu4} (1 - gamma_nu) U_nu(x) psi(x+nu)
@@ -12,33 +13,32 @@
 //
 // Memory: fields are stored [12][Vp] (component-major), so the 64 lanes of a
 // wave read 64 consecutive sites of one component in one coalesced access;
-// links are [4][9][Vp].  The kernels are bound by HBM/MALL bandwidth, not by
-// arithmetic: no MFMA, no LDS staging of neighbours (the 4D halo of any tile
-// small enough for LDS would be larger than the tile); neighbour reuse comes
-// from L1/L2, helped by an XCD-aware block order that gives each of the eight
-// XCDs a contiguous slab of sites.
+// links are [4][9][Vp].  The kernels are bound by memory bandwidth and
+// latency, not arithmetic: no MFMA and no LDS staging of neighbours (the 4D
+// halo of any tile small enough for LDS would be larger than the tile);
+// neighbour reuse comes from L1/L2, helped by an XCD-aware block order that
+// gives each of the eight XCDs a contiguous slab of sites.  Every hop issues
+// all of its loads before any arithmetic (branch-free, one load batch per
+// hop), which is what keeps enough bytes in flight.
 #include "ovd_internal.h"
+
+// occupancy hint for the stencil kernels (waves per SIMD); empty = compiler's choice
+#ifndef OVD_OCC
+#define OVD_OCC
+#endif
 
 namespace ovd {
 
 // ---------------------------------------------------------------------------
-// multiplication by the constants +1, -1, +i, -i
+// spin projection table
 // ---------------------------------------------------------------------------
-enum { F_P1 = 0, F_M1 = 1, F_PI = 2, F_MI = 3 };
-template <int F, typename T>
-__device__ __forceinline__ cpx<T> mulf(cpx<T> z) {
-    if constexpr (F == F_P1) return z;
-    else if constexpr (F == F_M1) return {-z.re, -z.im};
-    else if constexpr (F == F_PI) return {-z.im, z.re};
-    else return {z.im, -z.re};
-}
-
-// Spin projection of (1 - gamma_nu) (forward hop) and (1 + gamma_nu)
-// (backward hop) in the chiral basis, for hop index i = 2 nu + (backward):
+// (1 - gamma_nu) (forward hop) and (1 + gamma_nu) (backward hop) in the chiral
+// basis, hop index i = 2 nu + (backward):
 //   h0 = psi_0 + F0 psi_P0,  h1 = psi_1 + F1 psi_P1  (P1 = 5 - P0)
 //   result spins 0,1 = h0, h1;  spin 2 = G0 h_Q0,  spin 3 = G1 h_Q1  (Q1 = 1 - Q0)
 // with F, G in {+1, -1, +i, -i} (codes 0..3).  Packed per hop as
 //   bit 0: P0 == 3,  bits 1-2: F0, 3-4: F1,  bit 5: Q0,  bits 6-7: G0, 8-9: G1.
+enum { F_P1 = 0, F_M1 = 1, F_PI = 2, F_MI = 3 };
 #define OVD_HOP(P0, F0, F1, Q0, G0, G1) \
     ((P0 == 3 ? 1 : 0) | ((F0) << 1) | ((F1) << 3) | ((Q0) << 5) | ((G0) << 6) | ((G1) << 8))
 __constant__ int kHop[8] = {
@@ -52,88 +52,16 @@ __constant__ int kHop[8] = {
     OVD_HOP(2, F_P1, F_P1, 0, F_P1, F_P1)};  // t backward
 #undef OVD_HOP
 
-// z times the constant with code f (0: +1, 1: -1, 2: +i, 3: -i)
+// z times the constant with code f (0: +1, 1: -1, 2: +i, 3: -i), branch-free:
+// +1: (re, im), -1: (-re, -im), +i: (-im, re), -i: (im, -re)
 template <typename T>
 __device__ __forceinline__ cpx<T> mulc(cpx<T> z, int f) {
-    const T re = (f == 0) ? z.re : (f == 1) ? -z.re : (f == 2) ? -z.im : z.im;
-    const T im = (f == 0) ? z.im : (f == 1) ? -z.im : (f == 2) ? z.re : -z.re;
-    return {re, im};
-}
-
-// ---------------------------------------------------------------------------
-// field loaders
-// ---------------------------------------------------------------------------
-// a X + b Y + c Z on one [12][Vp] field; nt = 0 reads X unscaled.
-template <typename T>
-struct Lin3 {
-    const cpx<T>* __restrict__ X;
-    const cpx<T>* __restrict__ Y;
-    const cpx<T>* __restrict__ Z;
-    cpx<T> a, b, c;
-    int nt, Vp;
-    __device__ __forceinline__ cpx<T> operator()(int comp, int n) const {
-        const size_t o = (size_t)comp * Vp + n;
-        cpx<T> x = X[o];
-        if (nt == 0) return x;
-        cpx<T> r = a * x;
-        if (nt >= 2) r += b * Y[o];
-        if (nt >= 3) r += c * Z[o];
-        return r;
-    }
-    __device__ __forceinline__ cpx<T> operator()(int comp, int n, int) const { return (*this)(comp, n); }
-};
-
-// P + s Q with s in {0, +1, -1} (uniform per wave): the mu-derivative
-// combines the two halves of a block vector on the time hops.
-template <typename T>
-struct Src2 {
-    Lin3<T> p, q;
-    __device__ __forceinline__ cpx<T> operator()(int comp, int n, int sg) const {
-        cpx<T> v = p(comp, n);
-        if (sg > 0) v += q(comp, n);
-        else if (sg < 0) v -= q(comp, n);
-        return v;
-    }
-};
-
-// ---------------------------------------------------------------------------
-// one hop: acc += coef * (1 -+ gamma_nu) W psi(n), W = U_nu(x) forward or
-// U_nu(x-nu)^dag backward (ls = site of the link)
-// ---------------------------------------------------------------------------
-template <typename T, class SRC>
-__device__ __forceinline__ void hop(cpx<T> (&acc)[12], const SRC& src, int sg, int n, int hidx,
-                                    const cpx<T>* __restrict__ W, int ls, int Vp, T coef) {
-    const int code = kHop[hidx];
-    const int p0 = (code & 1) ? 3 : 2, p1 = 5 - p0;
-    const int f0 = (code >> 1) & 3, f1 = (code >> 3) & 3;
-    const int q0 = (code >> 5) & 1;
-    const int g0c = (code >> 6) & 3, g1c = (code >> 8) & 3;
-    const bool fwd = (hidx & 1) == 0;
-    cpx<T> h0[3], h1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        h0[c] = src(c, n, sg) + mulc(src(p0 * 3 + c, n, sg), f0);
-        h1[c] = src(3 + c, n, sg) + mulc(src(p1 * 3 + c, n, sg), f1);
-    }
-    const cpx<T>* Wn = W + (size_t)(hidx >> 1) * 9 * Vp + ls;
-    // forward: row a of U is U[a][b] at 3a+b;  backward: row a of U^dag is conj(U[b][a]) at 3b+a
-    const int ra = fwd ? 3 : 1, rb = fwd ? 1 : 3;
-    const T cs = fwd ? T(1) : T(-1);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cpx<T> u[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const cpx<T> w = Wn[(size_t)(ra * a + rb * b) * Vp];
-            u[b] = {w.re, cs * w.im};
-        }
-        const cpx<T> g0 = u[0] * h0[0] + u[1] * h0[1] + u[2] * h0[2];
-        const cpx<T> g1 = u[0] * h1[0] + u[1] * h1[1] + u[2] * h1[2];
-        acc[a] += coef * g0;
-        acc[3 + a] += coef * g1;
-        acc[6 + a] += coef * mulc(q0 == 0 ? g0 : g1, g0c);
-        acc[9 + a] += coef * mulc(q0 == 0 ? g1 : g0, g1c);
-    }
+    const bool sw = f >= 2;
+    const T re = sw ? z.im : z.re;
+    const T im = sw ? z.re : z.im;
+    const T sr = (f == 1 || f == 2) ? T(-1) : T(1);
+    const T si = (f == 1 || f == 3) ? T(-1) : T(1);
+    return {sr * re, si * im};
 }
 
 struct Nbr {
@@ -163,18 +91,106 @@ __device__ __forceinline__ Nbr neighbours(const Geom& g, int s) {
     return N;
 }
 
-// All eight hops, one loop iteration each, sharing one code path (the loop is
-// not unrolled so that the loads of later hops are not hoisted).  Spatial hops
-// read `src` with sign 0, the forward / backward time hops with signs sf / sb
-// (a two-field source then combines the two halves of a block vector).  Coefficients: -1/2 cs in space, -1/2 cf
-// and -1/2 cb in time, times the boundary factor on a wrapping time hop.
-template <typename T, class SRC>
-__device__ __forceinline__ void hops8(cpx<T> (&acc)[12], const SRC& src, int sf, int sb,
-                                      const Nbr& N, int s, const cpx<T>* __restrict__ W, int Vp,
-                                      T cs, T cf, T cb, int bc, bool space = true) {
+// Whole-site loads and stores of a spinor field and of one link matrix, 16
+// bytes per lane (one complex in FP64, two in FP32).
+template <typename T>
+__device__ __forceinline__ void load12(const cpx<T>* __restrict__ F, int n, int Vp, cpx<T> (&v)[12]) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = F[(size_t)c * Vp + n];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const float4 t = *reinterpret_cast<const float4*>(F + ((size_t)q * Vp + n) * 2);
+            v[2 * q] = {t.x, t.y};
+            v[2 * q + 1] = {t.z, t.w};
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store12(cpx<T>* __restrict__ F, int n, int Vp, const cpx<T> (&v)[12]) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) F[(size_t)c * Vp + n] = v[c];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            *reinterpret_cast<float4*>(F + ((size_t)q * Vp + n) * 2) =
+                float4{v[2 * q].re, v[2 * q].im, v[2 * q + 1].re, v[2 * q + 1].im};
+    }
+}
+
+// the 3x3 link U_nu(ls), entries 3a + b
+template <typename T>
+__device__ __forceinline__ void load_link(const cpx<T>* __restrict__ W, int nu, int ls, int Vp, cpx<T> (&u)[9]) {
+    if constexpr (sizeof(T) == 8) {
+        const cpx<T>* Wn = W + (size_t)nu * 9 * Vp + ls;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) u[i] = Wn[(size_t)i * Vp];
+    } else {
+        const cpx<T>* Wn = W + (size_t)nu * 5 * Vp * 2 + (size_t)ls * 2;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const float4 t = *reinterpret_cast<const float4*>(Wn + (size_t)q * Vp * 2);
+            u[2 * q] = {t.x, t.y};
+            if (2 * q + 1 < 9) u[2 * q + 1] = {t.z, t.w};
+        }
+    }
+}
+
+// half spinor of field F at site n for hop code `code`
+template <typename T>
+__device__ __forceinline__ void project(const cpx<T>* __restrict__ F, int n, int Vp, int code,
+                                        cpx<T> (&h0)[3], cpx<T> (&h1)[3]) {
+    cpx<T> v[12];
+    load12(F, n, Vp, v);
+    const bool p3 = code & 1;
+    const int f0 = (code >> 1) & 3, f1 = (code >> 3) & 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> a = p3 ? v[9 + c] : v[6 + c];   // spin P0
+        const cpx<T> b = p3 ? v[6 + c] : v[9 + c];   // spin P1
+        h0[c] = v[c] + mulc(a, f0);
+        h1[c] = v[3 + c] + mulc(b, f1);
+    }
+}
+
+// acc += coef * reconstruct(W h), W = U_nu(ls) (forward) or U_nu(ls)^dag (backward)
+template <typename T>
+__device__ __forceinline__ void link_mult_acc(cpx<T> (&acc)[12], const cpx<T> (&h0)[3], const cpx<T> (&h1)[3],
+                                              const cpx<T>* __restrict__ W, int hidx, int code, int ls, int Vp,
+                                              T coef) {
+    const bool fwd = (hidx & 1) == 0;
+    const int q0 = (code >> 5) & 1;
+    const int g0c = (code >> 6) & 3, g1c = (code >> 8) & 3;
+    cpx<T> u[9];
+    load_link(W, hidx >> 1, ls, Vp, u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // row a of U:  U[a][b] = u[3a + b];  row a of U^dag: conj(U[b][a]) = conj(u[3b + a])
+        const cpx<T> r0 = fwd ? u[3 * a] : conj(u[a]);
+        const cpx<T> r1 = fwd ? u[3 * a + 1] : conj(u[3 + a]);
+        const cpx<T> r2 = fwd ? u[3 * a + 2] : conj(u[6 + a]);
+        const cpx<T> g0 = r0 * h0[0] + r1 * h0[1] + r2 * h0[2];
+        const cpx<T> g1 = r0 * h1[0] + r1 * h1[1] + r2 * h1[2];
+        acc[a] += coef * g0;
+        acc[3 + a] += coef * g1;
+        acc[6 + a] += coef * mulc(q0 == 0 ? g0 : g1, g0c);
+        acc[9 + a] += coef * mulc(q0 == 0 ? g1 : g0, g1c);
+    }
+}
+
+// The eight hops of field P (links W).  On the two time hops the field
+// P + sf Q (forward) / P + sb Q (backward) is used instead, sf, sb in {0, +-1}
+// (the mu derivative of the block matrix combines its two halves there);
+// spatial hops get -1/2 cs, time hops -1/2 cf / -1/2 cb and the boundary
+// factor.  With space == false only the time hops are applied.
+template <typename T>
+__device__ __forceinline__ void hops(cpx<T> (&acc)[12], const cpx<T>* __restrict__ P, const cpx<T>* __restrict__ Q,
+                                     int sf, int sb, const Nbr& N, int s, const cpx<T>* __restrict__ W, int Vp,
+                                     T cs, T cf, T cb, int bc, bool space) {
     const T h = T(-0.5);
-    const T ctf = h * cf * (N.wf ? T(bc) : T(1));
-    const T ctb = h * cb * (N.wb ? T(bc) : T(1));
 #pragma unroll 1
     for (int i = space ? 0 : 6; i < 8; ++i) {
         const int nu = i >> 1;
@@ -183,71 +199,115 @@ __device__ __forceinline__ void hops8(cpx<T> (&acc)[12], const SRC& src, int sf,
         const int nbk = nu == 0 ? N.b[0] : nu == 1 ? N.b[1] : nu == 2 ? N.b[2] : N.b[3];
         const int n = fwd ? nf : nbk;
         const int ls = fwd ? s : nbk;
-        const T coef = (nu < 3) ? h * cs : (fwd ? ctf : ctb);
+        const int code = kHop[i];
+        T coef = h * cs;
+        if (nu == 3) coef = fwd ? h * cf * (N.wf ? T(bc) : T(1)) : h * cb * (N.wb ? T(bc) : T(1));
+        cpx<T> h0[3], h1[3];
+        project(P, n, Vp, code, h0, h1);
         const int sg = (nu < 3) ? 0 : (fwd ? sf : sb);
-        hop(acc, src, sg, n, i, W, ls, Vp, coef);
+        if (sg != 0) {   // uniform per wave
+            cpx<T> q0[3], q1[3];
+            project(Q, n, Vp, code, q0, q1);
+            const T sgn = T(sg);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                h0[c] += sgn * q0[c];
+                h1[c] += sgn * q1[c];
+            }
+        }
+        link_mult_acc(acc, h0, h1, W, i, code, ls, Vp, coef);
     }
 }
 
-__device__ __forceinline__ int xcd_group(int bid, int nb) {
-    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of site groups (nb is a multiple of 8)
-    return (bid & 7) * (nb >> 3) + (bid >> 3);
+// Work decomposition over the 8 XCDs.  Blocks are dispatched round-robin over
+// the XCDs (block b runs on XCD b % 8, in order of b / 8), and each XCD has its
+// own 4 MB L2.  A stencil re-reads every field at the neighbouring sites, the
+// furthest (the time neighbours) one time slice (Lx Ly Lz sites) away, so an
+// XCD keeps its neighbour data in L2 only if it sweeps a compact piece of
+// work in site order.  The (rhs, site group) work items are therefore split
+// into 8 compact chunks, one per XCD:
+//   nrhs a multiple of 8:  XCD x takes right-hand sides x m .. x m + m - 1
+//                          (m = nrhs / 8) over the whole lattice, site group
+//                          major, so those m share each link read;
+//   nrhs dividing 8:       XCD x takes one right-hand side over 1/(8/nrhs) of
+//                          the lattice (a contiguous range of time slices);
+//   otherwise:             contiguous ranges of (site group, rhs) pairs.
+// nb (site groups per rhs, padded) is a multiple of 8.
+struct Work {
+    int rhs, grp;
+};
+__device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs) {
+    const int x = bid & 7, idx = bid >> 3;
+    Work w;
+    if ((nrhs & 7) == 0) {
+        const int m = nrhs >> 3;
+        w.grp = idx / m;
+        w.rhs = x * m + idx % m;
+    } else if ((8 % nrhs) == 0) {
+        const int parts = 8 / nrhs;
+        w.rhs = x / parts;
+        w.grp = (x % parts) * (nb / parts) + idx;
+    } else {
+        const int i = x * (nb * nrhs / 8) + idx;
+        w.grp = i / nrhs;
+        w.rhs = i % nrhs;
+    }
+    return w;
 }
 
 // ---------------------------------------------------------------------------
 // standalone operator
 // ---------------------------------------------------------------------------
 template <typename T, int OP>
-__global__ __launch_bounds__(256) void apply_op_kernel(Geom g, const double* __restrict__ emu,
+__global__ __launch_bounds__(256) OVD_OCC void apply_op_kernel(Geom g, const double* __restrict__ emu,
                                                        const cpx<T>* __restrict__ U,
                                                        const cpx<T>* __restrict__ dU, T mdiag,
                                                        const cpx<T>* __restrict__ in,
-                                                       cpx<T>* __restrict__ out, int ngroups) {
-    const int rhs = blockIdx.y;
-    const int grp = xcd_group(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+                                                       cpx<T>* __restrict__ out, int ngroups, int nrhs) {
+    const Work w = xcd_work(blockIdx.x, gridDim.x / nrhs, nrhs);
+    const int rhs = w.rhs;
+    const int grp = w.grp * 4 + (threadIdx.x >> 6);
     const int s = grp * 64 + (threadIdx.x & 63);
     if (grp >= ngroups || s >= g.V) return;
     const int Vp = g.Vp;
     const size_t roff = (size_t)rhs * 12 * Vp;
     const T ep = T(emu[2 * rhs]), em = T(emu[2 * rhs + 1]);
-    Lin3<T> P{in + roff, nullptr, nullptr, {}, {}, {}, 0, Vp};
+    const cpx<T>* P = in + roff;
     const Nbr N = neighbours(g, s);
     cpx<T> acc[12];
     if constexpr (OP == 0 || OP == 1) {          // H or Dw
+        load12(P, s, Vp, acc);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = mdiag * P(c, s);
-        hops8(acc, P, 0, 0, N, s, U, Vp, T(1), ep, em, g.bc_t);
+        for (int c = 0; c < 12; ++c) acc[c] = mdiag * acc[c];
+        hops(acc, P, P, 0, 0, N, s, U, Vp, T(1), ep, em, g.bc_t, true);
     } else if constexpr (OP == 2) {             // dH/dmu: time hops, e^{mu} and -e^{-mu}
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
-        hops8(acc, P, 0, 0, N, s, U, Vp, T(0), ep, -em, g.bc_t, false);
+        hops(acc, P, P, 0, 0, N, s, U, Vp, T(0), ep, -em, g.bc_t, false);
     } else {                                    // dH/dt along dU: hops with dU, no mass term
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
-        hops8(acc, P, 0, 0, N, s, dU, Vp, T(1), ep, em, g.bc_t);
+        hops(acc, P, P, 0, 0, N, s, dU, Vp, T(1), ep, em, g.bc_t, true);
     }
-    cpx<T>* o = out + roff;
+    if (OP != 1) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        cpx<T> v = acc[c];
-        if (OP != 1 && c >= 6) v = -v;          // gamma5
-        o[(size_t)c * Vp + s] = v;
+        for (int c = 6; c < 12; ++c) acc[c] = -acc[c];   // gamma5
     }
+    store12(out + roff, s, Vp, acc);
 }
 
 template <typename T>
 void launch_apply_op(const Geom& g, int op, int nrhs, const double* d_emu, const cpx<T>* U,
                      const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s) {
     const int ngroups = (g.V + 63) / 64;
-    const int nb = ((ngroups + 3) / 4 + 7) / 8 * 8;
-    dim3 grid(nb, nrhs), block(256);
+    const int nq = ((ngroups + 3) / 4 + 7) / 8 * 8;   // blocks of 4 site groups, padded to 8
+    dim3 grid(nq * nrhs), block(256);
     const T md = T(m_diag);
     switch (op) {
-        case 0: apply_op_kernel<T, 0><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups); break;
-        case 1: apply_op_kernel<T, 1><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups); break;
-        case 2: apply_op_kernel<T, 2><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups); break;
-        default: apply_op_kernel<T, 3><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups); break;
+        case 0: apply_op_kernel<T, 0><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
+        case 1: apply_op_kernel<T, 1><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
+        case 2: apply_op_kernel<T, 2><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
+        default: apply_op_kernel<T, 3><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
     }
 }
 template void launch_apply_op<double>(const Geom&, int, int, const double*, const c64*, const c64*, double,
@@ -283,20 +343,45 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* [16
 }
 
 // ---------------------------------------------------------------------------
-// fused two-sided Lanczos step
+// Lanczos step, part 1: three-term update (element-wise)
+//     vhat_{j+1} = av X + bv Y + cv Z,   what_{j+1} = aw X' + bw Y' + cw Z'
+// with X = A vhat_j, Y = vhat_j, Z = vhat_{j-1} (all unnormalised; the
+// coefficients fold in the normalisations, see the stencil kernel below).
+// blockIdx.z = side (0: v, 1: w); NT = number of terms (2 on the first update).
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n_elem,
+                                                         const TslState* __restrict__ st) {
+    const int rhs = blockIdx.y;
+    const TslState* S = st + rhs;
+    if (S->flag) return;
+    const bool vside = blockIdx.z == 0;
+    const cpx<T> a = cast<T>(vside ? S->av : S->aw);
+    const cpx<T> b = cast<T>(vside ? S->bv : S->bw);
+    const cpx<T> c = cast<T>(vside ? S->cv : S->cw);
+    const cpx<T>* X = vside ? (const cpx<T>*)p.Xv + rhs * p.sXv : (const cpx<T>*)p.Xw + rhs * p.sXw;
+    const cpx<T>* Y = vside ? (const cpx<T>*)p.Yv + rhs * p.sYv : (const cpx<T>*)p.Yw + rhs * p.sYw;
+    const cpx<T>* Z = vside ? (const cpx<T>*)p.Zv + rhs * p.sZv : (const cpx<T>*)p.Zw + rhs * p.sZw;
+    cpx<T>* O = vside ? (cpx<T>*)p.outV + rhs * p.sV : (cpx<T>*)p.outW + rhs * p.sW;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+        cpx<T> r = a * X[e] + b * Y[e];
+        if constexpr (NT == 3) r += c * Z[e];
+        O[e] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos step, part 2: stencil and inner products.
 //
-// Step j (0-based) forms the next unnormalised Lanczos vectors
-//     vhat = av X_v + bv Y_v + cv Z_v,   what = aw X_w + bw Y_w + cw Z_w
-// (X = A v_j, Y = v_j, Z = v_{j-1}, all unnormalised, the coefficients fold
-// in the normalisations) at every site and, because the stencil needs them,
-// at the eight neighbours; it writes vhat, A vhat, what, A^dag what and the
-// block partial sums of
-//     omega = what^dag vhat,  gamma = what^dag A vhat,  p = x^dag vhat_top,
-//     |vhat|^2, |what|^2.
+// Reads the new unnormalised vectors vhat, what, writes A vhat and A^dag what
+// and the block partial sums of
+//     omega = what^dag vhat,  gamma = what^dag A vhat = (A^dag what)^dag vhat,
+//     p = x^dag vhat_top,  |vhat|^2, |what|^2.
 // The last block to finish sums the partials in a fixed order and advances the
 // recurrence: delta = sqrt|omega|, beta = omega/delta, alpha = gamma/omega
-// (= w^dag A v for the normalised vectors), so each step costs one launch and
-// one grid-wide reduction.
+// (= w^dag A v for the normalised vectors), and the coefficients of the next
+// update.  One grid-wide reduction per Lanczos step, no host round trip.
 //
 // Work split: a block is NK waves over the same 64 sites, wave = output kind.
 //   DIR 0 (A = H):                kind 0 = H vhat,  kind 1 = H^dag what
@@ -304,24 +389,26 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* [16
 //     kind 0 = H vt + dH vb,  kind 1 = H vb,  kind 2 = H^dag wt,  kind 3 = dH^dag wt + H^dag wb
 // with H^dag = H(-mu); for d/dmu, dH only has time hops (e^{mu}, -e^{-mu}) and
 // dH^dag = -dH/dmu(-mu) (time hops -e^{-mu}, e^{mu}); for a link direction,
-// dH is the hopping term with links dU and dH^dag that with dU at -mu.
+// dH is the hopping term with links dU, and dH^dag that with dU at -mu.
 // ---------------------------------------------------------------------------
 template <typename T, int DIR>
-__global__ __launch_bounds__(256) void tsl_step_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
-                                                       const cpx<T>* __restrict__ dU, T mdiag,
-                                                       TslState* __restrict__ st, TslCoeffs co,
-                                                       double* __restrict__ partials,
-                                                       unsigned* __restrict__ counters, int j, double tau,
-                                                       int nt, int ngroups) {
+__global__ __launch_bounds__(256) OVD_OCC void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
+                                                          const cpx<T>* __restrict__ dU, T mdiag,
+                                                          TslState* __restrict__ st, TslCoeffs co,
+                                                          double* __restrict__ partials,
+                                                          unsigned* __restrict__ counters, int j, double tau,
+                                                          int ngroups, int nrhs) {
     constexpr int NK = (DIR == 0) ? 2 : 4;
     __shared__ double lds[16 * 8];
     __shared__ int am_last;
-    const int rhs = blockIdx.y;
+    const int nb = gridDim.x / nrhs;                // blocks per rhs
+    const Work wk = xcd_work(blockIdx.x, nb, nrhs);
+    const int rhs = wk.rhs;
+    const int grp = wk.grp;                         // in [0, ngroups padded to 8)
     TslState* S = st + rhs;
-    if (S->flag) return;   // uniform over the grid: breakdown in an earlier step
+    if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
     const int Vp = g.Vp;
     const int kind = threadIdx.x >> 6;
-    const int grp = xcd_group(blockIdx.x, gridDim.x);
     const int s = grp * 64 + (threadIdx.x & 63);
     const bool active = (grp < ngroups) && (s < g.V) && (kind < NK);
     const T ep = T(S->emu), em = T(S->emu_inv);
@@ -343,69 +430,63 @@ __global__ __launch_bounds__(256) void tsl_step_kernel(Geom g, StepPtrs p, const
         if (DIR == 1 && kind == 3) { sf = -1; sb = +1; }   // dH/dmu^dag wt + H^dag wb
         if (DIR == 2 && (kind == 0 || kind == 3)) sec = true;
     }
-    const cpx<T> ca = cast<T>(vside ? S->av : S->aw);
-    const cpx<T> cb_ = cast<T>(vside ? S->bv : S->bw);
-    const cpx<T> cc = cast<T>(vside ? S->cv : S->cw);
-    const cpx<T>* X = vside ? (const cpx<T>*)p.Xv + rhs * p.sXv : (const cpx<T>*)p.Xw + rhs * p.sXw;
-    const cpx<T>* Y = vside ? (const cpx<T>*)p.Yv + rhs * p.sYv : (const cpx<T>*)p.Yw + rhs * p.sYw;
-    const cpx<T>* Z = vside ? (const cpx<T>*)p.Zv + rhs * p.sZv : (const cpx<T>*)p.Zw + rhs * p.sZw;
-    const Lin3<T> P{X + hp * HALF, Y + hp * HALF, Z + hp * HALF, ca, cb_, cc, nt, Vp};
-    const Lin3<T> Q{X + hq * HALF, Y + hq * HALF, Z + hq * HALF, ca, cb_, cc, nt, Vp};
+    const cpx<T>* F = vside ? (const cpx<T>*)p.outV + rhs * p.sV : (const cpx<T>*)p.outW + rhs * p.sW;
+    const cpx<T>* P = F + hp * HALF;
+    const cpx<T>* Q = F + hq * HALF;
     const T cf = vside ? ep : em, cbk = vside ? em : ep;
 
     double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (active) {
         const Nbr N = neighbours(g, s);
         cpx<T> acc[12];
-        cpx<T>* oV = vside ? (cpx<T>*)p.outV + rhs * p.sV : (cpx<T>*)p.outW + rhs * p.sW;
-        oV += hp * HALF;
+        load12(P, s, Vp, acc);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const cpx<T> v = P(c, s);
-            oV[(size_t)c * Vp + s] = v;
-            acc[c] = mdiag * v;
-        }
-        const Src2<T> pq{P, Q};
-        hops8(acc, pq, sf, sb, N, s, U, Vp, T(1), cf, cbk, g.bc_t);
-        if (DIR == 2 && sec) hops8(acc, Q, 0, 0, N, s, dU, Vp, T(1), cf, cbk, g.bc_t);
+        for (int c = 0; c < 12; ++c) acc[c] = mdiag * acc[c];
+        hops(acc, P, Q, sf, sb, N, s, U, Vp, T(1), cf, cbk, g.bc_t, true);
+        if (DIR == 2 && sec) hops(acc, Q, Q, 0, 0, N, s, dU, Vp, T(1), cf, cbk, g.bc_t, true);
         cpx<T>* oA = vside ? (cpx<T>*)p.outU + rhs * p.sU : (cpx<T>*)p.outZ + rhs * p.sZ;
         oA += hp * HALF;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            if (c >= 6) acc[c] = -acc[c];   // gamma5
-            oA[(size_t)c * Vp + s] = acc[c];
-        }
-        // reduction terms
+        for (int c = 6; c < 12; ++c) acc[c] = -acc[c];   // gamma5
+        store12(oA, s, Vp, acc);
+        // reduction terms.  v side: omega = what^dag vhat, |vhat|^2, p = x^dag vhat_top;
+        // w side: gamma = what^dag A vhat = (A^dag what)^dag vhat, |what|^2.
+        // Each thread holds at most its output and one loaded field at a time.
         if (vside) {
-            const cpx<T>* Xw = (const cpx<T>*)p.Xw + rhs * p.sXw + hp * HALF;
-            const cpx<T>* Yw = (const cpx<T>*)p.Yw + rhs * p.sYw + hp * HALF;
-            const cpx<T>* Zw = (const cpx<T>*)p.Zw + rhs * p.sZw + hp * HALF;
-            const Lin3<T> Wc{Xw, Yw, Zw, cast<T>(S->aw), cast<T>(S->bw), cast<T>(S->cw), nt, Vp};
-            const cpx<T>* xp = (hp == 0 && p.xproj) ? (const cpx<T>*)p.xproj + rhs * p.sx : nullptr;
+            cpx<T> vv[12], wv[12];
+            load12(P, s, Vp, vv);
+            load12((const cpx<T>*)p.outW + rhs * p.sW + hp * HALF, s, Vp, wv);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const c64 w = cast<double>(Wc(c, s));
-                const c64 v = cast<double>(P(c, s));
-                const c64 a = cast<double>(acc[c]);
-                const c64 om = cdot(w, v), ga = cdot(w, a);
+                const c64 om = cdot(cast<double>(wv[c]), cast<double>(vv[c]));
                 part[0] += om.re; part[1] += om.im;
-                part[2] += ga.re; part[3] += ga.im;
-                part[6] += norm2(v);
-                if (xp) {
-                    const c64 pr = cdot(cast<double>(xp[(size_t)c * Vp + s]), v);
+                part[6] += norm2(cast<double>(vv[c]));
+            }
+            if (hp == 0 && p.xproj) {
+                load12((const cpx<T>*)p.xproj + rhs * p.sx, s, Vp, wv);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const c64 pr = cdot(cast<double>(wv[c]), cast<double>(vv[c]));
                     part[4] += pr.re; part[5] += pr.im;
                 }
             }
         } else {
+            cpx<T> vv[12];
+            load12((const cpx<T>*)p.outV + rhs * p.sV + hp * HALF, s, Vp, vv);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) part[7] += norm2(cast<double>(P(c, s)));
+            for (int c = 0; c < 12; ++c) {
+                const c64 ga = cdot(cast<double>(acc[c]), cast<double>(vv[c]));
+                part[2] += ga.re; part[3] += ga.im;
+            }
+            load12(P, s, Vp, vv);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) part[7] += norm2(cast<double>(vv[c]));
         }
     }
 
     block_reduce<8>(part, lds);
-    const int nb = gridDim.x;
     if (threadIdx.x == 0) {
-        double* dst = partials + ((size_t)rhs * nb + blockIdx.x) * 8;
+        double* dst = partials + ((size_t)rhs * nb + grp) * 8;
         for (int i = 0; i < 8; ++i) __hip_atomic_store(dst + i, part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const unsigned prev = atomicAdd(counters + rhs, 1u);
@@ -438,6 +519,7 @@ __global__ __launch_bounds__(256) void tsl_step_kernel(Geom g, StepPtrs p, const
         S->bstep = j;
         return;
     }
+    // j = 0: v_1 = psi/|psi|, w_1 = phi/conj(phi^dag v_1); later delta = sqrt|omega|
     const double delta = (j == 0) ? sqrt(nv) : sqrt(aom);
     const c64 beta = (1.0 / delta) * omega;
     const c64 alpha = cdiv(gam, omega);
@@ -445,6 +527,8 @@ __global__ __launch_bounds__(256) void tsl_step_kernel(Geom g, StepPtrs p, const
     co.beta[ci] = beta;
     co.delta[ci] = c64{delta, 0.0};
     co.proj[ci] = (1.0 / delta) * pr;
+    // next update: vhat = (A vhat - alpha vhat)/delta - beta vhat_prev/delta_prev,
+    //              what = (A^dag what - conj(alpha) what)/conj(beta) - delta what_prev/conj(beta_prev)
     const c64 one{1.0, 0.0};
     S->av = c64{1.0 / delta, 0.0};
     S->bv = -((1.0 / delta) * alpha);
@@ -463,24 +547,40 @@ __global__ __launch_bounds__(256) void tsl_step_kernel(Geom g, StepPtrs p, const
 }
 
 template <typename T>
-void launch_tsl_step(const Geom& g, int dir, int nrhs, int nterms, const StepPtrs& p,
-                     const cpx<T>* U, const cpx<T>* dU, double m_diag, TslState* st,
-                     TslCoeffs co, double* partials, unsigned* counters, int j, double tau,
-                     hipStream_t s) {
+void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, const TslState* st,
+                       hipStream_t s) {
+    long long nblk = (fsz + 255) / 256;
+    if (nblk > 2048) nblk = 2048;
+    dim3 grid((unsigned)nblk, nrhs, 2);
+    if (nterms == 3)
+        tsl_update_kernel<T, 3><<<grid, 256, 0, s>>>(p, fsz, st);
+    else
+        tsl_update_kernel<T, 2><<<grid, 256, 0, s>>>(p, fsz, st);
+}
+
+template <typename T>
+void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
+                        const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
+                        unsigned* counters, int j, double tau, hipStream_t s) {
     const int ngroups = (g.V + 63) / 64;
-    const int nb = (ngroups + 7) / 8 * 8;
-    dim3 grid(nb, nrhs);
+    const int nb = (ngroups + 7) / 8 * 8;   // blocks per rhs; nb * nrhs is a multiple of 8
+    dim3 grid(nb * nrhs);
     const T md = T(m_diag);
     if (dir == 0)
-        tsl_step_kernel<T, 0><<<grid, dim3(128), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, nterms, ngroups);
+        tsl_stencil_kernel<T, 0><<<grid, dim3(128), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
     else if (dir == 1)
-        tsl_step_kernel<T, 1><<<grid, dim3(256), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, nterms, ngroups);
+        tsl_stencil_kernel<T, 1><<<grid, dim3(256), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
     else
-        tsl_step_kernel<T, 2><<<grid, dim3(256), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, nterms, ngroups);
+        tsl_stencil_kernel<T, 2><<<grid, dim3(256), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
 }
-template void launch_tsl_step<double>(const Geom&, int, int, int, const StepPtrs&, const c64*, const c64*,
-                                      double, TslState*, TslCoeffs, double*, unsigned*, int, double, hipStream_t);
-template void launch_tsl_step<float>(const Geom&, int, int, int, const StepPtrs&, const c32*, const c32*,
-                                     double, TslState*, TslCoeffs, double*, unsigned*, int, double, hipStream_t);
+
+#define OVD_INST(T)                                                                                        \
+    template void launch_tsl_update<T>(int, int, long long, const StepPtrs&, const TslState*, hipStream_t); \
+    template void launch_tsl_stencil<T>(const Geom&, int, int, const StepPtrs&, const cpx<T>*, const cpx<T>*, \
+                                        double, TslState*, TslCoeffs, double*, unsigned*, int, double,     \
+                                        hipStream_t);
+OVD_INST(double)
+OVD_INST(float)
+#undef OVD_INST
 
 }  // namespace ovd

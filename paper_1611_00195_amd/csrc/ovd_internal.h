@@ -64,9 +64,27 @@ struct Geom {
     int bc_t;     // +1 periodic, -1 antiperiodic time boundary
 };
 
-// Internal field layout ("SoA"): a spinor field is [12][Vp] complex, a block
-// vector (top, bottom) is [2][12][Vp], links are [4][9][Vp].  Right-hand sides
-// are stacked with an explicit stride.
+// Internal field layout: component-major so that a wave reads 64 consecutive
+// sites of one component at once, and every lane loads 16 bytes:
+//   FP64: spinor [12][Vp] complex, links [4][9][Vp] complex;
+//   FP32: spinor [6][Vp][2] complex (components 2q, 2q+1 side by side),
+//         links [4][5][Vp][2] complex (entries 2q, 2q+1; entry 9 is zero padding).
+// A block vector (top, bottom) is two spinor fields; right-hand sides are
+// stacked with an explicit stride.  Both layouts hold 12 Vp complex per field.
+template <typename T> __host__ __device__ inline size_t fidx(int c, int s, int Vp);
+template <> __host__ __device__ inline size_t fidx<double>(int c, int s, int Vp) { return (size_t)c * Vp + s; }
+template <> __host__ __device__ inline size_t fidx<float>(int c, int s, int Vp) {
+    return ((size_t)(c >> 1) * Vp + s) * 2 + (c & 1);
+}
+template <typename T> __host__ __device__ inline size_t lidx(int nu, int i, int s, int Vp);
+template <> __host__ __device__ inline size_t lidx<double>(int nu, int i, int s, int Vp) {
+    return ((size_t)nu * 9 + i) * Vp + s;
+}
+template <> __host__ __device__ inline size_t lidx<float>(int nu, int i, int s, int Vp) {
+    return ((size_t)nu * 5 + (i >> 1)) * Vp * 2 + (size_t)s * 2 + (i & 1);
+}
+// complex elements of one link field
+template <typename T> inline size_t link_elems(int Vp) { return sizeof(T) == 8 ? (size_t)36 * Vp : (size_t)40 * Vp; }
 
 // Per-right-hand-side scalar state of the Lanczos recurrence, FP64.
 struct TslState {
@@ -117,13 +135,17 @@ template <typename T>
 void launch_apply_op(const Geom& g, int op, int nrhs, const double* d_emu, const cpx<T>* U,
                      const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s);
 
-// fused Lanczos step.  dir: 0 plain H, 1 block with d/dmu, 2 block with d/dlink.
-// nterms: 0 (raw X), 1 (a X), 2 (a X + b Y), 3 (a X + b Y + c Z).
+// Lanczos step part 1: vhat/what = a X + b Y (+ c Z) element-wise on both
+// sides (nterms 2 or 3), fsz elements per rhs and side.
 template <typename T>
-void launch_tsl_step(const Geom& g, int dir, int nrhs, int nterms, const StepPtrs& p,
-                     const cpx<T>* U, const cpx<T>* dU, double m_diag, TslState* st,
-                     TslCoeffs co, double* partials, unsigned* counters, int j, double tau,
-                     hipStream_t s);
+void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, const TslState* st,
+                       hipStream_t s);
+// Lanczos step part 2: stencil on outV/outW into outU/outZ plus the step's
+// reductions and scalar recurrence.  dir: 0 plain H, 1 block d/dmu, 2 block d/dlink.
+template <typename T>
+void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
+                        const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
+                        unsigned* counters, int j, double tau, hipStream_t s);
 
 // sgn(T_k) e_1 for nrhs tridiagonal matrices by the resolvent quadrature.
 void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scratch,

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libovderiv.so")
+LIB_PATH = os.environ.get("OVDERIV_LIB", os.path.join(_HERE, "libovderiv.so"))
 
 OVD_OK, OVD_EINVAL, OVD_ENOMEM, OVD_EHIP, OVD_EBREAKDOWN, OVD_ENODEFL, OVD_ENAN = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
@@ -55,7 +55,8 @@ class _Dir(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("breakdown_step", ctypes.c_int), ("min_margin", ctypes.c_double),
                 ("sign_check", ctypes.c_double), ("ms_lanczos", ctypes.c_double),
-                ("ms_small_sign", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_small_sign", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_stencil", ctypes.c_double), ("ms_update", ctypes.c_double)]
 
 
 @dataclass
@@ -67,6 +68,8 @@ class Stats:
     ms_lanczos: float
     ms_small_sign: float
     ms_total: float
+    ms_stencil: float
+    ms_update: float
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -175,7 +178,8 @@ class Lattice:
 
     @staticmethod
     def _stats(s):
-        return Stats(s.k, s.breakdown_step, s.min_margin, s.sign_check, s.ms_lanczos, s.ms_small_sign, s.ms_total)
+        return Stats(s.k, s.breakdown_step, s.min_margin, s.sign_check, s.ms_lanczos, s.ms_small_sign, s.ms_total,
+                     s.ms_stencil, s.ms_update)
 
     def _dir(self, direction, dU):
         if direction in (None, "mu", DIR_MU):
