@@ -14,6 +14,7 @@
 #include "ovd_internal.h"
 #include "../../include/ovderiv.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -27,11 +28,14 @@ using namespace ovd;
 struct DeflSet {
     double mu = 0;
     int m = 0, l = 0;
+    int dir_kind = OVD_DIR_MU;
     std::vector<c64> lam;
-    c64* R = nullptr;   // SoA [m][12][Vp] FP64
+    c64* R = nullptr;   // FP64 [m][12][Vp] (padding sites zero)
     c64* L = nullptr;
     c64* dR = nullptr;  // [l][12][Vp]
     c64* dL = nullptr;
+    double* sgn = nullptr;   // device [m]: sgn(Re lambda_i)
+    double* ones = nullptr;  // device [m]: 1
 };
 
 struct ovd_lattice {
@@ -139,6 +143,46 @@ __global__ void left_sum_kernel(Geom g, const cpx<T>* __restrict__ src, cpx<T>* 
         o[i] = t + b;
         o[HALF + i] = b;
     }
+}
+
+// block start vectors from FP64 halves: src_v = (t; b), src_w = (t + b; b) or (t; b)
+template <typename T>
+__global__ void make_block_src_kernel(Geom g, const c64* __restrict__ t64, const c64* __restrict__ b64, long long sh,
+                                      cpx<T>* __restrict__ sv, cpx<T>* __restrict__ sw, long long fsz, int same) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= g.V) return;
+    const size_t HALF = (size_t)12 * g.Vp;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const c64 t = t64[r * sh + (size_t)c * g.Vp + s], b = b64[r * sh + (size_t)c * g.Vp + s];
+        const size_t i = fidx<T>(c, s, g.Vp);
+        sv[r * fsz + i] = cast<T>(t);
+        sv[r * fsz + HALF + i] = cast<T>(b);
+        sw[r * fsz + i] = cast<T>(same ? t : t + b);
+        sw[r * fsz + HALF + i] = cast<T>(b);
+    }
+}
+
+const DeflSet* find_defl(ovd_h h, double mu) {
+    for (const auto& d : h->defl)
+        if (std::fabs(d.mu - mu) <= 1e-12) return &d;
+    return nullptr;
+}
+
+// maximal runs of consecutive right-hand sides that share one deflation set
+struct Run {
+    const DeflSet* set;
+    int r0, n;
+};
+std::vector<Run> defl_runs(ovd_h h, int nrhs, const double* mu) {
+    std::vector<Run> runs;
+    for (int r = 0; r < nrhs; ++r) {
+        const DeflSet* d = find_defl(h, mu[r]);
+        if (!runs.empty() && runs.back().set == d) runs.back().n++;
+        else runs.push_back({d, r, 1});
+    }
+    return runs;
 }
 
 ovd_status check_handle(ovd_h h) {
@@ -285,18 +329,59 @@ ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const voi
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const long long fsz = (long long)12 * g.Vp;
-    WS(src, cpx<T>, "src_v", (size_t)nrhs * fsz);
+    const auto runs = defl_runs(h, nrhs, mu);
+    int mmax = 0;
+    for (const auto& rn : runs)
+        if (rn.set && rn.set->m > mmax) mmax = rn.set->m;
+    WS(b64, c64, "stage_b", (size_t)nrhs * fsz);
     WS(basis, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     WS(cf, c64, "ritz_coef", (size_t)nrhs * k);
     Timer tt;
     tt.start(h->stream);
-    launch_pack_spinor<T>(g, nrhs, b, src, fsz, h->stream);
+    HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * fsz, h->stream));
+    launch_pack_spinor<double>(g, nrhs, b, b64, fsz, h->stream);
+    // eq. 8: c = L^dag b, b' = b - R c, exact part R (sgn(lambda) c)
+    c64* sC = nullptr;
+    if (mmax > 0) {
+        WS(Cm, c64, "defl_C", (size_t)mmax * nrhs);
+        WS(sCm, c64, "defl_sC", (size_t)mmax * nrhs);
+        WS(scr, c64, "defl_scr", defl_proj_scratch(mmax, nrhs, fsz));
+        sC = sCm;
+        for (const auto& rn : runs) {
+            if (!rn.set) continue;
+            const DeflSet& d = *rn.set;
+            c64* bb = b64 + (size_t)rn.r0 * fsz;
+            c64* sc = sC + (size_t)rn.r0 * mmax;
+            launch_defl_proj(d.L, fsz, d.m, bb, fsz, rn.n, fsz, Cm, scr, h->stream);
+            launch_defl_scale(d.m, rn.n, d.ones, Cm, sc, -1.0, h->stream);
+            launch_defl_comb(d.R, fsz, d.m, sc, rn.n, bb, fsz, fsz, h->stream);
+            launch_defl_scale(d.m, rn.n, d.sgn, Cm, sc, 1.0, h->stream);
+        }
+    }
+    const cpx<T>* src;
+    if constexpr (std::is_same<T, double>::value) {
+        src = b64;
+    } else {
+        WS(sv, cpx<T>, "src_v", (size_t)nrhs * fsz);
+        launch_convert_field<T>(g, nrhs, b64, fsz, sv, fsz, h->stream);
+        src = sv;
+    }
+    HIPCHK(hipGetLastError());
     ovd_status s = run_tsl<T>(h, nrhs, k, 0, mu, src, src, nullptr, basis, c, stats);
     if (s != OVD_OK) return s;
     dim3 grid((k + 127) / 128, nrhs);
     make_coef_kernel<<<grid, 128, 0, h->stream>>>(k, h->last_co, c, cf);
     launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, y, h->stream);
+    if (mmax > 0) {
+        HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * fsz, h->stream));
+        for (const auto& rn : runs) {
+            if (!rn.set) continue;
+            c64* bb = b64 + (size_t)rn.r0 * fsz;
+            launch_defl_comb(rn.set->R, fsz, rn.set->m, sC + (size_t)rn.r0 * mmax, rn.n, bb, fsz, fsz, h->stream);
+        }
+        launch_add_soa_to_aos(g, nrhs, b64, fsz, y, h->stream);
+    }
     HIPCHK(hipGetLastError());
     tt.stop(h->stream);
     if (stats) stats->ms_total = tt.ms();
@@ -311,6 +396,15 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
     const long long half = (long long)12 * g.Vp;
     const long long fsz = 2 * half;
     const bool need_vec = (y != nullptr) || (dy != nullptr);
+    const auto runs = defl_runs(h, nrhs, mu);
+    int lmax = 0;
+    for (const auto& rn : runs)
+        if (rn.set && rn.set->l > lmax) lmax = rn.set->l;
+    for (const auto& rn : runs)
+        if (rn.set && rn.set->l > 0 && rn.set->dir_kind != (dirk == 2 ? OVD_DIR_LINK : OVD_DIR_MU))
+            return fail(h, OVD_EINVAL, "deflation set derivatives belong to another direction");
+    WS(b64, c64, "stage_b", (size_t)nrhs * half);
+    WS(t64, c64, "stage_t", (size_t)nrhs * half);
     WS(srcv, cpx<T>, "src_v", (size_t)nrhs * fsz);
     WS(srcw, cpx<T>, "src_w", (size_t)nrhs * fsz);
     cpx<T>* xp = nullptr;
@@ -326,15 +420,42 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     Timer tt;
     tt.start(h->stream);
-    // psi = (0; b)
-    HIPCHK(hipMemsetAsync(srcv, 0, sizeof(cpx<T>) * nrhs * fsz, h->stream));
-    for (int r = 0; r < nrhs; ++r)
-        launch_pack_spinor<T>(g, 1, (const c64*)b + (size_t)r * g.V * 12, srcv + r * fsz + half, fsz, h->stream);
-    if (h->opt.left_start == OVD_LEFT_SAME) {
-        HIPCHK(hipMemcpyAsync(srcw, srcv, sizeof(cpx<T>) * nrhs * fsz, hipMemcpyDeviceToDevice, h->stream));
-    } else {
+    // psi = (0; b), deflated by eq. 11: psi' = psi - P_{2l} psi = (-(R d + dR c); b - R c)
+    // with c = L^dag b, d = dL^dag b over the first l pairs
+    HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * half, h->stream));
+    HIPCHK(hipMemsetAsync(t64, 0, sizeof(c64) * nrhs * half, h->stream));
+    launch_pack_spinor<double>(g, nrhs, b, b64, half, h->stream);
+    c64 *sC = nullptr, *sD = nullptr;
+    if (lmax > 0) {
+        WS(Cm, c64, "defl_C", (size_t)lmax * nrhs);
+        WS(Dm, c64, "defl_D", (size_t)lmax * nrhs);
+        WS(tmp, c64, "defl_tmp", (size_t)lmax * nrhs);
+        WS(sCm, c64, "defl_sC", (size_t)lmax * nrhs);
+        WS(sDm, c64, "defl_sD", (size_t)lmax * nrhs);
+        WS(scr, c64, "defl_scr", defl_proj_scratch(lmax, nrhs, half));
+        sC = sCm;
+        sD = sDm;
+        for (const auto& rn : runs) {
+            if (!rn.set || rn.set->l == 0) continue;
+            const DeflSet& d = *rn.set;
+            const int l = d.l;
+            c64* bb = b64 + (size_t)rn.r0 * half;
+            c64* tb = t64 + (size_t)rn.r0 * half;
+            launch_defl_proj(d.L, half, l, bb, half, rn.n, half, Cm, scr, h->stream);
+            launch_defl_proj(d.dL, half, l, bb, half, rn.n, half, Dm, scr, h->stream);
+            launch_defl_scale(l, rn.n, d.ones, Cm, tmp, -1.0, h->stream);
+            launch_defl_comb(d.dR, half, l, tmp, rn.n, tb, half, half, h->stream);   // t -= dR c
+            launch_defl_comb(d.R, half, l, tmp, rn.n, bb, half, half, h->stream);    // b -= R c
+            launch_defl_scale(l, rn.n, d.ones, Dm, tmp, -1.0, h->stream);
+            launch_defl_comb(d.R, half, l, tmp, rn.n, tb, half, half, h->stream);    // t -= R d
+            launch_defl_scale(l, rn.n, d.sgn, Cm, sC + (size_t)rn.r0 * lmax, 1.0, h->stream);
+            launch_defl_scale(l, rn.n, d.sgn, Dm, sD + (size_t)rn.r0 * lmax, 1.0, h->stream);
+        }
+    }
+    {
         dim3 grid((g.V + 255) / 256, nrhs);
-        left_sum_kernel<T><<<grid, 256, 0, h->stream>>>(g, srcv, srcw, fsz);
+        make_block_src_kernel<T><<<grid, 256, 0, h->stream>>>(g, t64, b64, half, srcv, srcw, fsz,
+                                                              h->opt.left_start == OVD_LEFT_SAME);
     }
     if (xp) launch_pack_spinor<T>(g, nrhs, x, xp, half, h->stream);
     HIPCHK(hipGetLastError());
@@ -346,10 +467,44 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
         make_coef_kernel<<<grid, 128, 0, h->stream>>>(k, h->last_co, c, cf);
         if (dy) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, dy, h->stream);
         if (y) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 1, cf, k, y, h->stream);
+        if (lmax > 0) {
+            // exact part: top R (s d) + dR (s c), bottom R (s c)
+            HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * half, h->stream));
+            HIPCHK(hipMemsetAsync(t64, 0, sizeof(c64) * nrhs * half, h->stream));
+            for (const auto& rn : runs) {
+                if (!rn.set || rn.set->l == 0) continue;
+                const DeflSet& d = *rn.set;
+                c64* bb = b64 + (size_t)rn.r0 * half;
+                c64* tb = t64 + (size_t)rn.r0 * half;
+                launch_defl_comb(d.R, half, d.l, sD + (size_t)rn.r0 * lmax, rn.n, tb, half, half, h->stream);
+                launch_defl_comb(d.dR, half, d.l, sC + (size_t)rn.r0 * lmax, rn.n, tb, half, half, h->stream);
+                launch_defl_comb(d.R, half, d.l, sC + (size_t)rn.r0 * lmax, rn.n, bb, half, half, h->stream);
+            }
+            if (dy) launch_add_soa_to_aos(g, nrhs, t64, half, dy, h->stream);
+            if (y) launch_add_soa_to_aos(g, nrhs, b64, half, y, h->stream);
+        }
     }
     if (xdy) {
         WS(outd, c64, "scalar_out", nrhs);
         launch_scalar_dot(nrhs, k, c, h->last_co.proj, k, h->last_co.delta, outd, h->stream);
+        if (lmax > 0) {
+            // <x| R (s d) + dR (s c)> = sum_i conj(R_i^dag x) s_i d_i + conj(dR_i^dag x) s_i c_i
+            WS(x64, c64, "stage_x", (size_t)nrhs * half);
+            WS(P1, c64, "defl_P1", (size_t)lmax * nrhs);
+            WS(P2, c64, "defl_P2", (size_t)lmax * nrhs);
+            WS(scr, c64, "defl_scr", defl_proj_scratch(lmax, nrhs, half));
+            HIPCHK(hipMemsetAsync(x64, 0, sizeof(c64) * nrhs * half, h->stream));
+            launch_pack_spinor<double>(g, nrhs, x, x64, half, h->stream);
+            for (const auto& rn : runs) {
+                if (!rn.set || rn.set->l == 0) continue;
+                const DeflSet& d = *rn.set;
+                const c64* xb = x64 + (size_t)rn.r0 * half;
+                launch_defl_proj(d.R, half, d.l, xb, half, rn.n, half, P1, scr, h->stream);
+                launch_defl_proj(d.dR, half, d.l, xb, half, rn.n, half, P2, scr, h->stream);
+                launch_defl_scalar(d.l, rn.n, P1, sD + (size_t)rn.r0 * lmax, P2, sC + (size_t)rn.r0 * lmax,
+                                   outd + rn.r0, h->stream);
+            }
+        }
         HIPCHK(hipMemcpyAsync(xdy, outd, sizeof(c64) * nrhs, hipMemcpyDeviceToHost, h->stream));
     }
     HIPCHK(hipGetLastError());
@@ -426,12 +581,7 @@ ovd_status ovd_destroy(ovd_h h) {
     for (auto e : h->ev) (void)hipEventDestroy(e);
     if (h->U64) (void)hipFree(h->U64);
     if (h->U32) (void)hipFree(h->U32);
-    for (auto& d : h->defl) {
-        (void)hipFree(d.R);
-        (void)hipFree(d.L);
-        if (d.dR) (void)hipFree(d.dR);
-        if (d.dL) (void)hipFree(d.dL);
-    }
+    ovd_clear_deflation(h);
     delete h;
     return OVD_OK;
 }
@@ -537,12 +687,102 @@ ovd_status ovd_get_tridiag(ovd_h h, int rhs, int k, double* alpha, double* beta,
 
 ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const void* R, const void* L, int l,
                              const void* dR, const void* dL, const ovd_dir* dir) {
-    (void)mu; (void)m; (void)lam; (void)R; (void)L; (void)l; (void)dR; (void)dL; (void)dir;
-    return fail(h, OVD_EINVAL, "deflation is not available in this build");
+    if (!h) return OVD_EINVAL;
+    if (m < 1 || !lam || !R || !L || l < 0 || l > m || (l > 0 && (!dR || !dL)))
+        return fail(h, OVD_EINVAL, "bad ovd_set_deflation arguments");
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    const long long nf = (long long)12 * g.Vp;
+    DeflSet d;
+    d.mu = mu;
+    d.m = m;
+    d.l = l;
+    d.dir_kind = (dir && dir->kind == OVD_DIR_LINK) ? OVD_DIR_LINK : OVD_DIR_MU;
+    d.lam.resize(m);
+    std::vector<double> sg(m), on(m, 1.0);
+    for (int i = 0; i < m; ++i) {
+        d.lam[i] = c64{lam[2 * i], lam[2 * i + 1]};
+        sg[i] = lam[2 * i] >= 0.0 ? 1.0 : -1.0;   // sgn(Re lambda)
+    }
+    auto alloc = [&](c64** p, int n) -> hipError_t {
+        hipError_t e = hipMalloc(p, sizeof(c64) * (size_t)n * nf);
+        if (e == hipSuccess) e = hipMemsetAsync(*p, 0, sizeof(c64) * (size_t)n * nf, h->stream);
+        return e;
+    };
+    auto release = [&]() {
+        if (d.R) (void)hipFree(d.R);
+        if (d.L) (void)hipFree(d.L);
+        if (d.dR) (void)hipFree(d.dR);
+        if (d.dL) (void)hipFree(d.dL);
+        if (d.sgn) (void)hipFree(d.sgn);
+        if (d.ones) (void)hipFree(d.ones);
+    };
+    if (alloc(&d.R, m) != hipSuccess || alloc(&d.L, m) != hipSuccess ||
+        (l > 0 && (alloc(&d.dR, l) != hipSuccess || alloc(&d.dL, l) != hipSuccess)) ||
+        hipMalloc(&d.sgn, sizeof(double) * m) != hipSuccess || hipMalloc(&d.ones, sizeof(double) * m) != hipSuccess) {
+        release();
+        return fail(h, OVD_ENOMEM, "device allocation of the deflation set failed");
+    }
+    launch_pack_spinor<double>(g, m, R, d.R, nf, h->stream);
+    launch_pack_spinor<double>(g, m, L, d.L, nf, h->stream);
+    if (l > 0) {
+        launch_pack_spinor<double>(g, l, dR, d.dR, nf, h->stream);
+        launch_pack_spinor<double>(g, l, dL, d.dL, nf, h->stream);
+    }
+    (void)hipMemcpyAsync(d.sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->stream);
+    (void)hipMemcpyAsync(d.ones, on.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->stream);
+    // biorthonormality L^dag R = 1 (checked on the device, FP64)
+    c64* G = (c64*)ws_get(h, "defl_gram", sizeof(c64) * (size_t)m * m, &wst);
+    c64* scr = (c64*)ws_get(h, "defl_scr", sizeof(c64) * defl_proj_scratch(m, m, nf), &wst);
+    if (!G || !scr) {
+        release();
+        return wst;
+    }
+    launch_defl_proj(d.L, nf, m, d.R, nf, m, nf, G, scr, h->stream);
+    std::vector<c64> hg((size_t)m * m);
+    if (hipMemcpyAsync(hg.data(), G, sizeof(c64) * m * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        release();
+        return fail(h, OVD_EHIP, "deflation set upload failed");
+    }
+    double dev = 0.0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            const c64 e = hg[(size_t)i * m + j] - c64{i == j ? 1.0 : 0.0, 0.0};
+            dev = std::max(dev, std::sqrt(norm2(e)));
+        }
+    if (!(dev <= 1e-8)) {
+        release();
+        return fail(h, OVD_EINVAL, "deflation vectors are not biorthonormal: max |L^dag R - 1| = " + std::to_string(dev));
+    }
+    for (auto it = h->defl.begin(); it != h->defl.end(); ++it) {
+        if (std::fabs(it->mu - mu) <= 1e-12) {
+            (void)hipFree(it->R);
+            (void)hipFree(it->L);
+            if (it->dR) (void)hipFree(it->dR);
+            if (it->dL) (void)hipFree(it->dL);
+            (void)hipFree(it->sgn);
+            (void)hipFree(it->ones);
+            h->defl.erase(it);
+            break;
+        }
+    }
+    h->defl.push_back(d);
+    return OVD_OK;
 }
 
 ovd_status ovd_clear_deflation(ovd_h h) {
     if (!h) return OVD_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& d : h->defl) {
+        (void)hipFree(d.R);
+        (void)hipFree(d.L);
+        if (d.dR) (void)hipFree(d.dR);
+        if (d.dL) (void)hipFree(d.dL);
+        (void)hipFree(d.sgn);
+        (void)hipFree(d.ones);
+    }
+    h->defl.clear();
     return OVD_OK;
 }
 

@@ -162,4 +162,21 @@ void launch_reconstruct(const Geom& g, int nrhs, int k, const cpx<T>* basis, lon
 void launch_scalar_dot(int nrhs, int k, const c64* c, const c64* proj, int ld,
                        const c64* scale, c64* out, hipStream_t s);
 
+// deflation products (kernels_defl.hip), FP64 fields flattened to nf = 12 Vp
+// complex: C (m x nr, row-major) = A^dag B;  Y += A C
+size_t defl_proj_scratch(int m, int nr, long long nf);
+void launch_defl_proj(const c64* A, long long sA, int m, const c64* B, long long sB, int nr, long long nf,
+                      c64* C, c64* scratch, hipStream_t s);
+void launch_defl_comb(const c64* A, long long sA, int m, const c64* C, int nr, c64* Y, long long sY, long long nf,
+                      hipStream_t s);
+// out[i][r] = sign * f[i] * in[i][r]
+void launch_defl_scale(int m, int nr, const double* f, const c64* in, c64* out, double sign, hipStream_t s);
+// out[r] += sum_i conj(P1[i][r]) sD[i][r] + conj(P2[i][r]) sC[i][r]
+void launch_defl_scalar(int l, int nr, const c64* P1, const c64* sD, const c64* P2, const c64* sC, c64* out,
+                        hipStream_t s);
+void launch_add_soa_to_aos(const Geom& g, int n, const c64* in, long long stride, void* out_aos, hipStream_t s);
+template <typename T>
+void launch_convert_field(const Geom& g, int n, const c64* in, long long sin, cpx<T>* out, long long sout,
+                          hipStream_t s);
+
 }  // namespace ovd

@@ -241,6 +241,29 @@ class Lattice:
             s = [complex(xdy[2 * i], xdy[2 * i + 1]) for i in range(n)]
         return y, dy, s
 
+    def set_deflation(self, mu, lam, R, L, l=0, dR=None, dL=None, direction="mu", dU=None):
+        """Deflation set for one mu (eq. 8 with the m pairs, eq. 11 with the first l).
+
+        lam: m complex eigenvalues (closest to zero first); R, L: [m, V, 4, 3]
+        right / left eigenvectors with L^dag R = 1; dR, dL: [l, V, 4, 3]
+        derivatives of the first l along `direction`."""
+        m = len(lam)
+        _check_field(R, (m, self.V, 4, 3), "R")
+        _check_field(L, (m, self.V, 4, 3), "L")
+        if l > 0:
+            _check_field(dR, (l, self.V, 4, 3), "dR")
+            _check_field(dL, (l, self.V, 4, 3), "dL")
+        lam_c = (ctypes.c_double * (2 * m))()
+        for i, z in enumerate(lam):
+            lam_c[2 * i] = float(complex(z).real)
+            lam_c[2 * i + 1] = float(complex(z).imag)
+        d = _Dir(DIR_LINK if direction in ("link", DIR_LINK) else DIR_MU, None)
+        self._call("ovd_set_deflation", float(mu), m, lam_c, _ptr(R), _ptr(L), int(l),
+                   _ptr(dR) if l > 0 else None, _ptr(dL) if l > 0 else None, ctypes.byref(d))
+
+    def clear_deflation(self):
+        self._call("ovd_clear_deflation")
+
     def get_tridiag(self, k, rhs=0):
         """(alpha, beta, delta) of the last Lanczos run as lists of complex."""
         a = (ctypes.c_double * (2 * k))()
