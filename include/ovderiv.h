@@ -159,16 +159,22 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
                                 const void* x, double* xdy, ovd_stats* st);
 
 /* Gradient of s = <x|sgn(H(mu))|b> (the bilinear the paper's currents and
- * fermionic force are built from, Sec. 1): two-sided Lanczos with right start
- * b and left start x, s ~ (x^dag b)[sgn(T_k)]_11, and with
- * M_k = L_sgn(T_k, e_1 e_1^T) the derivative ds/dt ~ (x^dag b) tr(M_k W_k^dag dH V_k).
+ * fermionic force are built from, Sec. 1), FP64 whatever the handle's
+ * precision: two-sided Lanczos with right start b and left start x,
+ * s ~ (x^dag b)[sgn(T_k)]_11, and with M_k = L_sgn(T_k, e_1 e_1^T) the
+ * derivative ds/dt ~ (x^dag b) tr(M_k W_k^dag (dH/dt) V_k), evaluated for every
+ * link at once through Z = W_k M_k^dag.  Deflation is not applied.
  *   x, b      device complex128 [V][4][3]
  *   s, ds_dmu host complex128 [1], nullable
  *   F         device complex128 [4][V][3][3] or NULL: per-link force with
  *             ds/dt = tr(F_nu(y) X) for U_nu(y) -> exp(tX) U_nu(y)
- * Deflation is not applied. */
+ *   dsdU, dsdUc  device complex128 [4][V][3][3] or NULL: Wirtinger derivatives
+ *             ds/dU_nu(y)[a][b] and ds/dconj(U_nu(y)[a][b]) with the links taken
+ *             as unconstrained complex matrices (for automatic differentiation)
+ * The Krylov bases V_k, W_k are stored (2 k 12 V complex128 of workspace). */
 ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b,
-                              double* s, double* ds_dmu, void* F, ovd_stats* st);
+                              double* s, double* ds_dmu, void* F, void* dsdU, void* dsdUc,
+                              ovd_stats* st);
 
 /* Lanczos coefficients of the last Lanczos run (for parity checks), right-hand
  * side rhs: host complex128 arrays alpha[k], beta[k], delta[k].  T_k has

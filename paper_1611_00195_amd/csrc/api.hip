@@ -197,7 +197,8 @@ ovd_status check_handle(ovd_h h) {
 //   basis: if non-null, V-hat_1..V-hat_k are kept there ([rhs][k][fsz]).
 template <typename T>
 ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cpx<T>* src_v,
-                   const cpx<T>* src_w, const cpx<T>* xproj, cpx<T>* basis, c64* c_out, ovd_stats* stats) {
+                   const cpx<T>* src_w, const cpx<T>* xproj, cpx<T>* basis, c64* c_out, ovd_stats* stats,
+                   cpx<T>* basis_w = nullptr) {
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const int halves = dir == 0 ? 1 : 2;
@@ -229,9 +230,10 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     auto slot = [&](int base, int i) { return ring + (size_t)(base + i) * nrhs * fsz; };
     auto Vs = [&](int i) -> cpx<T>* { return basis ? basis + (size_t)(i - 1) * fsz : slot(0, i % 3); };
     auto Us = [&](int i) -> cpx<T>* { return slot(3, i % 2); };
-    auto Ws = [&](int i) -> cpx<T>* { return slot(5, i % 3); };
+    auto Ws = [&](int i) -> cpx<T>* { return basis_w ? basis_w + (size_t)(i - 1) * fsz : slot(5, i % 3); };
     auto Zs = [&](int i) -> cpx<T>* { return slot(8, i % 2); };
     const long long sV = basis ? (long long)k * fsz : fsz;
+    const long long sW = basis_w ? (long long)k * fsz : fsz;
 
     Timer tl, ts;
     // per-kernel events: 4 per step (update start/end, stencil start/end)
@@ -246,7 +248,8 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     // start vectors into slot 1
     HIPCHK(hipMemcpy2DAsync(Vs(1), sizeof(cpx<T>) * sV, src_v, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
                             hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(Ws(1), src_w, sizeof(cpx<T>) * nrhs * fsz, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(Ws(1), sizeof(cpx<T>) * sW, src_w, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
+                            hipMemcpyDeviceToDevice, h->stream));
     for (int j = 0; j < k; ++j) {
         StepPtrs p{};
         if (j > 0) {
@@ -254,12 +257,12 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             p.Yv = Vs(j); p.sYv = sV;
             p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
             p.Xw = Zs(j); p.sXw = fsz;
-            p.Yw = Ws(j); p.sYw = fsz;
-            p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = fsz;
+            p.Yw = Ws(j); p.sYw = sW;
+            p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = sW;
         }
         p.outV = Vs(j + 1); p.sV = sV;
         p.outU = Us(j + 1); p.sU = fsz;
-        p.outW = Ws(j + 1); p.sW = fsz;
+        p.outW = Ws(j + 1); p.sW = sW;
         p.outZ = Zs(j + 1); p.sZ = fsz;
         p.xproj = xproj;
         p.sx = (long long)12 * g.Vp;
@@ -786,10 +789,71 @@ ovd_status ovd_clear_deflation(ovd_h h) {
     return OVD_OK;
 }
 
-ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b, double* s, double* ds_dmu,
-                              void* F, ovd_stats* st) {
-    (void)mu; (void)k; (void)x; (void)b; (void)s; (void)ds_dmu; (void)F; (void)st;
-    return fail(h, OVD_EINVAL, "vjp is not available in this build");
+ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b, double* s_out,
+                              double* ds_dmu, void* F, void* dsdU, void* dsdUc, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (k < 1 || !x || !b) return fail(h, OVD_EINVAL, "bad ovd_sign_apply_vjp arguments");
+    if (st) std::memset(st, 0, sizeof(*st));
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    const long long fsz = (long long)12 * g.Vp;
+    // bilinear two-sided Lanczos in FP64: right start b, left start x, both bases kept
+    WS(srcv, c64, "vjp_src_v", fsz);
+    WS(srcw, c64, "vjp_src_w", fsz);
+    WS(bv, c64, "vjp_basis_v", (size_t)k * fsz);
+    WS(bw, c64, "vjp_basis_w", (size_t)k * fsz);
+    WS(c, c64, "ritz_c", k);
+    HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c64) * fsz, h->stream));
+    HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c64) * fsz, h->stream));
+    launch_pack_spinor<double>(g, 1, b, srcv, fsz, h->stream);
+    launch_pack_spinor<double>(g, 1, x, srcw, fsz, h->stream);
+    Timer tt;
+    tt.start(h->stream);
+    const double mus[1] = {mu};
+    s = run_tsl<double>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv, c, st, bw);
+    if (s != OVD_OK) return s;
+    const TslCoeffs co = h->last_co;
+    // s = (x^dag b) [sgn(T_k)]_11, x^dag b = beta_0 delta_0
+    c64 c0, b0, d0;
+    HIPCHK(hipMemcpyAsync(&c0, c, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&b0, co.beta, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&d0, co.delta, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const c64 xb = b0 * d0;
+    if (s_out) {
+        const c64 sv = xb * c0;
+        s_out[0] = sv.re;
+        s_out[1] = sv.im;
+    }
+    if (ds_dmu || F || dsdU || dsdUc) {
+        // M = L_sgn(T_k, e_1 e_1^T), M' = (x^dag b) M / (delta_p beta_q), Z = W-hat M'^dag
+        WS(scr, c64, "frechet_scr", small_frechet_scratch_elems(k));
+        WS(M, c64, "vjp_M", (size_t)k * k);
+        WS(Mp, c64, "vjp_Mp", (size_t)k * k);
+        WS(Z, c64, "vjp_Z", (size_t)k * fsz);
+        WS(trF, c64, "vjp_trF", g.V);
+        WS(dsum, c64, "vjp_dsum", 1);
+        double chk = 0.0;
+        launch_small_frechet(k, co, h->opt.quad_step, scr, M, &chk, h->stream);
+        launch_vjp_scale_m(k, co, M, Mp, h->stream);
+        launch_zgemm_wmh(bw, fsz, k, Mp, Z, fsz, fsz, h->stream);
+        launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
+                         h->stream);
+        launch_sum_c64(g.V, trF, dsum, h->stream);
+        c64 dm;
+        HIPCHK(hipMemcpyAsync(&dm, dsum, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (ds_dmu) {
+            ds_dmu[0] = dm.re;
+            ds_dmu[1] = dm.im;
+        }
+        if (st) st->sign_check = std::max(st->sign_check, chk);
+    }
+    tt.stop(h->stream);
+    if (st) st->ms_total = tt.ms();
+    return OVD_OK;
 }
 
 }  // extern "C"

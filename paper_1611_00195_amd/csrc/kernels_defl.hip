@@ -199,3 +199,73 @@ template void launch_convert_field<double>(const Geom&, int, const c64*, long lo
 template void launch_convert_field<float>(const Geom&, int, const c64*, long long, c32*, long long, hipStream_t);
 
 }  // namespace ovd
+
+namespace ovd {
+
+// ---------------------------------------------------------------------------
+// Z = W Mc, Mc[q][p] = conj(Mp[p][q])  (the N x k x k product of the gradient:
+// z_p = sum_q w_q conj(M'[p][q])).  W and Z are k fields of nf complex
+// (field q at q sW).  One wave per 16 rows x 64 columns, reduction over q in
+// steps of 4 on the matrix cores; Mp (k x k, row-major) stays in L2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void zgemm_wmh_kernel(const c64* __restrict__ W, long long sW, int k,
+                                                       const c64* __restrict__ Mp, c64* __restrict__ Z,
+                                                       long long sZ, long long nf) {
+    const int l = threadIdx.x;
+    const long long n0 = (long long)blockIdx.x * 16;
+    const int p0 = blockIdx.y * 64;
+    const long long na = n0 + (l & 15);
+    const int kk = l >> 4;
+    v4d re[4], im[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        re[t] = v4d{0, 0, 0, 0};
+        im[t] = v4d{0, 0, 0, 0};
+    }
+    for (int q = 0; q < k; q += 4) {
+        const int qk = q + kk;
+        c64 a{0.0, 0.0};
+        if (qk < k && na < nf) a = W[(size_t)qk * sW + na];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int pb = p0 + 16 * t + (l & 15);
+            c64 b{0.0, 0.0};
+            if (qk < k && pb < k) b = conj(Mp[(size_t)pb * k + qk]);
+            re[t] = mfma(a.re, b.re, re[t]);
+            re[t] = mfma(-a.im, b.im, re[t]);
+            im[t] = mfma(a.re, b.im, im[t]);
+            im[t] = mfma(a.im, b.re, im[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int pp = p0 + 16 * t + (l & 15);
+        if (pp >= k) continue;
+        for (int v = 0; v < 4; ++v) {
+            const long long nn = n0 + 4 * v + (l >> 4);
+            if (nn < nf) Z[(size_t)pp * sZ + nn] = c64{re[t][v], im[t][v]};
+        }
+    }
+}
+
+void launch_zgemm_wmh(const c64* W, long long sW, int k, const c64* Mp, c64* Z, long long sZ, long long nf,
+                      hipStream_t s) {
+    dim3 grid((unsigned)((nf + 15) / 16), (k + 63) / 64);
+    zgemm_wmh_kernel<<<grid, 64, 0, s>>>(W, sW, k, Mp, Z, sZ, nf);
+}
+
+// M'[p][q] = xb M[p][q] / (delta_p beta_q), xb = beta_0 delta_0 = x^dag b
+__global__ void vjp_scale_m_kernel(int k, TslCoeffs co, const c64* __restrict__ M, c64* __restrict__ Mp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k * k) return;
+    const int p = t / k, q = t % k;
+    const c64 xb = co.beta[0] * co.delta[0];
+    const c64 den = co.delta[p] * co.beta[q];
+    Mp[t] = cdiv(xb * M[t], den);
+}
+
+void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t s) {
+    vjp_scale_m_kernel<<<(k * k + 255) / 256, 256, 0, s>>>(k, co, M, Mp);
+}
+
+}  // namespace ovd

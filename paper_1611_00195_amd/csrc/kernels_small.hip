@@ -73,7 +73,7 @@ __global__ void small_sign_setup_kernel(int nrhs, int k, TslCoeffs co, double* _
 __global__ __launch_bounds__(64) void small_sign_solve_kernel(int nrhs, int k, TslCoeffs co,
                                                               const double* __restrict__ smin, double h,
                                                               double off, int q0, int nq,
-                                                              c64* __restrict__ scr, int transpose) {
+                                                              c64* __restrict__ scr, int transpose, int scale) {
     const int nsol = nrhs * 2 * nq;
     const int sol = blockIdx.x * blockDim.x + threadIdx.x;
     if (sol >= nsol) return;
@@ -112,13 +112,14 @@ __global__ __launch_bounds__(64) void small_sign_solve_kernel(int nrhs, int k, T
         }
     }
     if (cabs1(cd) == 0.0) cd = c64{1e-300, 0.0};
-    // back substitution, scaled by the node weight e^s
+    // back substitution, scaled by the node weight e^s when asked
+    const double wgt = scale ? y : 1.0;
     c64 x1 = cdiv(cb, cd);
-    AT(B, k - 1) = y * x1;
+    AT(B, k - 1) = wgt * x1;
     c64 x2{0.0, 0.0};
     for (int i = k - 2; i >= 0; --i) {
         const c64 xi = cdiv(AT(B, i) - AT(DU, i) * x1 - AT(DU2, i) * x2, AT(D, i));
-        AT(B, i) = y * xi;
+        AT(B, i) = wgt * xi;
         x2 = x1;
         x1 = xi;
     }
@@ -215,7 +216,7 @@ void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scr
         for (int q0 = 0; q0 < nq; q0 += chunk) {
             const int n = (nq - q0) < chunk ? (nq - q0) : chunk;
             const int nsol = nrhs * 2 * n;
-            small_sign_solve_kernel<<<(nsol + 63) / 64, 64, 0, s>>>(nrhs, k, co, smin, sp, off, q0, n, scr, 0);
+            small_sign_solve_kernel<<<(nsol + 63) / 64, 64, 0, s>>>(nrhs, k, co, smin, sp, off, q0, n, scr, 0, 1);
             dim3 g((k + 127) / 128, nrhs);
             small_sign_accum_kernel<<<g, 128, 0, s>>>(nrhs, k, n, scr, acc);
         }
@@ -229,6 +230,145 @@ void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scr
         last = 0.0;
         for (double d : hd) last = d > last ? d : last;
         if (last <= tol) break;
+    }
+    if (check) *check = last;
+}
+
+
+// ===========================================================================
+// Frechet derivative M = L_sgn(T, e_1 e_1^T) for the gradient of
+// <x|sgn(H)|b>, by differentiating the same integral:
+//   M = -(1/pi) int_0^inf [(T + iy)^{-1} E (T + iy)^{-1} + (T - iy)^{-1} E (T - iy)^{-1}] dy,
+//   E = e_1 e_1^T,  (T + iy)^{-1} E (T + iy)^{-1} = x x~^T with
+//   x = (T + iy)^{-1} e_1,  x~ = (T^T + iy)^{-1} e_1,
+// on the same nodes and with the same level-by-level refinement as the sign;
+// the tail beyond the last node is w1 E - w3 (E T^2 + T E T + T^2 E).
+// The node sum  sum_q e^{s_q} x_q x~_q^T  is a complex (k x S)(S x k) product,
+// accumulated on the matrix cores.
+// ===========================================================================
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Msum[i][j] += sum_sol XA[i][sol] XB[j][sol]  (k x k, XA/XB laid out [row][sol], nsol solves)
+__global__ __launch_bounds__(64) void frechet_accum_kernel(int k, int nsol, const c64* __restrict__ XA,
+                                                           const c64* __restrict__ XB, c64* __restrict__ M) {
+    const int l = threadIdx.x;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+    const int ia = i0 + (l & 15), jb = j0 + (l & 15), kk = l >> 4;
+    const bool va = ia < k, vb = jb < k;
+    v4d re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+    for (int s = 0; s < nsol; s += 4) {
+        const int sl = s + kk;
+        c64 a{0.0, 0.0}, b{0.0, 0.0};
+        if (va && sl < nsol) a = XA[(size_t)ia * nsol + sl];
+        if (vb && sl < nsol) b = XB[(size_t)jb * nsol + sl];
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, im, 0, 0, 0);
+    }
+    const int jj = j0 + (l & 15);
+    for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + 4 * v + (l >> 4);
+        if (ii < k && jj < k) M[(size_t)ii * k + jj] = M[(size_t)ii * k + jj] + c64{re[v], im[v]};
+    }
+}
+
+// Mout = -(h/pi) Msum + tail; diff = max |Mout - Mprev|; Mprev <- Mout   (one block)
+__global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __restrict__ smin, double h, int qlast,
+                                        const c64* __restrict__ Msum, c64* __restrict__ Mout,
+                                        c64* __restrict__ Mprev, double* __restrict__ diff) {
+    __shared__ double red[256];
+    __shared__ c64 T2[3][3], Tm[3][3];
+    __shared__ double w1s, w3s;
+    const int r = 0;
+    if (threadIdx.x == 0) {
+        const double sL = smin[r] + qlast * h;
+        const double E = exp(-h);
+        w1s = (2.0 / M_PI) * h * exp(-sL) * E / (1.0 - E);
+        w3s = (2.0 / M_PI) * h * exp(-3.0 * sL) * E * E * E / (1.0 - E * E * E);
+        auto T = [&](int a, int b) -> c64 {
+            if (a >= k || b >= k) return c64{0.0, 0.0};
+            if (a == b) return tdiag(co, r, a);
+            if (b == a + 1) return tsup(co, r, a);
+            if (a == b + 1) return tsub(co, r, b);
+            return c64{0.0, 0.0};
+        };
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                Tm[a][b] = T(a, b);
+                c64 s{0.0, 0.0};
+                for (int c = 0; c < 4; ++c) s += T(a, c) * T(c, b);
+                T2[a][b] = s;
+            }
+    }
+    __syncthreads();
+    double dmax = 0.0;
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+        const int i = t / k, j = t % k;
+        c64 m = (-h / M_PI) * Msum[t];
+        // tail: w1 E - w3 (E T^2 + T E T + T^2 E), E = e_1 e_1^T
+        if (i == 0 && j == 0) m += c64{w1s, 0.0};
+        c64 t3{0.0, 0.0};
+        if (i == 0 && j < 3) t3 += T2[0][j];
+        if (i < 2 && j < 2) t3 += Tm[i][0] * Tm[0][j];
+        if (j == 0 && i < 3) t3 += T2[i][0];
+        m -= w3s * t3;
+        const c64 d = m - Mprev[t];
+        const double ad = sqrt(norm2(d));
+        dmax = ad > dmax ? ad : dmax;
+        Mprev[t] = m;
+        Mout[t] = m;
+    }
+    red[threadIdx.x] = dmax;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + s] ? red[threadIdx.x] : red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) diff[0] = red[0];
+}
+
+size_t small_frechet_scratch_elems(int k) {
+    return 2 * (4 * (size_t)k * kChunkSolves) + 3 * (size_t)k * k + 4;
+}
+
+// M (k x k, row-major) = L_sgn(T, e_1 e_1^T) for one tridiagonal (rhs 0 of co)
+void launch_small_frechet(int k, TslCoeffs co, double quad_step, c64* scratch, c64* M_out, double* check,
+                          hipStream_t s) {
+    c64* scrA = scratch;
+    c64* scrB = scrA + 4 * (size_t)k * kChunkSolves;
+    c64* Msum = scrB + 4 * (size_t)k * kChunkSolves;
+    c64* Mprev = Msum + (size_t)k * k;
+    double* smin = (double*)(Mprev + (size_t)k * k);
+    double* diff = smin + 2;
+    (void)hipMemsetAsync(Msum, 0, sizeof(c64) * 2 * k * k, s);
+    small_sign_setup_kernel<<<1, 64, 0, s>>>(1, k, co, smin);
+    const double h0 = 2.0 * quad_step;
+    const int Q0 = (int)ceil((kLowSpan + kHighSpan) / h0) + 1;
+    const int chunk = kChunkSolves / 2;
+    double hd = 0.0, last = 0.0;
+    for (int lev = 0; lev <= kMaxLevels; ++lev) {
+        const double sp = lev == 0 ? h0 : h0 / (double)(1 << (lev - 1));
+        const double off = lev == 0 ? 0.0 : 0.5;
+        const int nq = lev == 0 ? Q0 : (Q0 - 1) * (1 << (lev - 1));
+        for (int q0 = 0; q0 < nq; q0 += chunk) {
+            const int n = (nq - q0) < chunk ? (nq - q0) : chunk;
+            const int nsol = 2 * n;
+            // scaled solves with T (weight e^s folded in), unscaled with T^T
+            small_sign_solve_kernel<<<(nsol + 63) / 64, 64, 0, s>>>(1, k, co, smin, sp, off, q0, n, scrA, 0, 1);
+            small_sign_solve_kernel<<<(nsol + 63) / 64, 64, 0, s>>>(1, k, co, smin, sp, off, q0, n, scrB, 1, 0);
+            dim3 g((k + 15) / 16, (k + 15) / 16);
+            frechet_accum_kernel<<<g, 64, 0, s>>>(k, nsol, scrA + (size_t)3 * k * nsol, scrB + (size_t)3 * k * nsol,
+                                                  Msum);
+        }
+        const double hl = h0 / (double)(1 << lev);
+        const int qlast = (Q0 - 1) * (1 << lev);
+        frechet_finalize_kernel<<<1, 256, 0, s>>>(k, co, smin, hl, qlast, Msum, M_out, Mprev, diff);
+        if (lev == 0) continue;
+        (void)hipMemcpyAsync(&hd, diff, sizeof(double), hipMemcpyDeviceToHost, s);
+        (void)hipStreamSynchronize(s);
+        last = hd;
+        if (last <= 1e-10) break;
     }
     if (check) *check = last;
 }

@@ -583,4 +583,109 @@ OVD_INST(double)
 OVD_INST(float)
 #undef OVD_INST
 
+// ---------------------------------------------------------------------------
+// Link force of s = <x|sgn(H)|b> from K = sum_p v_p z_p^dag (vhat_p, z_p from the
+// two-sided Lanczos basis and Z = W M'^dag).  For link U_nu(y) with forward
+// hop y -> y + nu:
+//   Kf[b][a] = sum_p sum_{s,t} (gamma5 (1 - gamma_nu))_{st} v_p(y+nu)[t][b] conj(z_p(y)[s][a])
+//   Kb[b][a] = sum_p sum_{s,t} (gamma5 (1 + gamma_nu))_{st} v_p(y)[t][b] conj(z_p(y+nu)[s][a])
+//   ds/dU[a][b] = -1/2 cf sgn Kf[b][a],   ds/dconj(U)[a][b] = -1/2 cb sgn Kb[a][b],
+//   F = -1/2 cf sgn U Kf + 1/2 cb sgn Kb U^dag  (ds/dt = tr(F X) for U -> e^{tX} U),
+// cf = e^{mu}, cb = e^{-mu} on time links (1 in space), sgn the boundary
+// factor of the hop.  One thread per (site, direction), direction fastest.
+// trF[y] = tr F_t(y), summed later into ds/dmu.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64* __restrict__ Vb, long long sV,
+                                                        const c64* __restrict__ Zb, long long sZ,
+                                                        const c64* __restrict__ U, double emu,
+                                                        c64* __restrict__ F, c64* __restrict__ dU,
+                                                        c64* __restrict__ dUc, c64* __restrict__ trF) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    const int y = t >> 2, nu = t & 3;
+    const int Vp = g.Vp;
+    const Nbr N = neighbours(g, y);
+    const int yp = nu == 0 ? N.f[0] : nu == 1 ? N.f[1] : nu == 2 ? N.f[2] : N.f[3];
+    const double sg = (nu == 3 && N.wf) ? double(g.bc_t) : 1.0;
+    const double cf = nu == 3 ? emu : 1.0, cb = nu == 3 ? 1.0 / emu : 1.0;
+    c64 Kf[9], Kb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Kf[i] = Kb[i] = c64{0.0, 0.0};
+    const int cfw = kHop[2 * nu], cbw = kHop[2 * nu + 1];
+    for (int p = 0; p < k; ++p) {
+        const c64* Vp_ = Vb + (size_t)p * sV;
+        const c64* Zp_ = Zb + (size_t)p * sZ;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            // pass 0: (gamma5 (1 - gamma_nu) v(y+nu)) x conj(z(y));  pass 1: (gamma5 (1 + gamma_nu) v(y)) x conj(z(y+nu))
+            const int code = pass == 0 ? cfw : cbw;
+            c64 h0[3], h1[3];
+            project(Vp_, pass == 0 ? yp : y, Vp, code, h0, h1);
+            c64 z[12];
+            load12(Zp_, pass == 0 ? y : yp, Vp, z);
+            const int q0 = (code >> 5) & 1;
+            const int g0c = (code >> 6) & 3, g1c = (code >> 8) & 3;
+            c64* K = pass == 0 ? Kf : Kb;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                // u spins: 0 h0, 1 h1, 2 -G0 h_Q0, 3 -G1 h_Q1 (the minus from gamma5)
+                const c64 u0 = h0[b], u1 = h1[b];
+                const c64 u2 = -mulc(q0 == 0 ? h0[b] : h1[b], g0c);
+                const c64 u3 = -mulc(q0 == 0 ? h1[b] : h0[b], g1c);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    K[3 * b + a] += u0 * conj(z[a]) + u1 * conj(z[3 + a]) + u2 * conj(z[6 + a]) + u3 * conj(z[9 + a]);
+                }
+            }
+        }
+    }
+    // link U_nu(y) from the FP64 internal link field
+    c64 u[9];
+    load_link(U, nu, y, Vp, u);
+    const double af = -0.5 * cf * sg, ab = 0.5 * cb * sg;
+    const size_t o = ((size_t)nu * g.V + y) * 9;
+    c64 tr{0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            c64 f{0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                f += af * (u[3 * a + c] * Kf[3 * c + b]);      // (U Kf)[a][b]
+                f += ab * (Kb[3 * a + c] * conj(u[3 * b + c])); // (Kb U^dag)[a][b]
+            }
+            if (F) F[o + 3 * a + b] = f;
+            if (a == b) tr += f;
+            if (dU) dU[o + 3 * a + b] = af * Kf[3 * b + a];
+            if (dUc) dUc[o + 3 * a + b] = (-ab) * Kb[3 * a + b];
+        }
+    if (nu == 3) trF[y] = tr;
+}
+
+void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
+                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s) {
+    vjp_force_kernel<<<(4 * g.V + 255) / 256, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF);
+}
+
+// out = sum_y trF[y] (one block, fixed order)
+__global__ void sum_c64_kernel(int n, const c64* __restrict__ v, c64* __restrict__ out) {
+    __shared__ double re[256], im[256];
+    c64 a{0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += v[i];
+    re[threadIdx.x] = a.re;
+    im[threadIdx.x] = a.im;
+    __syncthreads();
+    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+        if (threadIdx.x < m) {
+            re[threadIdx.x] += re[threadIdx.x + m];
+            im[threadIdx.x] += im[threadIdx.x + m];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = c64{re[0], im[0]};
+}
+
+void launch_sum_c64(int n, const c64* v, c64* out, hipStream_t s) { sum_c64_kernel<<<1, 256, 0, s>>>(n, v, out); }
+
 }  // namespace ovd

@@ -151,6 +151,10 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
 void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scratch,
                        size_t scratch_elems, c64* c_out, double* check, hipStream_t s);
 size_t small_sign_scratch_elems(int nrhs, int k, double quad_step);
+// M = L_sgn(T_k, e_1 e_1^T) (k x k, row-major) for rhs 0 of co
+void launch_small_frechet(int k, TslCoeffs co, double quad_step, c64* scratch, c64* M_out, double* check,
+                          hipStream_t s);
+size_t small_frechet_scratch_elems(int k);
 
 // y = sum_j coef[rhs][j] * basis[rhs][j]  (top/bottom halves selected by half_off)
 template <typename T>
@@ -178,5 +182,13 @@ void launch_add_soa_to_aos(const Geom& g, int n, const c64* in, long long stride
 template <typename T>
 void launch_convert_field(const Geom& g, int n, const c64* in, long long sin, cpx<T>* out, long long sout,
                           hipStream_t s);
+
+// gradient of <x|sgn(H)|b> (kernels_defl.hip / kernels_stencil.hip)
+void launch_zgemm_wmh(const c64* W, long long sW, int k, const c64* Mp, c64* Z, long long sZ, long long nf,
+                      hipStream_t s);
+void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t s);
+void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
+                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s);
+void launch_sum_c64(int n, const c64* v, c64* out, hipStream_t s);
 
 }  // namespace ovd

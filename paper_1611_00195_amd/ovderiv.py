@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ovd_clear_deflation": (i, [vp]),
         "ovd_sign_apply": (i, [vp, i, dp, i, vp, vp, ctypes.POINTER(_Stats)]),
         "ovd_sign_apply_deriv": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, vp, dp, ctypes.POINTER(_Stats)]),
-        "ovd_sign_apply_vjp": (i, [vp, d, i, vp, vp, dp, dp, vp, ctypes.POINTER(_Stats)]),
+        "ovd_sign_apply_vjp": (i, [vp, d, i, vp, vp, dp, dp, vp, vp, vp, ctypes.POINTER(_Stats)]),
         "ovd_get_tridiag": (i, [vp, i, i, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
@@ -240,6 +240,27 @@ class Lattice:
         if xdy is not None:
             s = [complex(xdy[2 * i], xdy[2 * i + 1]) for i in range(n)]
         return y, dy, s
+
+    def sign_apply_vjp(self, x, b, mu, k, force=True, wirtinger=False, grad=True):
+        """s = <x|sgn(H(mu))|b>, ds/dmu and the link gradients (FP64).
+
+        Returns (s, ds_dmu, F, dsdU, dsdUc); F = per-link force [4, V, 3, 3]
+        (ds/dt = tr(F X) for U -> e^{tX} U) when force, and the Wirtinger
+        derivatives ds/dU, ds/dconj(U) when wirtinger.  With grad=False only s
+        is computed (ds_dmu is None)."""
+        _check_field(x, (1, self.V, 4, 3), "x")
+        _check_field(b, (1, self.V, 4, 3), "b")
+        sc = (ctypes.c_double * 2)()
+        dm = (ctypes.c_double * 2)() if grad else None
+        opts = dict(dtype=torch.complex128, device=b.device)
+        F = torch.empty((4, self.V, 3, 3), **opts) if grad and force else None
+        dU = torch.empty((4, self.V, 3, 3), **opts) if grad and wirtinger else None
+        dUc = torch.empty((4, self.V, 3, 3), **opts) if grad and wirtinger else None
+        st = _Stats()
+        self._call("ovd_sign_apply_vjp", float(mu), int(k), _ptr(x), _ptr(b), sc, dm, _ptr(F), _ptr(dU), _ptr(dUc),
+                   ctypes.byref(st))
+        self.last_stats = self._stats(st)
+        return complex(sc[0], sc[1]), (complex(dm[0], dm[1]) if grad else None), F, dU, dUc
 
     def set_deflation(self, mu, lam, R, L, l=0, dR=None, dL=None, direction="mu", dU=None):
         """Deflation set for one mu (eq. 8 with the m pairs, eq. 11 with the first l).
