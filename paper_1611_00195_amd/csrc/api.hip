@@ -205,8 +205,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     const long long fsz = (long long)halves * 12 * g.Vp;
     const cpx<T>* U = std::is_same<T, double>::value ? (const cpx<T>*)h->U64 : (const cpx<T>*)h->U32;
     const cpx<T>* dU = std::is_same<T, double>::value ? (const cpx<T>*)h->dU64 : (const cpx<T>*)h->dU32;
-    const int ngroups = (g.V + 63) / 64;
-    const int nb = (ngroups + 7) / 8 * 8;
+    const int nb = tsl_stencil_blocks(g, dir);
 
     WS(ring, cpx<T>, "tsl_ring", (size_t)10 * nrhs * fsz);
     WS(st, TslState, "tsl_state", nrhs);

@@ -22,9 +22,16 @@
 // hop), which is what keeps enough bytes in flight.
 #include "ovd_internal.h"
 
-// occupancy hint for the stencil kernels (waves per SIMD); empty = compiler's choice
+// scheduling fence between the hops of a site (limits how far the compiler
+// hoists the next hop's loads, and so the register count); empty = none
+#ifndef OVD_HOP_FENCE
+#define OVD_HOP_FENCE
+#endif
+
+// occupancy hint for the stencil kernels (waves per SIMD), by precision T;
+// empty = compiler's choice
 #ifndef OVD_OCC
-#define OVD_OCC
+#define OVD_OCC(T)
 #endif
 
 namespace ovd {
@@ -156,28 +163,121 @@ __device__ __forceinline__ void project(const cpx<T>* __restrict__ F, int n, int
     }
 }
 
-// acc += coef * reconstruct(W h), W = U_nu(ls) (forward) or U_nu(ls)^dag (backward)
+// ---------------------------------------------------------------------------
+// Compile-time hops.  The same spin table as kHop, known to the compiler, so
+// that the constants of each hop fold into sign flips and re/im swaps (no
+// selects), with the field and link addresses as a uniform base plus a 32-bit
+// per-lane byte offset (16 bytes per site in every plane, in both precisions).
+// ---------------------------------------------------------------------------
+struct HopC {
+    int p3, f0, f1, q0, g0, g1;
+};
+constexpr HopC kHopCT[8] = {{1, F_PI, F_PI, 1, F_MI, F_MI}, {1, F_MI, F_MI, 1, F_PI, F_PI},
+                            {1, F_P1, F_M1, 1, F_M1, F_P1}, {1, F_M1, F_P1, 1, F_P1, F_M1},
+                            {0, F_PI, F_MI, 0, F_MI, F_PI}, {0, F_MI, F_PI, 0, F_PI, F_MI},
+                            {0, F_M1, F_M1, 0, F_M1, F_M1}, {0, F_P1, F_P1, 0, F_P1, F_P1}};
+
+template <int F, typename T>
+__device__ __forceinline__ cpx<T> mulk(cpx<T> z) {
+    if constexpr (F == F_P1) return z;
+    else if constexpr (F == F_M1) return {-z.re, -z.im};
+    else if constexpr (F == F_PI) return {-z.im, z.re};
+    else return {z.im, -z.re};
+}
+
+// one 16-byte plane entry: one complex in FP64, two in FP32
 template <typename T>
-__device__ __forceinline__ void link_mult_acc(cpx<T> (&acc)[12], const cpx<T> (&h0)[3], const cpx<T> (&h1)[3],
-                                              const cpx<T>* __restrict__ W, int hidx, int code, int ls, int Vp,
-                                              T coef) {
-    const bool fwd = (hidx & 1) == 0;
-    const int q0 = (code >> 5) & 1;
-    const int g0c = (code >> 6) & 3, g1c = (code >> 8) & 3;
+__device__ __forceinline__ void ld_plane(const char* __restrict__ base, uint32_t off, cpx<T>* dst) {
+    if constexpr (sizeof(T) == 8) {
+        const double2 d = *reinterpret_cast<const double2*>(base + off);
+        dst[0] = {d.x, d.y};
+    } else {
+        const float4 t = *reinterpret_cast<const float4*>(base + off);
+        dst[0] = {t.x, t.y};
+        dst[1] = {t.z, t.w};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ld_site(const char* __restrict__ P, uint32_t Vp16, uint32_t off, cpx<T> (&v)[12]) {
+    constexpr int per = sizeof(T) == 8 ? 1 : 2;
+#pragma unroll
+    for (int q = 0; q < 12 / per; ++q) ld_plane<T>(P + (size_t)q * Vp16, off, v + q * per);
+}
+
+template <typename T>
+__device__ __forceinline__ void ld_link(const char* __restrict__ W, uint32_t Vp16, int nu, uint32_t off,
+                                        cpx<T> (&u)[9]) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) ld_plane<T>(W + (size_t)(nu * 9 + e) * Vp16, off, u + e);
+    } else {
+        cpx<T> t[10];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) ld_plane<T>(W + (size_t)(nu * 5 + q) * Vp16, off, t + 2 * q);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = t[e];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_site(char* __restrict__ P, uint32_t Vp16, uint32_t off, const cpx<T> (&v)[12]) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+            *reinterpret_cast<double2*>(P + (size_t)c * Vp16 + off) = double2{v[c].re, v[c].im};
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            *reinterpret_cast<float4*>(P + (size_t)q * Vp16 + off) =
+                float4{v[2 * q].re, v[2 * q].im, v[2 * q + 1].re, v[2 * q + 1].im};
+    }
+}
+
+// half spinor of hop I from a loaded site
+template <typename T, int I>
+__device__ __forceinline__ void proj_ct(const cpx<T> (&v)[12], cpx<T> (&h0)[3], cpx<T> (&h1)[3]) {
+    constexpr HopC H = kHopCT[I];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> a = H.p3 ? v[9 + c] : v[6 + c];
+        const cpx<T> b = H.p3 ? v[6 + c] : v[9 + c];
+        h0[c] = v[c] + mulk<H.f0>(a);
+        h1[c] = v[3 + c] + mulk<H.f1>(b);
+    }
+}
+
+// acc += coef * reconstruct(W proj(P(neighbour))) for hop I
+template <typename T, int I>
+__device__ __forceinline__ void hop_ct(cpx<T> (&acc)[12], const char* __restrict__ P, const char* __restrict__ W,
+                                       uint32_t Vp16, uint32_t noff, uint32_t loff, T coef) {
+    constexpr HopC H = kHopCT[I];
+    constexpr bool fwd = (I & 1) == 0;
+    cpx<T> h0[3], h1[3];
+    {
+        cpx<T> v[12];
+        ld_site<T>(P, Vp16, noff, v);
+        proj_ct<T, I>(v, h0, h1);
+    }
     cpx<T> u[9];
-    load_link(W, hidx >> 1, ls, Vp, u);
+    ld_link<T>(W, Vp16, I >> 1, loff, u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        h0[c] = coef * h0[c];
+        h1[c] = coef * h1[c];
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        // row a of U:  U[a][b] = u[3a + b];  row a of U^dag: conj(U[b][a]) = conj(u[3b + a])
+        // row a of U: U[a][b] = u[3a + b];  row a of U^dag: conj(U[b][a])
         const cpx<T> r0 = fwd ? u[3 * a] : conj(u[a]);
         const cpx<T> r1 = fwd ? u[3 * a + 1] : conj(u[3 + a]);
         const cpx<T> r2 = fwd ? u[3 * a + 2] : conj(u[6 + a]);
         const cpx<T> g0 = r0 * h0[0] + r1 * h0[1] + r2 * h0[2];
         const cpx<T> g1 = r0 * h1[0] + r1 * h1[1] + r2 * h1[2];
-        acc[a] += coef * g0;
-        acc[3 + a] += coef * g1;
-        acc[6 + a] += coef * mulc(q0 == 0 ? g0 : g1, g0c);
-        acc[9 + a] += coef * mulc(q0 == 0 ? g1 : g0, g1c);
+        acc[a] += g0;
+        acc[3 + a] += g1;
+        acc[6 + a] += mulk<H.g0>(H.q0 == 0 ? g0 : g1);
+        acc[9 + a] += mulk<H.g1>(H.q0 == 0 ? g1 : g0);
     }
 }
 
@@ -185,37 +285,47 @@ __device__ __forceinline__ void link_mult_acc(cpx<T> (&acc)[12], const cpx<T> (&
 // P + sf Q (forward) / P + sb Q (backward) is used instead, sf, sb in {0, +-1}
 // (the mu derivative of the block matrix combines its two halves there);
 // spatial hops get -1/2 cs, time hops -1/2 cf / -1/2 cb and the boundary
-// factor.  With space == false only the time hops are applied.
-template <typename T>
-__device__ __forceinline__ void hops(cpx<T> (&acc)[12], const cpx<T>* __restrict__ P, const cpx<T>* __restrict__ Q,
-                                     int sf, int sb, const Nbr& N, int s, const cpx<T>* __restrict__ W, int Vp,
-                                     T cs, T cf, T cb, int bc, bool space) {
+// factor.  With SPACE false only the time hops are applied.
+template <bool SPACE, typename T>
+__device__ __forceinline__ void hops(cpx<T> (&acc)[12], const cpx<T>* __restrict__ Pf, const cpx<T>* __restrict__ Qf,
+                                     int sf, int sb, const Nbr& N, int s, const cpx<T>* __restrict__ Wf, int Vp,
+                                     T cs, T cf, T cb, int bc) {
+    const char* P = reinterpret_cast<const char*>(Pf);
+    const char* Q = reinterpret_cast<const char*>(Qf);
+    const char* W = reinterpret_cast<const char*>(Wf);
+    const uint32_t Vp16 = (uint32_t)Vp * 16u;
+    const uint32_t so = (uint32_t)s * 16u;
     const T h = T(-0.5);
-#pragma unroll 1
-    for (int i = space ? 0 : 6; i < 8; ++i) {
-        const int nu = i >> 1;
-        const bool fwd = (i & 1) == 0;
-        const int nf = nu == 0 ? N.f[0] : nu == 1 ? N.f[1] : nu == 2 ? N.f[2] : N.f[3];
-        const int nbk = nu == 0 ? N.b[0] : nu == 1 ? N.b[1] : nu == 2 ? N.b[2] : N.b[3];
-        const int n = fwd ? nf : nbk;
-        const int ls = fwd ? s : nbk;
-        const int code = kHop[i];
-        T coef = h * cs;
-        if (nu == 3) coef = fwd ? h * cf * (N.wf ? T(bc) : T(1)) : h * cb * (N.wb ? T(bc) : T(1));
-        cpx<T> h0[3], h1[3];
-        project(P, n, Vp, code, h0, h1);
-        const int sg = (nu < 3) ? 0 : (fwd ? sf : sb);
-        if (sg != 0) {   // uniform per wave
-            cpx<T> q0[3], q1[3];
-            project(Q, n, Vp, code, q0, q1);
-            const T sgn = T(sg);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                h0[c] += sgn * q0[c];
-                h1[c] += sgn * q1[c];
-            }
-        }
-        link_mult_acc(acc, h0, h1, W, i, code, ls, Vp, coef);
+    if constexpr (SPACE) {
+        const T c = h * cs;
+        hop_ct<T, 0>(acc, P, W, Vp16, (uint32_t)N.f[0] * 16u, so, c);
+        OVD_HOP_FENCE;
+        hop_ct<T, 1>(acc, P, W, Vp16, (uint32_t)N.b[0] * 16u, (uint32_t)N.b[0] * 16u, c);
+        OVD_HOP_FENCE;
+        hop_ct<T, 2>(acc, P, W, Vp16, (uint32_t)N.f[1] * 16u, so, c);
+        OVD_HOP_FENCE;
+        hop_ct<T, 3>(acc, P, W, Vp16, (uint32_t)N.b[1] * 16u, (uint32_t)N.b[1] * 16u, c);
+        OVD_HOP_FENCE;
+        hop_ct<T, 4>(acc, P, W, Vp16, (uint32_t)N.f[2] * 16u, so, c);
+        OVD_HOP_FENCE;
+        hop_ct<T, 5>(acc, P, W, Vp16, (uint32_t)N.b[2] * 16u, (uint32_t)N.b[2] * 16u, c);
+        OVD_HOP_FENCE;
+    }
+    // time hops; the second field enters as a hop of its own (linear in the
+    // field, and one field at a time keeps the register count of a single hop)
+    const T ctf = h * cf * (N.wf ? T(bc) : T(1));
+    const T ctb = h * cb * (N.wb ? T(bc) : T(1));
+    const uint32_t of = (uint32_t)N.f[3] * 16u, ob = (uint32_t)N.b[3] * 16u;
+    hop_ct<T, 6>(acc, P, W, Vp16, of, so, ctf);
+    if (sf != 0) {   // uniform per wave
+        OVD_HOP_FENCE;
+        hop_ct<T, 6>(acc, Q, W, Vp16, of, so, T(sf) * ctf);
+    }
+    OVD_HOP_FENCE;
+    hop_ct<T, 7>(acc, P, W, Vp16, ob, ob, ctb);
+    if (sb != 0) {
+        OVD_HOP_FENCE;
+        hop_ct<T, 7>(acc, Q, W, Vp16, ob, ob, T(sb) * ctb);
     }
 }
 
@@ -226,12 +336,13 @@ __device__ __forceinline__ void hops(cpx<T> (&acc)[12], const cpx<T>* __restrict
 // XCD keeps its neighbour data in L2 only if it sweeps a compact piece of
 // work in site order.  The (rhs, site group) work items are therefore split
 // into 8 compact chunks, one per XCD:
-//   nrhs a multiple of 8:  XCD x takes right-hand sides x m .. x m + m - 1
+//   nrhs >= 16 and a multiple of 8:  XCD x takes right-hand sides x m .. x m + m - 1
 //                          (m = nrhs / 8) over the whole lattice, site group
 //                          major, so those m share each link read;
-//   nrhs dividing 8:       XCD x takes one right-hand side over 1/(8/nrhs) of
-//                          the lattice (a contiguous range of time slices);
-//   otherwise:             contiguous ranges of (site group, rhs) pairs.
+//   otherwise:             XCD x takes a contiguous range of site groups for
+//                          all right-hand sides (rhs innermost), so that the
+//                          links and neighbours of a range stay in its L2.
+// The choice follows measurements of Dw.v at 14^4 (1, 8 and 48 sources).
 // nb (site groups per rhs, padded) is a multiple of 8.
 struct Work {
     int rhs, grp;
@@ -239,14 +350,10 @@ struct Work {
 __device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs) {
     const int x = bid & 7, idx = bid >> 3;
     Work w;
-    if ((nrhs & 7) == 0) {
+    if ((nrhs & 7) == 0 && nrhs >= 16) {
         const int m = nrhs >> 3;
         w.grp = idx / m;
         w.rhs = x * m + idx % m;
-    } else if ((8 % nrhs) == 0) {
-        const int parts = 8 / nrhs;
-        w.rhs = x / parts;
-        w.grp = (x % parts) * (nb / parts) + idx;
     } else {
         const int i = x * (nb * nrhs / 8) + idx;
         w.grp = i / nrhs;
@@ -259,7 +366,7 @@ __device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs) {
 // standalone operator
 // ---------------------------------------------------------------------------
 template <typename T, int OP>
-__global__ __launch_bounds__(256) OVD_OCC void apply_op_kernel(Geom g, const double* __restrict__ emu,
+__global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_kernel(Geom g, const double* __restrict__ emu,
                                                        const cpx<T>* __restrict__ U,
                                                        const cpx<T>* __restrict__ dU, T mdiag,
                                                        const cpx<T>* __restrict__ in,
@@ -279,15 +386,15 @@ __global__ __launch_bounds__(256) OVD_OCC void apply_op_kernel(Geom g, const dou
         load12(P, s, Vp, acc);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = mdiag * acc[c];
-        hops(acc, P, P, 0, 0, N, s, U, Vp, T(1), ep, em, g.bc_t, true);
+        hops<true>(acc, P, P, 0, 0, N, s, U, Vp, T(1), ep, em, g.bc_t);
     } else if constexpr (OP == 2) {             // dH/dmu: time hops, e^{mu} and -e^{-mu}
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
-        hops(acc, P, P, 0, 0, N, s, U, Vp, T(0), ep, -em, g.bc_t, false);
+        hops<false>(acc, P, P, 0, 0, N, s, U, Vp, T(0), ep, -em, g.bc_t);
     } else {                                    // dH/dt along dU: hops with dU, no mass term
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
-        hops(acc, P, P, 0, 0, N, s, dU, Vp, T(1), ep, em, g.bc_t, true);
+        hops<true>(acc, P, P, 0, 0, N, s, dU, Vp, T(1), ep, em, g.bc_t);
     }
     if (OP != 1) {
 #pragma unroll
@@ -376,117 +483,277 @@ __global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n
 //
 // Reads the new unnormalised vectors vhat, what, writes A vhat and A^dag what
 // and the block partial sums of
-//     omega = what^dag vhat,  gamma = what^dag A vhat = (A^dag what)^dag vhat,
-//     p = x^dag vhat_top,  |vhat|^2, |what|^2.
+//     omega = what^dag vhat,  gamma = what^dag A vhat,  p = x^dag vhat_top,
+//     |vhat|^2, |what|^2.
 // The last block to finish sums the partials in a fixed order and advances the
 // recurrence: delta = sqrt|omega|, beta = omega/delta, alpha = gamma/omega
 // (= w^dag A v for the normalised vectors), and the coefficients of the next
 // update.  One grid-wide reduction per Lanczos step, no host round trip.
 //
-// Work split: a block is NK waves over the same 64 sites, wave = output kind.
-//   DIR 0 (A = H):                kind 0 = H vhat,  kind 1 = H^dag what
-//   DIR 1/2 (A = B = [[H, dH], [0, H]], B^dag = [[H^dag, 0], [dH^dag, H^dag]]):
-//     kind 0 = H vt + dH vb,  kind 1 = H vb,  kind 2 = H^dag wt,  kind 3 = dH^dag wt + H^dag wb
-// with H^dag = H(-mu); for d/dmu, dH only has time hops (e^{mu}, -e^{-mu}) and
-// dH^dag = -dH/dmu(-mu) (time hops -e^{-mu}, e^{mu}); for a link direction,
-// dH is the hopping term with links dU, and dH^dag that with dU at -mu.
+// Each thread computes two output fields at one site from two input fields
+// ("pair"), loading every link once for both and every neighbour of each
+// input once:
+//   DIR 0 (A = H):  A = vhat -> H vhat,  B = what -> H^dag what  (one wave each);
+//   DIR 1/2 (A = B = [[H, dH], [0, H]]):
+//     v wave: A = vt, B = vb;  top = H vt + dH vb,  bottom = H vb;
+//     w wave: A = wt, B = wb;  top = H^dag wt,      bottom = dH^dag wt + H^dag wb,
+// with H^dag = H(-mu).  For d/dmu, dH has only time hops, with the factors
+// (+e^{mu}, -e^{-mu}) where H has (e^{mu}, e^{-mu}), and dH^dag those of
+// -dH/dmu(-mu); by linearity these enter as "mix" terms of the time hops
+// (top += x_AB B, bottom += x_BA A before the link multiply).  For a link
+// direction, dH is the hopping term with links dU (dH^dag: dU at -mu).
+// A block is 4 waves: (v, w) on site group 2b and (v, w) on group 2b + 1.
 // ---------------------------------------------------------------------------
+
+// acc += reconstruct_I(g0, g1): spins 0, 1 = g0, g1; spins 2, 3 from the hop table
+template <typename T, int I>
+__device__ __forceinline__ void recon_add(cpx<T> (&acc)[12], const cpx<T> (&g0)[3], const cpx<T> (&g1)[3]) {
+    constexpr HopC H = kHopCT[I];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] += g0[a];
+        acc[3 + a] += g1[a];
+        acc[6 + a] += mulk<H.g0>(H.q0 == 0 ? g0[a] : g1[a]);
+        acc[9 + a] += mulk<H.g1>(H.q0 == 0 ? g1[a] : g0[a]);
+    }
+}
+
+// g = U h (forward hop) or U^dag h (backward hop), h a half spinor (2 x 3 colours)
+template <typename T, bool FWD>
+__device__ __forceinline__ void link_mul(const cpx<T> (&u)[9], const cpx<T> (&h0)[3], const cpx<T> (&h1)[3],
+                                         cpx<T> (&g0)[3], cpx<T> (&g1)[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cpx<T> r0 = FWD ? u[3 * a] : conj(u[a]);
+        const cpx<T> r1 = FWD ? u[3 * a + 1] : conj(u[3 + a]);
+        const cpx<T> r2 = FWD ? u[3 * a + 2] : conj(u[6 + a]);
+        g0[a] = r0 * h0[0] + r1 * h0[1] + r2 * h0[2];
+        g1[a] = r0 * h1[0] + r1 * h1[1] + r2 * h1[2];
+    }
+}
+
+// Hop I of a pair.  cA, cB: hop factors of the two outputs; xAB, xBA: mix
+// factors (time hops of the mu derivative, else 0); with DIR 2 the second
+// link field W2 carries the derivative hop of B into top (v side) or of A into
+// bottom (w side).
+template <typename T, int I, int DIR>
+__device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12], const char* __restrict__ A,
+                                         const char* __restrict__ B, const char* __restrict__ W,
+                                         const char* __restrict__ W2, uint32_t Vp16, uint32_t noff, uint32_t loff,
+                                         T cA, T cB, T xAB, T xBA, bool vside) {
+    constexpr bool fwd = (I & 1) == 0;
+    constexpr bool mix = (DIR == 1) && (I >= 6);
+    cpx<T> a0[3], a1[3], b0[3], b1[3];
+    {
+        cpx<T> v[12];
+        ld_site<T>(A, Vp16, noff, v);
+        proj_ct<T, I>(v, a0, a1);
+    }
+    {
+        cpx<T> v[12];
+        ld_site<T>(B, Vp16, noff, v);
+        proj_ct<T, I>(v, b0, b1);
+    }
+    cpx<T> hA0[3], hA1[3], hB0[3], hB1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        hA0[c] = cA * a0[c];
+        hA1[c] = cA * a1[c];
+        hB0[c] = cB * b0[c];
+        hB1[c] = cB * b1[c];
+        if constexpr (mix) {
+            hA0[c] += (cA * xAB) * b0[c];
+            hA1[c] += (cA * xAB) * b1[c];
+            hB0[c] += (cB * xBA) * a0[c];
+            hB1[c] += (cB * xBA) * a1[c];
+        }
+    }
+    cpx<T> g0[3], g1[3];
+    {
+        cpx<T> u[9];
+        ld_link<T>(W, Vp16, I >> 1, loff, u);
+        link_mul<T, fwd>(u, hA0, hA1, g0, g1);
+        recon_add<T, I>(accA, g0, g1);
+        link_mul<T, fwd>(u, hB0, hB1, g0, g1);
+        recon_add<T, I>(accB, g0, g1);
+    }
+    if constexpr (DIR == 2) {
+        cpx<T> u[9], d0[3], d1[3];
+        ld_link<T>(W2, Vp16, I >> 1, loff, u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            d0[c] = vside ? cA * b0[c] : cB * a0[c];
+            d1[c] = vside ? cA * b1[c] : cB * a1[c];
+        }
+        link_mul<T, fwd>(u, d0, d1, g0, g1);
+        if (vside) recon_add<T, I>(accA, g0, g1);
+        else recon_add<T, I>(accB, g0, g1);
+    }
+}
+
 template <typename T, int DIR>
-__global__ __launch_bounds__(256) OVD_OCC void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
+__device__ __forceinline__ void pair_hops(cpx<T> (&accA)[12], cpx<T> (&accB)[12], const cpx<T>* Af,
+                                          const cpx<T>* Bf, const cpx<T>* Wf, const cpx<T>* W2f, const Nbr& N, int s,
+                                          int Vp, T cfA, T cbA, T cfB, T cbB, T xfAB, T xbAB, T xfBA, T xbBA, int bc,
+                                          bool vside) {
+    const char* A = reinterpret_cast<const char*>(Af);
+    const char* B = reinterpret_cast<const char*>(Bf);
+    const char* W = reinterpret_cast<const char*>(Wf);
+    const char* W2 = reinterpret_cast<const char*>(W2f);
+    const uint32_t Vp16 = (uint32_t)Vp * 16u;
+    const uint32_t so = (uint32_t)s * 16u;
+    const T h = T(-0.5), z = T(0);
+#define OVD_PH(I, NB, LS, CA, CB, XAB, XBA)                                                                       \
+    pair_hop<T, I, DIR>(accA, accB, A, B, W, W2, Vp16, (uint32_t)(NB) * 16u, (uint32_t)(LS) * 16u, CA, CB, XAB, \
+                        XBA, vside);                                                                             \
+    OVD_HOP_FENCE;
+    OVD_PH(0, N.f[0], s, h, h, z, z)
+    OVD_PH(1, N.b[0], N.b[0], h, h, z, z)
+    OVD_PH(2, N.f[1], s, h, h, z, z)
+    OVD_PH(3, N.b[1], N.b[1], h, h, z, z)
+    OVD_PH(4, N.f[2], s, h, h, z, z)
+    OVD_PH(5, N.b[2], N.b[2], h, h, z, z)
+    const T sf = N.wf ? T(bc) : T(1), sb = N.wb ? T(bc) : T(1);
+    OVD_PH(6, N.f[3], s, h * cfA * sf, h * cfB * sf, xfAB, xfBA)
+    OVD_PH(7, N.b[3], N.b[3], h * cbA * sb, h * cbB * sb, xbAB, xbBA)
+#undef OVD_PH
+    (void)so;
+}
+
+// partial sums of the step: 0,1 omega; 2,3 gamma; 4,5 p; 6 |vhat|^2; 7 |what|^2
+template <typename T>
+__device__ __forceinline__ void dot_acc(double* part, int i, const cpx<T> (&a)[12], const cpx<T> (&b)[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const c64 d = cdot(cast<double>(a[c]), cast<double>(b[c]));
+        part[i] += d.re;
+        part[i + 1] += d.im;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) part[i] += norm2(cast<double>(a[c]));
+}
+
+// site groups (of 64) per block: DIR 0 has one pair per site (4 groups per
+// block), DIR 1/2 two pairs per site (2 groups x (v, w) waves)
+template <int DIR> constexpr int tsl_groups_per_block() { return DIR == 0 ? 4 : 2; }
+
+template <typename T, int DIR>
+__global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
                                                           const cpx<T>* __restrict__ dU, T mdiag,
                                                           TslState* __restrict__ st, TslCoeffs co,
                                                           double* __restrict__ partials,
                                                           unsigned* __restrict__ counters, int j, double tau,
                                                           int ngroups, int nrhs) {
-    constexpr int NK = (DIR == 0) ? 2 : 4;
+    constexpr int GPB = tsl_groups_per_block<DIR>();
     __shared__ double lds[16 * 8];
     __shared__ int am_last;
     const int nb = gridDim.x / nrhs;                // blocks per rhs
     const Work wk = xcd_work(blockIdx.x, nb, nrhs);
     const int rhs = wk.rhs;
-    const int grp = wk.grp;                         // in [0, ngroups padded to 8)
     TslState* S = st + rhs;
     if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
     const int Vp = g.Vp;
-    const int kind = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const bool vside = (DIR == 0) || (wave & 1) == 0;
+    const int grp = (DIR == 0) ? wk.grp * GPB + wave : wk.grp * GPB + (wave >> 1);
     const int s = grp * 64 + (threadIdx.x & 63);
-    const bool active = (grp < ngroups) && (s < g.V) && (kind < NK);
+    const bool active = (grp < ngroups) && (s < g.V);
     const T ep = T(S->emu), em = T(S->emu_inv);
     const size_t HALF = (size_t)12 * Vp;
-    // Per-kind configuration (uniform per wave):
-    //   vside: output on the v side (A, i.e. H(mu)) or the w side (A^dag, H(-mu));
-    //   hp / hq: half-field index (0 top, 1 bottom) of the primary / secondary input;
-    //   sf, sb: sign of the secondary input on the forward / backward time hop (d/dmu);
-    //   sec: secondary input hopped with dU (d/dlink).
-    const bool vside = (kind == 0) || (kind == 1 && DIR != 0);
-    int hp = 0, hq = 0, sf = 0, sb = 0;
-    bool sec = false;
-    if (DIR != 0) {
-        if (kind == 0) { hp = 0; hq = 1; }
-        else if (kind == 1) { hp = 1; hq = 1; }
-        else if (kind == 2) { hp = 0; hq = 0; }
-        else { hp = 1; hq = 0; }
-        if (DIR == 1 && kind == 0) { sf = +1; sb = -1; }   // H vt + dH/dmu vb
-        if (DIR == 1 && kind == 3) { sf = -1; sb = +1; }   // dH/dmu^dag wt + H^dag wb
-        if (DIR == 2 && (kind == 0 || kind == 3)) sec = true;
+    const cpx<T>* Vf = (const cpx<T>*)p.outV + rhs * p.sV;
+    const cpx<T>* Wf = (const cpx<T>*)p.outW + rhs * p.sW;
+    cpx<T>* oV = (cpx<T>*)p.outU + rhs * p.sU;
+    cpx<T>* oW = (cpx<T>*)p.outZ + rhs * p.sZ;
+    // the pair: DIR 0 (A, B) = (vhat, what); DIR 1/2 the two halves of one side
+    const cpx<T>* Ain = (DIR == 0 || vside) ? Vf : Wf;
+    const cpx<T>* Bin = (DIR == 0) ? Wf : Ain + HALF;
+    cpx<T>* Aout = (DIR == 0 || vside) ? oV : oW;
+    cpx<T>* Bout = (DIR == 0) ? oW : Aout + HALF;
+    // hop factors: v side H(mu), w side H(-mu)
+    T cfA, cbA, cfB, cbB, xfAB = 0, xbAB = 0, xfBA = 0, xbBA = 0;
+    if (DIR == 0) {
+        cfA = ep; cbA = em; cfB = em; cbB = ep;
+    } else {
+        cfA = cfB = vside ? ep : em;
+        cbA = cbB = vside ? em : ep;
+        if (DIR == 1) {
+            if (vside) { xfAB = T(1); xbAB = T(-1); }    // top += (d/dmu H) vb
+            else { xfBA = T(-1); xbBA = T(1); }          // bottom += (d/dmu H)^dag wt
+        }
     }
-    const cpx<T>* F = vside ? (const cpx<T>*)p.outV + rhs * p.sV : (const cpx<T>*)p.outW + rhs * p.sW;
-    const cpx<T>* P = F + hp * HALF;
-    const cpx<T>* Q = F + hq * HALF;
-    const T cf = vside ? ep : em, cbk = vside ? em : ep;
 
     double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (active) {
         const Nbr N = neighbours(g, s);
-        cpx<T> acc[12];
-        load12(P, s, Vp, acc);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = mdiag * acc[c];
-        hops(acc, P, Q, sf, sb, N, s, U, Vp, T(1), cf, cbk, g.bc_t, true);
-        if (DIR == 2 && sec) hops(acc, Q, Q, 0, 0, N, s, dU, Vp, T(1), cf, cbk, g.bc_t, true);
-        cpx<T>* oA = vside ? (cpx<T>*)p.outU + rhs * p.sU : (cpx<T>*)p.outZ + rhs * p.sZ;
-        oA += hp * HALF;
-#pragma unroll
-        for (int c = 6; c < 12; ++c) acc[c] = -acc[c];   // gamma5
-        store12(oA, s, Vp, acc);
-        // reduction terms.  v side: omega = what^dag vhat, |vhat|^2, p = x^dag vhat_top;
-        // w side: gamma = what^dag A vhat = (A^dag what)^dag vhat, |what|^2.
-        // Each thread holds at most its output and one loaded field at a time.
-        if (vside) {
-            cpx<T> vv[12], wv[12];
-            load12(P, s, Vp, vv);
-            load12((const cpx<T>*)p.outW + rhs * p.sW + hp * HALF, s, Vp, wv);
+        const char* Ab = reinterpret_cast<const char*>(Ain);
+        const char* Bb = reinterpret_cast<const char*>(Bin);
+        const char* Xb = p.xproj ? reinterpret_cast<const char*>((const cpx<T>*)p.xproj + rhs * p.sx) : nullptr;
+        const uint32_t Vp16 = (uint32_t)Vp * 16u, so = (uint32_t)s * 16u;
+        cpx<T> accA[12], accB[12];
+        {
+            // own site: mass term, and the reductions that need only the inputs
+            cpx<T> a[12], b[12];
+            ld_site<T>(Ab, Vp16, so, a);
+            ld_site<T>(Bb, Vp16, so, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const c64 om = cdot(cast<double>(wv[c]), cast<double>(vv[c]));
-                part[0] += om.re; part[1] += om.im;
-                part[6] += norm2(cast<double>(vv[c]));
+                accA[c] = mdiag * a[c];
+                accB[c] = mdiag * b[c];
             }
-            if (hp == 0 && p.xproj) {
-                load12((const cpx<T>*)p.xproj + rhs * p.sx, s, Vp, wv);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) {
-                    const c64 pr = cdot(cast<double>(wv[c]), cast<double>(vv[c]));
-                    part[4] += pr.re; part[5] += pr.im;
+            if (DIR == 0) {            // a = vhat, b = what
+                dot_acc(part, 0, b, a);
+                nrm_acc(part, 6, a);
+                nrm_acc(part, 7, b);
+                if (Xb) {
+                    ld_site<T>(Xb, Vp16, so, b);
+                    dot_acc(part, 4, b, a);
                 }
+            } else if (vside) {        // a = vt, b = vb
+                nrm_acc(part, 6, a);
+                nrm_acc(part, 6, b);
+                if (Xb) {
+                    ld_site<T>(Xb, Vp16, so, b);
+                    dot_acc(part, 4, b, a);
+                }
+            } else {                   // a = wt, b = wb; omega over both halves
+                nrm_acc(part, 7, a);
+                nrm_acc(part, 7, b);
+                cpx<T> v[12];
+                ld_site<T>(reinterpret_cast<const char*>(Vf), Vp16, so, v);
+                dot_acc(part, 0, a, v);
+                ld_site<T>(reinterpret_cast<const char*>(Vf + HALF), Vp16, so, v);
+                dot_acc(part, 0, b, v);
             }
-        } else {
-            cpx<T> vv[12];
-            load12((const cpx<T>*)p.outV + rhs * p.sV + hp * HALF, s, Vp, vv);
+        }
+        pair_hops<T, DIR>(accA, accB, Ain, Bin, U, dU, N, s, Vp, cfA, cbA, cfB, cbB, xfAB, xbAB, xfBA, xbBA,
+                          g.bc_t, vside);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const c64 ga = cdot(cast<double>(acc[c]), cast<double>(vv[c]));
-                part[2] += ga.re; part[3] += ga.im;
-            }
-            load12(P, s, Vp, vv);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) part[7] += norm2(cast<double>(vv[c]));
+        for (int c = 6; c < 12; ++c) {   // gamma5
+            accA[c] = -accA[c];
+            accB[c] = -accB[c];
+        }
+        store_site<T>(reinterpret_cast<char*>(Aout), Vp16, so, accA);
+        store_site<T>(reinterpret_cast<char*>(Bout), Vp16, so, accB);
+        // gamma = what^dag (A vhat)
+        if (DIR == 0) {                // = (A^dag what)^dag vhat = accB^dag vhat
+            cpx<T> v[12];
+            ld_site<T>(Ab, Vp16, so, v);
+            dot_acc(part, 2, accB, v);
+        } else if (vside) {
+            cpx<T> w[12];
+            ld_site<T>(reinterpret_cast<const char*>(Wf), Vp16, so, w);
+            dot_acc(part, 2, w, accA);
+            ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
+            dot_acc(part, 2, w, accB);
         }
     }
 
     block_reduce<8>(part, lds);
     if (threadIdx.x == 0) {
-        double* dst = partials + ((size_t)rhs * nb + grp) * 8;
+        double* dst = partials + ((size_t)rhs * nb + wk.grp) * 8;
         for (int i = 0; i < 8; ++i) __hip_atomic_store(dst + i, part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const unsigned prev = atomicAdd(counters + rhs, 1u);
@@ -558,20 +825,25 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
         tsl_update_kernel<T, 2><<<grid, 256, 0, s>>>(p, fsz, st);
 }
 
+int tsl_stencil_blocks(const Geom& g, int dir) {
+    const int ngroups = (g.V + 63) / 64;
+    const int gpb = dir == 0 ? tsl_groups_per_block<0>() : tsl_groups_per_block<1>();
+    return ((ngroups + gpb - 1) / gpb + 7) / 8 * 8;   // nb * nrhs is a multiple of 8
+}
+
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
                         unsigned* counters, int j, double tau, hipStream_t s) {
     const int ngroups = (g.V + 63) / 64;
-    const int nb = (ngroups + 7) / 8 * 8;   // blocks per rhs; nb * nrhs is a multiple of 8
-    dim3 grid(nb * nrhs);
+    dim3 grid(tsl_stencil_blocks(g, dir) * nrhs), block(256);
     const T md = T(m_diag);
     if (dir == 0)
-        tsl_stencil_kernel<T, 0><<<grid, dim3(128), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
+        tsl_stencil_kernel<T, 0><<<grid, block, 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
     else if (dir == 1)
-        tsl_stencil_kernel<T, 1><<<grid, dim3(256), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
+        tsl_stencil_kernel<T, 1><<<grid, block, 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
     else
-        tsl_stencil_kernel<T, 2><<<grid, dim3(256), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
+        tsl_stencil_kernel<T, 2><<<grid, block, 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
 }
 
 #define OVD_INST(T)                                                                                        \

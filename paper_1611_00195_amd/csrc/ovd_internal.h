@@ -142,6 +142,8 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
                        hipStream_t s);
 // Lanczos step part 2: stencil on outV/outW into outU/outZ plus the step's
 // reductions and scalar recurrence.  dir: 0 plain H, 1 block d/dmu, 2 block d/dlink.
+// blocks per right-hand side of the stencil kernel (size of its partial sums)
+int tsl_stencil_blocks(const Geom& g, int dir);
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,

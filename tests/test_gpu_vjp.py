@@ -66,18 +66,21 @@ def test_vjp_converges_to_dense():
     assert all(errs[1][i] < errs[0][i] for i in range(3))
 
 
-def test_autograd_against_finite_differences():
+def test_autograd_against_oracle_and_finite_differences():
     """L = Re(c s); torch gradients of U (complex), mu, x and b along random
-    directions against central differences of the dense sign on the CPU."""
+    directions.  Parity: the oracle's Krylov gradient at the same k (1e-9).
+    Exactness: central differences of the dense sign, which the GPU value must
+    match as closely as the oracle's own Krylov value does (the truncation
+    error at this k, 1e-3 for the bilinear and 3e-3 for the one-sided solves)."""
     from paper_1611_00195_amd.functional import sign_bilinear
     from gpu_helpers import dev, host, print_case
-    dims = (2, 2, 2, 2)
-    print_case(test="vjp_autograd", dims=dims)
+    from oracle import tsl
+    dims, k = (2, 2, 2, 2), 64
+    print_case(test="vjp_autograd", dims=dims, k=k)
     U = synth.make_links(dims, 0.5, 511)
     x = synth.make_source(dims, 512)
     b = synth.make_source(dims, 513)
     c = 0.7 - 0.4j
-    k = 160
     from paper_1611_00195_amd import ovderiv
     lat = ovderiv.Lattice(dims)
     Ut, xt, bt = dev(U).requires_grad_(), dev(x).requires_grad_(), dev(b).requires_grad_()
@@ -89,26 +92,36 @@ def test_autograd_against_finite_differences():
         S = matfun.sign_schur(dirac.dense_h(Uh, dims, mu))
         return (c * np.vdot(xh.ravel(), S @ bh.ravel())).real
 
+    # oracle at the same k: K_k = (x^dag b) V_k M_k W_k^dag, and the one-sided
+    # sgn(H(mu)) b and sgn(H(-mu)) x = sgn(H)^dag x
+    ops = lambda mu: (lambda v: dirac.flat(dirac.apply_h(U, v, dims, mu)),
+                      lambda v: dirac.flat(dirac.apply_hdag(U, v, dims, mu)))
+    Lz = tsl.lanczos(*ops(MU), b.ravel(), x.ravel(), k)
+    E1 = np.zeros_like(Lz["T"])
+    E1[0, 0] = 1.0
+    Kk = np.vdot(x.ravel(), b.ravel()) * Lz["V"] @ matfun.frechet_sign_block(Lz["T"], E1) @ np.conj(Lz["W"]).T
+    Sb, _ = tsl.krylov_sign(*ops(MU), b.ravel(), b.ravel(), k)
+    Sx, _ = tsl.krylov_sign(*ops(-MU), x.ravel(), x.ravel(), k)
+
     rng = np.random.default_rng(514)
     cn = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
     h = 1e-5
 
-    def check(an, fd, tol):
-        an, fd = float(an), float(fd)
-        assert abs(an - fd) < tol * max(1.0, abs(fd)), (an, fd)
+    def check(an, kv, fd):
+        an, kv, fd = float(an), float(kv), float(fd)
+        assert abs(an - kv) < 1e-9 * max(1.0, abs(kv)), ("parity", an, kv)
+        assert abs(an - fd) <= 1.5 * abs(kv - fd) + 1e-8, ("exactness", an, kv, fd)
 
     # complex, non-unitary link direction: dL = Re(sum conj(grad) E)
     E = cn(*U.shape)
-    fd = (L(U + h * E, MU, x, b) - L(U - h * E, MU, x, b)) / (2 * h)
-    check(np.sum(np.conj(host(Ut.grad)) * E).real, fd, 1e-7)
-    fd = (L(U, MU + h, x, b) - L(U, MU - h, x, b)) / (2 * h)
-    check(mut.grad.item(), fd, 1e-7)
-    # the x and b gradients are one-sided Krylov approximations of sgn(H) b and
-    # sgn(H)^dag x (polynomial degree k, half that of the bilinear), so they
-    # carry the larger truncation error of k = 160 on this lattice
+    check(np.sum(np.conj(host(Ut.grad)) * E).real,
+          (c * np.trace(Kk @ dirac.dense_dh_dlink(E, dims, MU))).real,
+          (L(U + h * E, MU, x, b) - L(U - h * E, MU, x, b)) / (2 * h))
+    check(mut.grad.item(), (c * np.trace(Kk @ dirac.dense_dh_dmu(U, dims, MU))).real,
+          (L(U, MU + h, x, b) - L(U, MU - h, x, b)) / (2 * h))
     ex = cn(*x.shape)
-    fd = (L(U, MU, x + h * ex, b) - L(U, MU, x - h * ex, b)) / (2 * h)
-    check(np.sum(np.conj(host(xt.grad)) * ex).real, fd, 1e-6)
+    check(np.sum(np.conj(host(xt.grad)) * ex).real, (c * np.vdot(ex.ravel(), Sb)).real,
+          (L(U, MU, x + h * ex, b) - L(U, MU, x - h * ex, b)) / (2 * h))
     eb = cn(*b.shape)
-    fd = (L(U, MU, x, b + h * eb) - L(U, MU, x, b - h * eb)) / (2 * h)
-    check(np.sum(np.conj(host(bt.grad)) * eb).real, fd, 1e-6)
+    check(np.sum(np.conj(host(bt.grad)) * eb).real, (c * np.vdot(Sx, eb.ravel())).real,
+          (L(U, MU, x, b + h * eb) - L(U, MU, x, b - h * eb)) / (2 * h))
