@@ -28,6 +28,11 @@
 #define OVD_HOP_FENCE
 #endif
 
+// scheduling fence between the two inputs of a paired hop; empty = none
+#ifndef OVD_PAIR_FENCE
+#define OVD_PAIR_FENCE
+#endif
+
 // occupancy hint for the stencil kernels (waves per SIMD), by precision T;
 // empty = compiler's choice
 #ifndef OVD_OCC
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_kernel(Geom g, const 
                                                        cpx<T>* __restrict__ out, int ngroups, int nrhs) {
     const Work w = xcd_work(blockIdx.x, gridDim.x / nrhs, nrhs);
     const int rhs = w.rhs;
-    const int grp = w.grp * 4 + (threadIdx.x >> 6);
+    const int grp = w.grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int s = grp * 64 + (threadIdx.x & 63);
     if (grp >= ngroups || s >= g.V) return;
     const int Vp = g.Vp;
@@ -543,51 +548,71 @@ __device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12],
                                          T cA, T cB, T xAB, T xBA, bool vside) {
     constexpr bool fwd = (I & 1) == 0;
     constexpr bool mix = (DIR == 1) && (I >= 6);
-    cpx<T> a0[3], a1[3], b0[3], b1[3];
+    cpx<T> u[9];
+    ld_link<T>(W, Vp16, I >> 1, loff, u);
+    cpx<T> a0[3], a1[3], b0[3], b1[3], g0[3], g1[3];
     {
         cpx<T> v[12];
         ld_site<T>(A, Vp16, noff, v);
         proj_ct<T, I>(v, a0, a1);
     }
-    {
-        cpx<T> v[12];
-        ld_site<T>(B, Vp16, noff, v);
-        proj_ct<T, I>(v, b0, b1);
-    }
-    cpx<T> hA0[3], hA1[3], hB0[3], hB1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        hA0[c] = cA * a0[c];
-        hA1[c] = cA * a1[c];
-        hB0[c] = cB * b0[c];
-        hB1[c] = cB * b1[c];
-        if constexpr (mix) {
-            hA0[c] += (cA * xAB) * b0[c];
-            hA1[c] += (cA * xAB) * b1[c];
-            hB0[c] += (cB * xBA) * a0[c];
-            hB1[c] += (cB * xBA) * a1[c];
-        }
-    }
-    cpx<T> g0[3], g1[3];
-    {
-        cpx<T> u[9];
-        ld_link<T>(W, Vp16, I >> 1, loff, u);
-        link_mul<T, fwd>(u, hA0, hA1, g0, g1);
-        recon_add<T, I>(accA, g0, g1);
-        link_mul<T, fwd>(u, hB0, hB1, g0, g1);
-        recon_add<T, I>(accB, g0, g1);
-    }
-    if constexpr (DIR == 2) {
-        cpx<T> u[9], d0[3], d1[3];
-        ld_link<T>(W2, Vp16, I >> 1, loff, u);
+    if constexpr (!mix) {
+        // A and B independent: one input at a time (fewer live registers)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            d0[c] = vside ? cA * b0[c] : cB * a0[c];
-            d1[c] = vside ? cA * b1[c] : cB * a1[c];
+            b0[c] = cA * a0[c];
+            b1[c] = cA * a1[c];
         }
-        link_mul<T, fwd>(u, d0, d1, g0, g1);
-        if (vside) recon_add<T, I>(accA, g0, g1);
-        else recon_add<T, I>(accB, g0, g1);
+        link_mul<T, fwd>(u, b0, b1, g0, g1);
+        recon_add<T, I>(accA, g0, g1);
+        OVD_PAIR_FENCE;
+        {
+            cpx<T> v[12];
+            ld_site<T>(B, Vp16, noff, v);
+            proj_ct<T, I>(v, b0, b1);
+        }
+        if constexpr (DIR == 2) {
+            // derivative hop with the second link field: B into top (v side), A into bottom (w side)
+            cpx<T> w[9], d0[3], d1[3];
+            ld_link<T>(W2, Vp16, I >> 1, loff, w);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d0[c] = vside ? cA * b0[c] : cB * a0[c];
+                d1[c] = vside ? cA * b1[c] : cB * a1[c];
+            }
+            link_mul<T, fwd>(w, d0, d1, g0, g1);
+            if (vside) recon_add<T, I>(accA, g0, g1);
+            else recon_add<T, I>(accB, g0, g1);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            b0[c] = cB * b0[c];
+            b1[c] = cB * b1[c];
+        }
+        link_mul<T, fwd>(u, b0, b1, g0, g1);
+        recon_add<T, I>(accB, g0, g1);
+    } else {
+        // time hops of the mu derivative: top += x_AB B, bottom += x_BA A
+        {
+            cpx<T> v[12];
+            ld_site<T>(B, Vp16, noff, v);
+            proj_ct<T, I>(v, b0, b1);
+        }
+        cpx<T> h0[3], h1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = cA * a0[c] + (cA * xAB) * b0[c];
+            h1[c] = cA * a1[c] + (cA * xAB) * b1[c];
+        }
+        link_mul<T, fwd>(u, h0, h1, g0, g1);
+        recon_add<T, I>(accA, g0, g1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = cB * b0[c] + (cB * xBA) * a0[c];
+            h1[c] = cB * b1[c] + (cB * xBA) * a1[c];
+        }
+        link_mul<T, fwd>(u, h0, h1, g0, g1);
+        recon_add<T, I>(accB, g0, g1);
     }
 }
 
@@ -656,7 +681,7 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
     TslState* S = st + rhs;
     if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
     const int Vp = g.Vp;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const bool vside = (DIR == 0) || (wave & 1) == 0;
     const int grp = (DIR == 0) ? wk.grp * GPB + wave : wk.grp * GPB + (wave >> 1);
     const int s = grp * 64 + (threadIdx.x & 63);
@@ -693,41 +718,43 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
         const char* Xb = p.xproj ? reinterpret_cast<const char*>((const cpx<T>*)p.xproj + rhs * p.sx) : nullptr;
         const uint32_t Vp16 = (uint32_t)Vp * 16u, so = (uint32_t)s * 16u;
         cpx<T> accA[12], accB[12];
+        // own site: mass term, and the reductions that need only the inputs,
+        // one loaded field at a time (fences keep the loads of the phases apart)
         {
-            // own site: mass term, and the reductions that need only the inputs
-            cpx<T> a[12], b[12];
+            cpx<T> a[12];
             ld_site<T>(Ab, Vp16, so, a);
-            ld_site<T>(Bb, Vp16, so, b);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                accA[c] = mdiag * a[c];
-                accB[c] = mdiag * b[c];
+            for (int c = 0; c < 12; ++c) accA[c] = mdiag * a[c];
+            nrm_acc(part, (DIR == 0 || vside) ? 6 : 7, a);
+            if ((DIR == 0 || vside) && Xb) {          // p = x^dag vhat_top
+                cpx<T> x[12];
+                ld_site<T>(Xb, Vp16, so, x);
+                dot_acc(part, 4, x, a);
             }
-            if (DIR == 0) {            // a = vhat, b = what
+            if (DIR == 0) {                           // omega = what^dag vhat
+                cpx<T> b[12];
+                ld_site<T>(Bb, Vp16, so, b);
                 dot_acc(part, 0, b, a);
-                nrm_acc(part, 6, a);
-                nrm_acc(part, 7, b);
-                if (Xb) {
-                    ld_site<T>(Xb, Vp16, so, b);
-                    dot_acc(part, 4, b, a);
-                }
-            } else if (vside) {        // a = vt, b = vb
-                nrm_acc(part, 6, a);
-                nrm_acc(part, 6, b);
-                if (Xb) {
-                    ld_site<T>(Xb, Vp16, so, b);
-                    dot_acc(part, 4, b, a);
-                }
-            } else {                   // a = wt, b = wb; omega over both halves
-                nrm_acc(part, 7, a);
-                nrm_acc(part, 7, b);
+            } else if (!vside) {                      // omega, top halves: wt^dag vt
                 cpx<T> v[12];
                 ld_site<T>(reinterpret_cast<const char*>(Vf), Vp16, so, v);
                 dot_acc(part, 0, a, v);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            cpx<T> b[12];
+            ld_site<T>(Bb, Vp16, so, b);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) accB[c] = mdiag * b[c];
+            nrm_acc(part, (DIR != 0 && vside) ? 6 : 7, b);
+            if (DIR != 0 && !vside) {                 // omega, bottom halves: wb^dag vb
+                cpx<T> v[12];
                 ld_site<T>(reinterpret_cast<const char*>(Vf + HALF), Vp16, so, v);
                 dot_acc(part, 0, b, v);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
         pair_hops<T, DIR>(accA, accB, Ain, Bin, U, dU, N, s, Vp, cfA, cbA, cfB, cbB, xfAB, xbAB, xfBA, xbBA,
                           g.bc_t, vside);
 #pragma unroll
@@ -743,11 +770,17 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
             ld_site<T>(Ab, Vp16, so, v);
             dot_acc(part, 2, accB, v);
         } else if (vside) {
-            cpx<T> w[12];
-            ld_site<T>(reinterpret_cast<const char*>(Wf), Vp16, so, w);
-            dot_acc(part, 2, w, accA);
-            ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
-            dot_acc(part, 2, w, accB);
+            {
+                cpx<T> w[12];
+                ld_site<T>(reinterpret_cast<const char*>(Wf), Vp16, so, w);
+                dot_acc(part, 2, w, accA);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                cpx<T> w[12];
+                ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
+                dot_acc(part, 2, w, accB);
+            }
         }
     }
 
