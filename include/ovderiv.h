@@ -69,6 +69,11 @@ typedef struct {
     double quad_step;       /* first refined step of the trapezoidal rule in log(y) used for
                                sgn(T_k) e_1 (halved until two levels agree to 1e-10),
                                default 0.1 */
+    int step_timing;        /* 1: time every Lanczos kernel with events (ovd_stats.ms_stencil,
+                               ms_update); 0 (default): only the totals */
+    int use_graph;          /* 1 (default): the k Lanczos steps of a call are recorded once
+                               into a HIP graph (per shape and workspace) and replayed;
+                               0: launched one by one */
 } ovd_options;
 
 typedef struct {

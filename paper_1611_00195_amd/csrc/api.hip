@@ -56,6 +56,14 @@ struct ovd_lattice {
     TslCoeffs last_co{};
     // event pool for per-kernel timing of the Lanczos loop
     std::vector<hipEvent_t> ev;
+    // recorded Lanczos loops (HIP graphs), keyed by everything baked into them
+    struct GraphEntry {
+        std::vector<uintptr_t> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;   // capture only; replays run on `stream`
 };
 
 namespace {
@@ -249,32 +257,78 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
                             hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipMemcpy2DAsync(Ws(1), sizeof(cpx<T>) * sW, src_w, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
                             hipMemcpyDeviceToDevice, h->stream));
-    for (int j = 0; j < k; ++j) {
-        StepPtrs p{};
-        if (j > 0) {
-            p.Xv = Us(j); p.sXv = fsz;
-            p.Yv = Vs(j); p.sYv = sV;
-            p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
-            p.Xw = Zs(j); p.sXw = fsz;
-            p.Yw = Ws(j); p.sYw = sW;
-            p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = sW;
+    const bool timing = h->opt.step_timing != 0;
+    // the k steps: update (from the second step on) and stencil with the step's reductions
+    auto enqueue_steps = [&](hipStream_t stream) -> hipError_t {
+        for (int j = 0; j < k; ++j) {
+            StepPtrs p{};
+            if (j > 0) {
+                p.Xv = Us(j); p.sXv = fsz;
+                p.Yv = Vs(j); p.sYv = sV;
+                p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
+                p.Xw = Zs(j); p.sXw = fsz;
+                p.Yw = Ws(j); p.sYw = sW;
+                p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = sW;
+            }
+            p.outV = Vs(j + 1); p.sV = sV;
+            p.outU = Us(j + 1); p.sU = fsz;
+            p.outW = Ws(j + 1); p.sW = sW;
+            p.outZ = Zs(j + 1); p.sZ = fsz;
+            p.xproj = xproj;
+            p.sx = (long long)12 * g.Vp;
+            if (j > 0) {
+                if (timing) (void)hipEventRecord(h->ev[4 * j], stream);
+                launch_tsl_update<T>(nrhs, j == 1 ? 2 : 3, fsz, p, st, stream);
+                if (timing) (void)hipEventRecord(h->ev[4 * j + 1], stream);
+            }
+            if (timing) (void)hipEventRecord(h->ev[4 * j + 2], stream);
+            launch_tsl_stencil<T>(g, dir, nrhs, p, U, dU, md, st, co, partials, counters, j,
+                                  h->opt.breakdown_tol, stream);
+            if (timing) (void)hipEventRecord(h->ev[4 * j + 3], stream);
         }
-        p.outV = Vs(j + 1); p.sV = sV;
-        p.outU = Us(j + 1); p.sU = fsz;
-        p.outW = Ws(j + 1); p.sW = sW;
-        p.outZ = Zs(j + 1); p.sZ = fsz;
-        p.xproj = xproj;
-        p.sx = (long long)12 * g.Vp;
-        if (j > 0) {
-            HIPCHK(hipEventRecord(h->ev[4 * j], h->stream));
-            launch_tsl_update<T>(nrhs, j == 1 ? 2 : 3, fsz, p, st, h->stream);
-            HIPCHK(hipEventRecord(h->ev[4 * j + 1], h->stream));
+        return hipGetLastError();
+    };
+    bool launched = false;
+    if (h->opt.use_graph && !timing) {
+        double tau = h->opt.breakdown_tol;
+        uint64_t tb, mb;
+        std::memcpy(&tb, &tau, 8);
+        std::memcpy(&mb, &md, 8);
+        const std::vector<uintptr_t> key = {
+            sizeof(T), (uintptr_t)dir, (uintptr_t)nrhs, (uintptr_t)k, (uintptr_t)ring, (uintptr_t)basis,
+            (uintptr_t)basis_w, (uintptr_t)xproj, (uintptr_t)U, (uintptr_t)dU, (uintptr_t)st, (uintptr_t)coef,
+            (uintptr_t)partials, (uintptr_t)counters, (uintptr_t)tb, (uintptr_t)mb, (uintptr_t)g.V};
+        hipGraphExec_t exec = nullptr;
+        for (auto& e : h->graphs)
+            if (e.key == key) exec = e.exec;
+        if (!exec) {
+            if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+            const hipError_t le = enqueue_steps(h->cap_stream);
+            const hipError_t ce = hipStreamEndCapture(h->cap_stream, &graph);
+            if (le != hipSuccess || ce != hipSuccess || !graph) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(h, OVD_EHIP, std::string("recording the Lanczos steps into a graph failed: ") +
+                                             hipGetErrorString(le != hipSuccess ? le : ce));
+            }
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return fail(h, OVD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+            if (h->graphs.size() >= 8) {   // keep a few shapes; drop the oldest
+                (void)hipStreamSynchronize(h->stream);
+                (void)hipGraphExecDestroy(h->graphs.front().exec);
+                (void)hipGraphDestroy(h->graphs.front().graph);
+                h->graphs.erase(h->graphs.begin());
+            }
+            h->graphs.push_back({key, graph, exec});
         }
-        HIPCHK(hipEventRecord(h->ev[4 * j + 2], h->stream));
-        launch_tsl_stencil<T>(g, dir, nrhs, p, U, dU, md, st, co, partials, counters, j,
-                              h->opt.breakdown_tol, h->stream);
-        HIPCHK(hipEventRecord(h->ev[4 * j + 3], h->stream));
+        HIPCHK(hipGraphLaunch(exec, h->stream));
+        launched = true;
     }
+    if (!launched) HIPCHK(enqueue_steps(h->stream));
     HIPCHK(hipGetLastError());
     tl.stop(h->stream);
 
@@ -300,7 +354,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         stats->min_margin = minm;
         stats->ms_lanczos = tl.ms();
         double msu = 0.0, mss = 0.0;
-        for (int j = 0; j < k; ++j) {
+        for (int j = 0; j < (timing ? k : 0); ++j) {
             float t = 0.f;
             if (j > 0 && hipEventElapsedTime(&t, h->ev[4 * j], h->ev[4 * j + 1]) == hipSuccess) msu += t;
             if (hipEventElapsedTime(&t, h->ev[4 * j + 2], h->ev[4 * j + 3]) == hipSuccess) mss += t;
@@ -562,6 +616,8 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.left_start = OVD_LEFT_SUM;
     h->opt.breakdown_tol = 1e-14;
     h->opt.quad_step = 0.1;
+    h->opt.step_timing = 0;
+    h->opt.use_graph = 1;
     if (opt) {
         h->opt = *opt;
         if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
@@ -581,6 +637,11 @@ ovd_status ovd_destroy(ovd_h h) {
     (void)hipStreamSynchronize(h->stream);
     for (auto& kv : h->ws) (void)hipFree(kv.second.first);
     for (auto e : h->ev) (void)hipEventDestroy(e);
+    for (auto& e : h->graphs) {
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
+    }
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->U64) (void)hipFree(h->U64);
     if (h->U32) (void)hipFree(h->U32);
     ovd_clear_deflation(h);

@@ -45,7 +45,8 @@ class Breakdown(OvdError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("left_start", ctypes.c_int),
-                ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double)]
+                ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
+                ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class _Dir(ctypes.Structure):
@@ -134,7 +135,7 @@ class Lattice:
     workspaces live on the current device."""
 
     def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
-                 breakdown_tol=1e-14, quad_step=0.1, stream=None):
+                 breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True):
         self.dims = tuple(int(d) for d in dims)
         self.V = 1
         for d in self.dims:
@@ -144,7 +145,7 @@ class Lattice:
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
-        opt = _Options(precision, left_start, breakdown_tol, quad_step)
+        opt = _Options(precision, left_start, breakdown_tol, quad_step, int(bool(step_timing)), int(bool(use_graph)))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
