@@ -70,15 +70,19 @@ def dwv_bytes_per_site(prec_bytes: int) -> float:
     return (12 + 36 + 12) * 2 * prec_bytes
 
 
-def time_form(args, U, prec, n, steps, warmup, V):
-    """Time `steps` batched derivative evaluations of n sources at one precision."""
+def time_form(args, U, prec, n, steps, warmup, V, step_timing=False):
+    """Time `steps` batched derivative evaluations of n sources at one precision.
+
+    step_timing=False: the production path (the k Lanczos steps replayed as one
+    HIP graph).  step_timing=True: launched one by one with HIP events around
+    every stencil and update kernel on the library's stream, for the roofline."""
     import torch
 
     import synth
     from paper_1611_00195_amd import ovderiv
 
     dims = tuple(args.dims)
-    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, step_timing=step_timing)
     lat.set_links(U)
     b = torch.from_numpy(synth.make_sources(dims, n, 4000)).cuda()
     x = torch.from_numpy(synth.make_sources(dims, n, 5000)).cuda()
@@ -118,9 +122,11 @@ def run_gpu(args):
     prec = ovderiv.MIXED if args.precision == "mixed" else ovderiv.FP64
     n = args.nrhs
     main = time_form(args, U, prec, n, args.steps, args.warmup, V)
+    # roofline: the same workload launched kernel by kernel with events
+    prof = time_form(args, U, prec, n, max(1, min(args.steps, 2)), 0, V, step_timing=True)
     pb = 4 if prec == ovderiv.MIXED else 8
-    st_ms = main["ms_stencil"] / args.k                   # average stencil launch
-    up_ms = main["ms_update"] / (args.k - 1)              # average update launch
+    st_ms = prof["ms_stencil"] / args.k                   # average stencil launch
+    up_ms = prof["ms_update"] / (args.k - 1)              # average update launch
     bytes_launch = stencil_bytes_per_site(pb, n) * V * n
     achieved = bytes_launch / (st_ms * 1e-3) / 1e9
     up_bytes = update_bytes_per_site(pb) * V * n
@@ -128,6 +134,7 @@ def run_gpu(args):
         "evals_per_s": main["evals_per_s"],
         "ms_per_step": main["ms_per_step"],
         "ms_lanczos_per_step": main["ms_lanczos"],
+        "ms_lanczos_per_step_kernel_by_kernel": prof["ms_lanczos"],
         "ms_small_sign_per_step": main["ms_small_sign"],
         "roofline": {
             "bound": "hbm",
@@ -162,6 +169,8 @@ def run_gpu(args):
             "mixed_vs_fp64_max_rel_err_xdy": err,
         }
     out["forms"] = forms
+    if not args.skip_forms:
+        out["vjp"] = time_vjp(args, U, V)
     # Dw.v bandwidth: nrhs fields per launch so that the traffic exceeds the 256 MB MALL
     nd = args.dwv_nrhs
     src = torch.from_numpy(synth.make_sources(dims, 1, 6000)).cuda().repeat(nd, 1, 1, 1).contiguous()
@@ -182,6 +191,34 @@ def run_gpu(args):
         l2.close()
     out["dw_v"] = dw
     return out
+
+
+def time_vjp(args, U, V):
+    """The gradient of s = <x|sgn(H)|b> w.r.t. mu and all 4 V links (FP64, one
+    source pair, both Krylov bases stored): calls per second and the MFMA rate
+    of the Z = W M'^dag product (8 N k^2 flops)."""
+    import torch
+
+    import synth
+    from paper_1611_00195_amd import ovderiv
+
+    dims = tuple(args.dims)
+    lat = ovderiv.Lattice(dims, m0=args.m0)
+    lat.set_links(U)
+    b = torch.from_numpy(synth.make_sources(dims, 1, 4000)).cuda()
+    x = torch.from_numpy(synth.make_sources(dims, 1, 5000)).cuda()
+    lat.sign_apply_vjp(x, b, args.mu, args.k, force=True, wirtinger=True)
+    torch.cuda.synchronize()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s, dsdmu, F, _, _ = lat.sign_apply_vjp(x, b, args.mu, args.k, force=True, wirtinger=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    lat.close()
+    return {"calls_per_s": round(1.0 / dt, 3), "ms_per_call": round(1e3 * dt, 2), "s": [s.real, s.imag],
+            "ds_dmu": [dsdmu.real, dsdmu.imag], "precision": "fp64", "k": args.k,
+            "zgemm_flops": 8.0 * 12 * V * args.k ** 2}
 
 
 def counters_run(args):
@@ -310,6 +347,7 @@ def main():
             "update_kernel": g["update_kernel"],
             "forms": g["forms"],
             "dw_v": g["dw_v"],
+            "vjp": g.get("vjp"),
             "min_margin": g["min_margin"],
             "sign_check": g["sign_check"],
             "xdy_first": g["xdy0"],

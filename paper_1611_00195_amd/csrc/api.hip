@@ -289,7 +289,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         return hipGetLastError();
     };
     bool launched = false;
-    if (h->opt.use_graph && !timing) {
+    if (h->opt.use_graph && !timing) {   // per-kernel events are not recorded into graphs
         double tau = h->opt.breakdown_tol;
         uint64_t tb, mb;
         std::memcpy(&tb, &tau, 8);

@@ -125,3 +125,24 @@ def test_autograd_against_oracle_and_finite_differences():
     eb = cn(*b.shape)
     check(np.sum(np.conj(host(bt.grad)) * eb).real, (c * np.vdot(Sx, eb.ravel())).real,
           (L(U, MU, x, b + h * eb) - L(U, MU, x, b - h * eb)) / (2 * h))
+
+
+def test_vjp_dsdmu_agrees_with_block_derivative():
+    """Two different GPU routes to d<x|sgn(H)|b>/dmu: the bilinear gradient
+    (one Lanczos run with left start x, Frechet derivative of sgn(T_k)) and the
+    block-matrix derivative of eq. 6-7 projected on x (storage-free mode).  On
+    smooth links (eps = 0.4, as at the benchmark size) both have converged at
+    k = 400 and must agree; the block route's own change from k = 300 to 400
+    bounds its truncation error."""
+    from gpu_helpers import dev, print_case
+    dims = (6, 6, 6, 6)
+    print_case(test="vjp_vs_block", dims=dims)
+    U = synth.make_links(dims, 0.4, 521)
+    x = synth.make_source(dims, 522)
+    b = synth.make_source(dims, 523)
+    lat = _lat(dims, U)
+    _, dm, _, _, _ = lat.sign_apply_vjp(dev(x[None]), dev(b[None]), MU, 400, force=False)
+    vals = [lat.sign_apply_deriv(dev(b[None]), MU, k, x=dev(x[None]), want_vectors=False)[2][0] for k in (300, 400)]
+    trunc = abs(vals[1] - vals[0])
+    assert trunc < 1e-8 * abs(vals[1])
+    assert abs(dm - vals[1]) < 1e-8 * abs(vals[1])
