@@ -52,7 +52,8 @@ typedef enum {
     OVD_EHIP = -3,        /* a HIP runtime call failed */
     OVD_EBREAKDOWN = -4,  /* serious Lanczos breakdown: |w^dag v| <= tau |w| |v| */
     OVD_ENODEFL = -5,     /* deflation requested for a mu with no deflation set */
-    OVD_ENAN = -6         /* non-finite value detected in the recurrence */
+    OVD_ENAN = -6,        /* non-finite value detected in the recurrence */
+    OVD_ENOCONV = -7      /* an iterative solver (eigenpairs, shifted solves) did not converge */
 } ovd_status;
 
 enum { OVD_FP64 = 0, OVD_MIXED = 1 };        /* precision of Krylov vectors and stencil */
@@ -138,6 +139,45 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
 ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam,
                              const void* R, const void* L, int l,
                              const void* dR, const void* dL, const ovd_dir* dir);
+/* Statistics of ovd_compute_deflation. */
+typedef struct {
+    int outer_right, outer_left;      /* filtered subspace iterations on H(mu) and H(-mu) = H(mu)^dag */
+    double max_res_right, max_res_left; /* max |H r - lambda r| (|r| = 1) of the m pairs, both sides */
+    double max_biorth;                /* max |L^dag R - 1| */
+    int gmres_iters;                  /* total GMRES iterations of the 2 l derivative solves */
+    double max_gmres_res;             /* largest relative residual of those solves */
+    double ms;                        /* wall time */
+} ovd_eig_stats;
+
+/* Compute and install the deflation set of mu on the GPU (Sec. 3): the m
+ * eigenvalues of H(mu) closest to zero (smallest |lambda|) with right and left
+ * eigenvectors normalised to L^dag R = 1 (eq. 8), and for the first l of them
+ * the derivatives dR, dL along dir (mu or a link direction) that the
+ * generalised deflation of eq. 9-11 needs, in the gauge L_j^dag dR_j = 0,
+ * dL_j^dag R_j = 0:
+ *   dR_j = sum_{i != j} R_i (L_i^dag dH R_j)/(lambda_j - lambda_i) + (lambda_j - H)^{-1} (1 - P) dH R_j
+ *   dL_j = sum_{i != j} L_i conj((L_j^dag dH R_i)/(lambda_j - lambda_i)) + (conj(lambda_j) - H^dag)^{-1} (1 - P)^dag dH^dag L_j
+ * with P = sum_{i<m} R_i L_i^dag and the resolvents taken on the range of 1 - P.
+ * Method: Chebyshev-filtered subspace iteration on H^2 (and H^dag^2) with
+ * Rayleigh-Ritz on H, FP64; restarted GMRES for the shifted solves.
+ *   tol   residual bound |H r - lambda r| for |r| = 1 (<= 0: 1e-10)
+ *   lam   host double[2 m] (re, im), increasing |lambda|, or NULL
+ * The set replaces any set of the same mu, exactly as ovd_set_deflation.
+ * Errors: OVD_EINVAL (m < 1, l > m, m > 512, bad dir), OVD_ENOCONV (not
+ * converged, or a cluster of eigenvalues straddles the m-th one, or
+ * degenerate eigenvalues among the first l), OVD_ENOMEM, OVD_EHIP.  Needs about
+ * (8 (m + max(16, m/2)) + 5 m) 12 V complex128 of device memory while it runs. */
+ovd_status ovd_compute_deflation(ovd_h h, double mu, int m, int l, const ovd_dir* dir, double tol,
+                                 double* lam, ovd_eig_stats* st);
+
+/* Read back the deflation set of mu (as installed by ovd_set_deflation or
+ * ovd_compute_deflation).  m, l: host int or NULL; lam: host double[2 m] or
+ * NULL; R, L: device complex128 [m][V][4][3] or NULL; dR, dL: device
+ * complex128 [l][V][4][3] or NULL.  OVD_ENODEFL if there is no set for mu.
+ * Call once with only m and l to size the buffers. */
+ovd_status ovd_get_deflation(ovd_h h, double mu, int* m, int* l, double* lam, void* R, void* L,
+                             void* dR, void* dL);
+
 ovd_status ovd_clear_deflation(ovd_h h);
 
 /* y = sgn(H(mu)) b by k steps of two-sided Lanczos with left start equal to

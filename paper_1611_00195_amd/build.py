@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libovderiv.so")
-SOURCES = ["api.hip", "kernels_stencil.hip", "kernels_misc.hip", "kernels_small.hip", "kernels_defl.hip"]
+SOURCES = ["api.hip", "kernels_stencil.hip", "kernels_misc.hip", "kernels_small.hip", "kernels_defl.hip", "eigs.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are switched off: hipcc would otherwise form them

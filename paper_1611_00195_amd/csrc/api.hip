@@ -748,6 +748,62 @@ ovd_status ovd_get_tridiag(ovd_h h, int rhs, int k, double* alpha, double* beta,
     return OVD_OK;
 }
 
+}  // extern "C"
+
+// finish a deflation set whose vectors are on the device: upload sgn(lambda),
+// check L^dag R = 1, replace any set of the same mu
+template <typename Release>
+ovd_status install_defl(ovd_h h, DeflSet& d, const std::vector<double>& sg, const std::vector<double>& on,
+                        Release release) {
+    ovd_status wst = OVD_OK;
+    const int m = d.m;
+    const long long nf = (long long)12 * h->g.Vp;
+    const double mu = d.mu;
+    (void)hipMemcpyAsync(d.sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->stream);
+    (void)hipMemcpyAsync(d.ones, on.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->stream);
+    // biorthonormality L^dag R = 1 (checked on the device, FP64)
+    c64* G = (c64*)ws_get(h, "defl_gram", sizeof(c64) * (size_t)m * m, &wst);
+    c64* scr = (c64*)ws_get(h, "defl_scr", sizeof(c64) * defl_proj_scratch(m, m, nf), &wst);
+    if (!G || !scr) {
+        release();
+        return wst;
+    }
+    launch_defl_proj(d.L, nf, m, d.R, nf, m, nf, G, scr, h->stream);
+    std::vector<c64> hg((size_t)m * m);
+    if (hipMemcpyAsync(hg.data(), G, sizeof(c64) * m * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        release();
+        return fail(h, OVD_EHIP, "deflation set upload failed");
+    }
+    double dev = 0.0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            const c64 e = hg[(size_t)i * m + j] - c64{i == j ? 1.0 : 0.0, 0.0};
+            dev = std::max(dev, std::sqrt(norm2(e)));
+        }
+    if (!(dev <= 1e-8)) {
+        release();
+        return fail(h, OVD_EINVAL, "deflation vectors are not biorthonormal: max |L^dag R - 1| = " + std::to_string(dev));
+    }
+    for (auto it = h->defl.begin(); it != h->defl.end(); ++it) {
+        if (std::fabs(it->mu - mu) <= 1e-12) {
+            (void)hipFree(it->R);
+            (void)hipFree(it->L);
+            if (it->dR) (void)hipFree(it->dR);
+            if (it->dL) (void)hipFree(it->dL);
+            (void)hipFree(it->sgn);
+            (void)hipFree(it->ones);
+            h->defl.erase(it);
+            break;
+        }
+    }
+    h->defl.push_back(d);
+    return OVD_OK;
+}
+
+
+extern "C" {
+
 ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const void* R, const void* L, int l,
                              const void* dR, const void* dL, const ovd_dir* dir) {
     if (!h) return OVD_EINVAL;
@@ -792,45 +848,96 @@ ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const
         launch_pack_spinor<double>(g, l, dR, d.dR, nf, h->stream);
         launch_pack_spinor<double>(g, l, dL, d.dL, nf, h->stream);
     }
-    (void)hipMemcpyAsync(d.sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->stream);
-    (void)hipMemcpyAsync(d.ones, on.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->stream);
-    // biorthonormality L^dag R = 1 (checked on the device, FP64)
-    c64* G = (c64*)ws_get(h, "defl_gram", sizeof(c64) * (size_t)m * m, &wst);
-    c64* scr = (c64*)ws_get(h, "defl_scr", sizeof(c64) * defl_proj_scratch(m, m, nf), &wst);
-    if (!G || !scr) {
-        release();
-        return wst;
+    return install_defl(h, d, sg, on, release);
+}
+
+ovd_status ovd_compute_deflation(ovd_h h, double mu, int m, int l, const ovd_dir* dir, double tol, double* lam,
+                                 ovd_eig_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (m < 1 || l < 0 || l > m || m > 512) return fail(h, OVD_EINVAL, "bad ovd_compute_deflation arguments");
+    if (st) std::memset(st, 0, sizeof(*st));
+    int dk = 1;
+    if (l > 0) {
+        s = upload_dir(h, dir, &dk);
+        if (s != OVD_OK) return s;
     }
-    launch_defl_proj(d.L, nf, m, d.R, nf, m, nf, G, scr, h->stream);
-    std::vector<c64> hg((size_t)m * m);
-    if (hipMemcpyAsync(hg.data(), G, sizeof(c64) * m * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess) {
-        release();
-        return fail(h, OVD_EHIP, "deflation set upload failed");
+    EigParams P;
+    P.g = h->g;
+    P.U = h->U64;
+    P.dU = h->dU64;
+    P.md = h->m0 + 4.0 * h->r;
+    P.mu = mu;
+    P.m = m;
+    P.l = l;
+    P.dir_link = dk == 2;
+    if (tol > 0) P.tol = tol;
+    P.stream = h->stream;
+    EigResult R;
+    const int rc = eigs_compute(P, R);
+    if (st) {
+        st->outer_right = R.outer_right;
+        st->outer_left = R.outer_left;
+        st->max_res_right = R.res_right;
+        st->max_res_left = R.res_left;
+        st->max_biorth = R.biorth;
+        st->gmres_iters = R.gmres_iters;
+        st->max_gmres_res = R.gmres_res;
+        st->ms = R.ms;
     }
-    double dev = 0.0;
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-            const c64 e = hg[(size_t)i * m + j] - c64{i == j ? 1.0 : 0.0, 0.0};
-            dev = std::max(dev, std::sqrt(norm2(e)));
+    if (rc != 0) {
+        for (void* q : {(void*)R.R, (void*)R.L, (void*)R.dR, (void*)R.dL})
+            if (q) (void)hipFree(q);
+        const ovd_status code = rc == -2 ? OVD_ENOMEM : rc == -3 ? OVD_EHIP : OVD_ENOCONV;
+        return fail(h, code, R.err);
+    }
+    DeflSet d;
+    d.mu = mu;
+    d.m = m;
+    d.l = l;
+    d.dir_kind = dk == 2 ? OVD_DIR_LINK : OVD_DIR_MU;
+    d.lam = R.lam;
+    d.R = R.R;
+    d.L = R.L;
+    d.dR = R.dR;
+    d.dL = R.dL;
+    std::vector<double> sg(m), on(m, 1.0);
+    for (int i = 0; i < m; ++i) {
+        sg[i] = R.lam[i].re >= 0.0 ? 1.0 : -1.0;
+        if (lam) {
+            lam[2 * i] = R.lam[i].re;
+            lam[2 * i + 1] = R.lam[i].im;
         }
-    if (!(dev <= 1e-8)) {
+    }
+    auto release = [&]() {
+        for (void* q : {(void*)d.R, (void*)d.L, (void*)d.dR, (void*)d.dL, (void*)d.sgn, (void*)d.ones})
+            if (q) (void)hipFree(q);
+    };
+    if (hipMalloc(&d.sgn, sizeof(double) * m) != hipSuccess || hipMalloc(&d.ones, sizeof(double) * m) != hipSuccess) {
         release();
-        return fail(h, OVD_EINVAL, "deflation vectors are not biorthonormal: max |L^dag R - 1| = " + std::to_string(dev));
+        return fail(h, OVD_ENOMEM, "device allocation of the deflation set failed");
     }
-    for (auto it = h->defl.begin(); it != h->defl.end(); ++it) {
-        if (std::fabs(it->mu - mu) <= 1e-12) {
-            (void)hipFree(it->R);
-            (void)hipFree(it->L);
-            if (it->dR) (void)hipFree(it->dR);
-            if (it->dL) (void)hipFree(it->dL);
-            (void)hipFree(it->sgn);
-            (void)hipFree(it->ones);
-            h->defl.erase(it);
-            break;
+    return install_defl(h, d, sg, on, release);
+}
+
+ovd_status ovd_get_deflation(ovd_h h, double mu, int* m, int* l, double* lam, void* R, void* L, void* dR, void* dL) {
+    if (!h) return OVD_EINVAL;
+    const DeflSet* d = find_defl(h, mu);
+    if (!d) return fail(h, OVD_ENODEFL, "no deflation set for this mu");
+    if (m) *m = d->m;
+    if (l) *l = d->l;
+    if (lam)
+        for (int i = 0; i < d->m; ++i) {
+            lam[2 * i] = d->lam[i].re;
+            lam[2 * i + 1] = d->lam[i].im;
         }
-    }
-    h->defl.push_back(d);
+    const long long nf = (long long)12 * h->g.Vp;
+    if (R) launch_unpack_spinor<double>(h->g, d->m, d->R, nf, R, h->stream);
+    if (L) launch_unpack_spinor<double>(h->g, d->m, d->L, nf, L, h->stream);
+    if (dR && d->l > 0) launch_unpack_spinor<double>(h->g, d->l, d->dR, nf, dR, h->stream);
+    if (dL && d->l > 0) launch_unpack_spinor<double>(h->g, d->l, d->dL, nf, dL, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
     return OVD_OK;
 }
 

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <string>
+#include <vector>
 
 namespace ovd {
 
@@ -192,5 +194,32 @@ void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t 
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
                       double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s);
 void launch_sum_c64(int n, const c64* v, c64* out, hipStream_t s);
+
+// eigenpairs of smallest |lambda| and eigenvector derivatives for deflation (eigs.hip)
+struct EigParams {
+    Geom g;
+    const c64* U = nullptr;     // FP64 internal links
+    const c64* dU = nullptr;    // FP64 internal link direction (dir_link)
+    double md = 0.0;            // m0 + 4 r
+    double mu = 0.0;
+    int m = 0, l = 0, p = 0;    // pairs, derivative pairs, subspace size (0: m + max(16, m/2))
+    bool dir_link = false;
+    double tol = 1e-10;         // residual |H r - theta r| of the wanted pairs
+    int max_outer = 80, degree = 80;
+    double gmres_tol = 1e-11;
+    int gmres_max = 4000;
+    uint64_t seed = 1611;
+    hipStream_t stream = nullptr;
+};
+struct EigResult {
+    std::vector<c64> lam;                 // m eigenvalues, increasing |lambda|
+    c64 *R = nullptr, *L = nullptr;       // device [m][12][Vp], caller frees
+    c64 *dR = nullptr, *dL = nullptr;     // device [l][12][Vp] or null, caller frees
+    int outer_right = 0, outer_left = 0, gmres_iters = 0;
+    double res_right = 0, res_left = 0, biorth = 0, gmres_res = 0, ms = 0;
+    std::string err;
+};
+// 0 on success; -2 allocation, -3 HIP error, -7 no convergence (err says why)
+int eigs_compute(const EigParams& p, EigResult& out);
 
 }  // namespace ovd

@@ -20,7 +20,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("OVDERIV_LIB", os.path.join(_HERE, "libovderiv.so"))
 
-OVD_OK, OVD_EINVAL, OVD_ENOMEM, OVD_EHIP, OVD_EBREAKDOWN, OVD_ENODEFL, OVD_ENAN = 0, -1, -2, -3, -4, -5, -6
+OVD_OK, OVD_EINVAL, OVD_ENOMEM, OVD_EHIP, OVD_EBREAKDOWN, OVD_ENODEFL, OVD_ENAN, OVD_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 LEFT_SUM, LEFT_SAME = 0, 1
 DIR_MU, DIR_LINK = 0, 1
@@ -29,7 +29,8 @@ OP_H, OP_DW, OP_DH_DMU, OP_DH_DLINK = 0, 1, 2, 3
 EXPORTS = [
     "ovd_create_lattice", "ovd_destroy", "ovd_last_error", "ovd_set_stream", "ovd_set_links",
     "ovd_apply_op", "ovd_set_deflation", "ovd_clear_deflation", "ovd_sign_apply",
-    "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag",
+    "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag", "ovd_compute_deflation",
+    "ovd_get_deflation",
 ]
 
 
@@ -47,6 +48,13 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("left_start", ctypes.c_int),
                 ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
                 ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class _EigStats(ctypes.Structure):
+    _fields_ = [("outer_right", ctypes.c_int), ("outer_left", ctypes.c_int),
+                ("max_res_right", ctypes.c_double), ("max_res_left", ctypes.c_double),
+                ("max_biorth", ctypes.c_double), ("gmres_iters", ctypes.c_int),
+                ("max_gmres_res", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 class _Dir(ctypes.Structure):
@@ -88,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ovd_apply_op": (i, [vp, i, d, ctypes.POINTER(_Dir), i, vp, vp, dp]),
         "ovd_set_deflation": (i, [vp, d, i, dp, vp, vp, i, vp, vp, ctypes.POINTER(_Dir)]),
         "ovd_clear_deflation": (i, [vp]),
+        "ovd_get_deflation": (i, [vp, d, ctypes.POINTER(i), ctypes.POINTER(i), dp, vp, vp, vp, vp]),
+        "ovd_compute_deflation": (i, [vp, d, i, i, ctypes.POINTER(_Dir), d, dp, ctypes.POINTER(_EigStats)]),
         "ovd_sign_apply": (i, [vp, i, dp, i, vp, vp, ctypes.POINTER(_Stats)]),
         "ovd_sign_apply_deriv": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, vp, dp, ctypes.POINTER(_Stats)]),
         "ovd_sign_apply_vjp": (i, [vp, d, i, vp, vp, dp, dp, vp, vp, vp, ctypes.POINTER(_Stats)]),
@@ -282,6 +292,35 @@ class Lattice:
         d = _Dir(DIR_LINK if direction in ("link", DIR_LINK) else DIR_MU, None)
         self._call("ovd_set_deflation", float(mu), m, lam_c, _ptr(R), _ptr(L), int(l),
                    _ptr(dR) if l > 0 else None, _ptr(dL) if l > 0 else None, ctypes.byref(d))
+
+    def compute_deflation(self, mu, m, l=0, direction="mu", dU=None, tol=1e-10):
+        """Eigenpairs of smallest |lambda| (and derivatives of the first l) on the
+        GPU, installed as the deflation set of mu.  Returns (lam, stats)."""
+        dirs, keep = self._dir(direction if l > 0 else None, dU)
+        lam = (ctypes.c_double * (2 * m))()
+        st = _EigStats()
+        self._call("ovd_compute_deflation", float(mu), int(m), int(l), ctypes.byref(dirs), float(tol), lam,
+                   ctypes.byref(st))
+        import numpy as np
+        lv = np.array([complex(lam[2 * i], lam[2 * i + 1]) for i in range(m)])
+        stats = {f: getattr(st, f) for f, _ in _EigStats._fields_}
+        return lv, stats
+
+    def get_deflation(self, mu):
+        """(lam, R, L, dR, dL) of the deflation set of mu; dR, dL None if l = 0."""
+        m, l = ctypes.c_int(0), ctypes.c_int(0)
+        self._call("ovd_get_deflation", float(mu), ctypes.byref(m), ctypes.byref(l), None, None, None, None, None)
+        m, l = m.value, l.value
+        lam = (ctypes.c_double * (2 * m))()
+        opts = dict(dtype=torch.complex128, device="cuda")
+        R = torch.empty((m, self.V, 4, 3), **opts)
+        L = torch.empty((m, self.V, 4, 3), **opts)
+        dR = torch.empty((l, self.V, 4, 3), **opts) if l > 0 else None
+        dL = torch.empty((l, self.V, 4, 3), **opts) if l > 0 else None
+        self._call("ovd_get_deflation", float(mu), None, None, lam, _ptr(R), _ptr(L), _ptr(dR), _ptr(dL))
+        import numpy as np
+        lv = np.array([complex(lam[2 * i], lam[2 * i + 1]) for i in range(m)])
+        return lv, R, L, dR, dL
 
     def clear_deflation(self):
         self._call("ovd_clear_deflation")
