@@ -256,8 +256,49 @@ struct SideResult {
     double max_res = 0.0;
 };
 
-// subspace iteration for one side (mu or -mu); the m converged Ritz vectors
-// are left in Out (m fields, unit norm)
+// sort the eigenpairs (w, S) of a p x p projected matrix by |w| (S columns)
+void sort_by_modulus(int p, std::vector<cd>& w, std::vector<cd>& S) {
+    std::vector<int> ord(p);
+    for (int i = 0; i < p; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int i, int j) { return std::abs(w[i]) < std::abs(w[j]); });
+    std::vector<cd> Ss((size_t)p * p), ws(p);
+    for (int j = 0; j < p; ++j) {
+        ws[j] = w[ord[j]];
+        for (int i = 0; i < p; ++i) Ss[(size_t)i * p + j] = S[(size_t)i * p + ord[j]];
+    }
+    w.swap(ws);
+    S.swap(Ss);
+}
+
+// residual norms |(W - Q G) s_j| (Q orthonormal, G = Q^dag W) of the first n columns of S
+bool ritz_residuals(Ctx& c, const c64* Q, const c64* W, c64* Z, int p, const std::vector<cd>& G,
+                    const std::vector<cd>& S, int n, std::vector<double>& res) {
+    if (!c.copy(Z, W, p)) return false;
+    std::vector<cd> mG(G.size());
+    for (size_t i = 0; i < G.size(); ++i) mG[i] = -G[i];
+    if (!c.comb(Q, p, mG, p, Z)) return false;
+    std::vector<cd> E;
+    if (!c.proj(Z, p, Z, p, E)) return false;
+    res.assign(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        cd acc = 0.0;
+        for (int i = 0; i < p; ++i) {
+            cd t = 0.0;
+            for (int k = 0; k < p; ++k) t += E[(size_t)i * p + k] * S[(size_t)k * p + j];
+            acc += std::conj(S[(size_t)i * p + j]) * t;
+        }
+        res[j] = std::sqrt(std::max(0.0, acc.real()));
+    }
+    return true;
+}
+
+// Subspace iteration for one side (mu or -mu).  The filter and the subspace
+// update use Rayleigh-Ritz with H^2, whose wanted eigenvalues lambda^2 are at
+// the edge of its spectrum (Rayleigh-Ritz with H itself would produce spurious
+// Ritz values near zero from mixtures of eigenvectors of opposite sign); the
+// m best vectors are then projected with H to separate lambda from -lambda and
+// to measure the residual |H r - lambda r|.  The m eigenvectors of H end up in
+// Out (unit norm), increasing |lambda|.
 bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, int degree, uint64_t seed, c64* Out,
                    SideResult& sr) {
     c64* X = c.fields(p);
@@ -265,7 +306,10 @@ bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, i
     c64* B1 = c.fields(p);
     c64* B2 = c.fields(p);
     c64* T = c.fields(p);
-    if (!X || !B0 || !B1 || !B2 || !T) return false;
+    c64* Qm = c.fields(m);
+    c64* Wm = c.fields(m);
+    c64* Zm = c.fields(m);
+    if (!X || !B0 || !B1 || !B2 || !T || !Qm || !Wm || !Zm) return false;
     {
         const long long ne = (long long)p * c.nf;
         fill_random_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, c.s>>>(ne, c.nf, c.g.V, c.g.Vp, seed, X);
@@ -276,63 +320,67 @@ bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, i
     const double hb = std::fabs(c.md) + 3.0 + std::exp(std::fabs(mu));
     const double b = 1.02 * hb * hb;
     double a = 0.25 * b;
+    double best = 1e300;
+    int best_it = 0;
     for (int it = 1; it <= max_outer; ++it) {
         c64* Y = nullptr;
         if (!cheb_filter(c, mu, X, B0, B1, B2, T, p, degree, a, b, &Y)) return false;
-        c64* Q = (Y == B0) ? B0 : (Y == B1 ? B1 : B2);
-        c64* Wb = (Q == B0) ? B1 : B0;     // H Q
-        c64* Zb = (Q == B2) ? B1 : B2;     // H Q - Q G
+        c64* Q = Y;
+        c64* Wb = (Q == B0) ? B1 : B0;     // H Q, then H^2 Q
+        c64* Zb = (Q == B2) ? B1 : B2;
         if (!orthonormalise(c, Q, T, p)) return false;
-        if (!c.apply(0, mu, Q, Wb, p)) return false;
-        std::vector<cd> G;
-        if (!c.proj(Q, p, Wb, p, G)) return false;
-        std::vector<cd> w, S;
-        if (!dense::eig_general(p, G, w, S)) {
+        if (!c.apply(0, mu, Q, T, p) || !c.apply(0, mu, T, Wb, p)) return false;
+        std::vector<cd> G2;
+        if (!c.proj(Q, p, Wb, p, G2)) return false;
+        std::vector<cd> w2, S2;
+        if (!dense::eig_general(p, G2, w2, S2)) {
             c.err = "QR iteration of the projected problem did not converge";
             return false;
         }
-        std::vector<int> ord(p);
-        for (int i = 0; i < p; ++i) ord[i] = i;
-        std::sort(ord.begin(), ord.end(), [&](int i, int j) { return std::abs(w[i]) < std::abs(w[j]); });
-        std::vector<cd> Ss((size_t)p * p), ws(p);
-        for (int j = 0; j < p; ++j) {
-            ws[j] = w[ord[j]];
-            for (int i = 0; i < p; ++i) Ss[(size_t)i * p + j] = S[(size_t)i * p + ord[j]];
-        }
-        // residual vectors Z = H Q - Q G, their Gram matrix E; |res_j|^2 = s_j^dag E s_j
-        if (!c.copy(Zb, Wb, p)) return false;
-        std::vector<cd> mG(G.size());
-        for (size_t i = 0; i < G.size(); ++i) mG[i] = -G[i];
-        if (!c.comb(Q, p, mG, p, Zb)) return false;
-        std::vector<cd> E;
-        if (!c.proj(Zb, p, Zb, p, E)) return false;
-        double rmax = 0.0;
-        for (int j = 0; j < m; ++j) {
-            cd acc = 0.0;
-            for (int i = 0; i < p; ++i) {
-                cd t = 0.0;
-                for (int k = 0; k < p; ++k) t += E[(size_t)i * p + k] * Ss[(size_t)k * p + j];
-                acc += std::conj(Ss[(size_t)i * p + j]) * t;
-            }
-            rmax = std::max(rmax, std::sqrt(std::max(0.0, acc.real())));
-        }
-        // Ritz vectors X = Q S (all p, ordered) as the next start
+        sort_by_modulus(p, w2, S2);
+        // next start: all p Ritz vectors of H^2
         if (!c.ok(hipMemsetAsync(X, 0, sizeof(c64) * (size_t)p * c.nf, c.s), "memset")) return false;
-        if (!c.comb(Q, p, Ss, p, X)) return false;
-        sr.theta.assign(ws.begin(), ws.begin() + m);
+        if (!c.comb(Q, p, S2, p, X)) return false;
+        // the m best: orthonormalise, project H, residuals |H r - lambda r|
+        if (!c.copy(Qm, X, m)) return false;
+        if (!orthonormalise(c, Qm, Zm, m)) return false;
+        if (!c.apply(0, mu, Qm, Wm, m)) return false;
+        std::vector<cd> G, w, S;
+        if (!c.proj(Qm, m, Wm, m, G)) return false;
+        if (!dense::eig_general(m, G, w, S)) {
+            c.err = "QR iteration of the projected problem did not converge";
+            return false;
+        }
+        sort_by_modulus(m, w, S);
+        std::vector<double> res;
+        if (!ritz_residuals(c, Qm, Wm, Zm, m, G, S, m, res)) return false;
+        const double rmax = *std::max_element(res.begin(), res.end());
+        sr.theta = w;
         sr.outer = it;
         sr.max_res = rmax;
         if (verbose()) {
             std::fprintf(stderr, "eigs mu=%+.3f outer %d: max residual %.3e, |lambda_m| %.6f, a %.4f\n", mu, it, rmax,
-                         std::abs(ws[m - 1]), a);
+                         std::abs(w[m - 1]), a);
             std::fflush(stderr);
         }
-        if (rmax <= tol) break;
-        // damp everything above the largest Ritz value of the subspace
-        a = std::max(std::norm(ws[p - 1]), 1e-6 * b);
+        // stagnation: no halving of the best residual in 20 outer iterations
+        if (rmax < 0.5 * best) {
+            best = rmax;
+            best_it = it;
+        }
+        const bool stalled = it - best_it >= 20;
+        if (rmax <= tol || it == max_outer || stalled) {
+            // eigenvectors r = Qm s (unit norm)
+            if (!c.ok(hipMemsetAsync(Out, 0, sizeof(c64) * (size_t)m * c.nf, c.s), "memset")) return false;
+            if (!c.comb(Qm, m, S, m, Out)) return false;
+            break;
+        }
+        // damp everything above the largest Ritz value of H^2 in the subspace
+        a = std::max(w2[p - 1].real(), 1e-6 * b);
         if (a >= b) a = 0.5 * b;
+        (void)Zb;
     }
-    return c.copy(Out, X, m);
+    return true;
 }
 
 // restarted GMRES for (shift - A) z = rhs on range(1 - P), P = sum R_i L_i^dag
