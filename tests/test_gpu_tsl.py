@@ -196,3 +196,45 @@ def test_free_field_converges_at_headline_size():
     print(f"free field 14^4 k={k}: sign error {e_f:.2e}, derivative error {e_d:.2e}")
     assert e_f < 1e-6
     assert e_d < 1e-4
+
+
+@pytest.mark.parametrize("nrhs", [5, 16])
+def test_batch_shapes_match_single_source(nrhs):
+    """Ragged (5) and XCD-split (16, a multiple of 8 >= 16) batches of the
+    derivative: every source's <x|dy> equals its single-source value, and the
+    first and last agree with the oracle."""
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k, mu = (4, 4, 4, 6), 40, 0.3
+    print_case(test="batch_shapes", dims=dims, k=k, nrhs=nrhs)
+    U, lat = _setup(dims, 0.5, 231)
+    b = synth.make_sources(dims, nrhs, 232)
+    x = synth.make_sources(dims, nrhs, 233)
+    mus = [mu + 0.01 * r for r in range(nrhs)]
+    y, dy, s = lat.sign_apply_deriv(dev(b), mus, k, x=dev(x))
+    for r in range(nrhs):
+        _, _, s1 = lat.sign_apply_deriv(dev(b[r:r + 1]), [mus[r]], k, x=dev(x[r:r + 1]), want_vectors=False)
+        assert abs(s[r] - s1[0]) < 1e-12 * abs(s1[0]), r
+    for r in (0, nrhs - 1):
+        h, hd, dh, dhd = ops(U, dims, mus[r])
+        dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[r].ravel(), k)
+        assert rel(host(dy)[r], dref) < 1e-10 and rel(host(y)[r], yref) < 1e-10
+
+
+def test_headline_size_first_steps():
+    """14 x 14^3: the first Lanczos coefficients of the block system (the
+    headline derivative, eq. 6-7) against the oracle's first steps at full size."""
+    from gpu_helpers import dev, ops, print_case
+    dims, k, mu = (14, 14, 14, 14), 6, 0.3
+    print_case(test="headline_first_steps", dims=dims, k=k)
+    U, lat = _setup(dims, 0.4, 1611)
+    b = synth.make_sources(dims, 1, 4000)
+    lat.sign_apply_deriv(dev(b), mu, k)
+    a, be, de = lat.get_tridiag(k)
+    h, hd, dh, dhd = ops(U, dims, mu)
+    n = b[0].size
+    op, op_h = tsl.block_ops(h, hd, dh, dhd, n)
+    psi = np.concatenate([np.zeros(n, complex), b[0].ravel()])
+    L = tsl.lanczos(op, op_h, psi, tsl.block_left_start(psi, n), k, keep_basis=False)
+    assert np.abs(np.array(a) - L["alpha"]).max() < 1e-11
+    assert np.abs(np.array(be[1:]) - L["beta"][1:k]).max() < 1e-11
+    assert np.abs(np.array(de[1:]) - L["delta"][1:k]).max() < 1e-11
