@@ -75,6 +75,14 @@ typedef struct {
     int use_graph;          /* 1 (default): the k Lanczos steps of a call are recorded once
                                into a HIP graph (per shape and workspace) and replayed;
                                0: launched one by one */
+    int autotune;           /* 1 (default): the first call of each precision, direction and
+                               batch size times the stencil's launch shapes (XCD work order,
+                               site groups per block) and keeps the fastest; 0: fixed shapes */
+    int shape_map;          /* >= 0: force the XCD work order of the stencils (0: nrhs/8
+                               sources per XCD, only when nrhs % 8 == 0; 1: contiguous site
+                               ranges per XCD); -1 (default): tuned or default */
+    int shape_gpb;          /* > 0: force the site groups per block (Lanczos stencil: 1 or 2
+                               for derivatives, 2 or 4 otherwise; Dw.v: 2 or 4); 0: tuned */
 } ovd_options;
 
 typedef struct {
@@ -203,6 +211,32 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
                                 int k, const void* b, void* y, void* dy,
                                 const void* x, double* xdy, ovd_stats* st);
 
+/* One lattice's share of an uneven batch: the arguments of
+ * ovd_sign_apply_deriv for handle h, and its status on return. */
+typedef struct {
+    ovd_h h;
+    int nrhs;
+    const double* mu;       /* host [nrhs] */
+    const ovd_dir* dir;     /* NULL: mu */
+    int k;
+    const void* b;
+    void* y;
+    void* dy;
+    const void* x;
+    double* xdy;            /* host [2 nrhs] or NULL */
+    ovd_stats* st;          /* or NULL */
+    ovd_status status;      /* out */
+} ovd_deriv_job;
+
+/* Uneven batch (derivatives on several lattices of different sizes at once,
+ * each lattice with its own handle, batch of sources, mu values and k): every
+ * job runs ovd_sign_apply_deriv on its handle from a host thread of its own,
+ * so that the lattices' Lanczos graphs run concurrently when the handles were
+ * created on different streams.  A handle may appear only once.  Returns
+ * OVD_OK if every job succeeded, else the first failing job's status (each
+ * job's status is in its status field). */
+ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs);
+
 /* Gradient of s = <x|sgn(H(mu))|b> (the bilinear the paper's currents and
  * fermionic force are built from, Sec. 1), FP64 whatever the handle's
  * precision: two-sided Lanczos with right start b and left start x,
@@ -220,6 +254,11 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
 ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b,
                               double* s, double* ds_dmu, void* F, void* dsdU, void* dsdUc,
                               ovd_stats* st);
+
+/* Launch shapes chosen by the autotuner so far, as text
+ * "kernel:precision:dir-or-op:nrhs=map<m>,gpb<g>;..." into buf (host, len
+ * bytes, truncated and NUL-terminated). */
+ovd_status ovd_get_tuned(ovd_h h, char* buf, int len);
 
 /* Lanczos coefficients of the last Lanczos run (for parity checks), right-hand
  * side rhs: host complex128 arrays alpha[k], beta[k], delta[k].  T_k has

@@ -21,6 +21,7 @@
 #include <map>
 #include <type_traits>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace ovd;
@@ -64,6 +65,8 @@ struct ovd_lattice {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;   // capture only; replays run on `stream`
+    // autotuned launch shapes, keyed by kernel, precision, direction / operator and batch size
+    std::map<std::string, StencilVariant> tuned;
 };
 
 namespace {
@@ -124,6 +127,55 @@ struct Timer {
         }
     }
 };
+
+// Autotuner: time every candidate launch shape with `launch(v)` (1 warm-up
+// and 3 timed launches each, on the handle's stream) and keep the fastest.
+// `reset()` runs before each candidate.
+template <typename Launch, typename Reset>
+StencilVariant autotune(ovd_h h, const std::vector<StencilVariant>& cands, Launch launch, Reset reset) {
+    StencilVariant best = cands.front();
+    float best_ms = 1e30f;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return best;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return best;
+    }
+    for (const auto& v : cands) {
+        reset();
+        launch(v);
+        (void)hipEventRecord(a, h->stream);
+        for (int r = 0; r < 3; ++r) launch(v);
+        (void)hipEventRecord(b, h->stream);
+        float ms = 0.f;
+        if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipGetLastError();
+    return best;
+}
+
+// a shape forced through the options, completed with defaults; false if none is forced
+bool forced_shape(ovd_h h, int nrhs, int def_gpb, StencilVariant* v) {
+    if (h->opt.shape_map < 0 && h->opt.shape_gpb <= 0) return false;
+    v->map = h->opt.shape_map >= 0 ? h->opt.shape_map : default_map(nrhs);
+    if (v->map == 0 && nrhs % 8 != 0) v->map = 1;
+    v->gpb = h->opt.shape_gpb > 0 ? h->opt.shape_gpb : def_gpb;
+    return true;
+}
+
+std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& gpbs) {
+    std::vector<StencilVariant> c;
+    for (int map : {1, 0}) {
+        if (map == 0 && nrhs % 8 != 0) continue;
+        for (int gpb : gpbs) c.push_back(StencilVariant{map, gpb});
+    }
+    return c;
+}
 
 // fill per-rhs coefficient vector coef[r][j] = delta[r][0] * c[r][j] / delta[r][j]
 __global__ void make_coef_kernel(int k, TslCoeffs co, const c64* __restrict__ c, c64* __restrict__ coef) {
@@ -213,7 +265,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     const long long fsz = (long long)halves * 12 * g.Vp;
     const cpx<T>* U = std::is_same<T, double>::value ? (const cpx<T>*)h->U64 : (const cpx<T>*)h->U32;
     const cpx<T>* dU = std::is_same<T, double>::value ? (const cpx<T>*)h->dU64 : (const cpx<T>*)h->dU32;
-    const int nb = tsl_stencil_blocks(g, dir);
+    const int nb = tsl_stencil_blocks(g, dir, dir == 0 ? 2 : 1);   // the most blocks of any launch shape
 
     WS(ring, cpx<T>, "tsl_ring", (size_t)10 * nrhs * fsz);
     WS(st, TslState, "tsl_state", nrhs);
@@ -258,6 +310,45 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     HIPCHK(hipMemcpy2DAsync(Ws(1), sizeof(cpx<T>) * sW, src_w, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
                             hipMemcpyDeviceToDevice, h->stream));
     const bool timing = h->opt.step_timing != 0;
+    // launch shape of the stencil: autotuned once per precision, direction and batch size
+    StencilVariant var{default_map(nrhs), dir == 0 ? 4 : 2};
+    {
+        const std::string key = std::string("tsl:") + (sizeof(T) == 8 ? "d" : "f") + ":" + std::to_string(dir) + ":" +
+                                std::to_string(nrhs);
+        auto it = h->tuned.find(key);
+        if (forced_shape(h, nrhs, dir == 0 ? 4 : 2, &var)) {
+            if (dir == 0 && var.gpb != 2) var.gpb = 4;
+            if (dir != 0 && var.gpb != 1) var.gpb = 2;
+        } else if (it != h->tuned.end()) {
+            var = it->second;
+        } else if (h->opt.autotune) {
+            // time step 0 on the start vectors with a scratch copy of the recurrence state
+            WS(tst, TslState, "tune_state", nrhs);
+            WS(tcoef, c64, "tune_coef", (size_t)4 * nrhs);
+            WS(tpart, double, "tune_partials", (size_t)nrhs * nb * 8);
+            WS(tcnt, unsigned, "tune_counters", nrhs);
+            TslCoeffs tco{tcoef, tcoef + nrhs, tcoef + (size_t)2 * nrhs, tcoef + (size_t)3 * nrhs, 1};
+            StepPtrs p0{};
+            p0.outV = Vs(1); p0.sV = sV;
+            p0.outU = Us(1); p0.sU = fsz;
+            p0.outW = Ws(1); p0.sW = sW;
+            p0.outZ = Zs(1); p0.sZ = fsz;
+            p0.xproj = xproj;
+            p0.sx = (long long)12 * g.Vp;
+            var = autotune(
+                h, shape_candidates(nrhs, dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1}),
+                [&](StencilVariant v) {
+                    launch_tsl_stencil<T>(g, dir, nrhs, p0, U, dU, md, tst, tco, tpart, tcnt, 0, h->opt.breakdown_tol,
+                                          h->stream, v);
+                },
+                [&]() {
+                    (void)hipMemcpyAsync(tst, hs.data(), sizeof(TslState) * nrhs, hipMemcpyHostToDevice, h->stream);
+                    (void)hipMemsetAsync(tcnt, 0, sizeof(unsigned) * nrhs, h->stream);
+                });
+            HIPCHK(hipGetLastError());
+            h->tuned[key] = var;
+        }
+    }
     // the k steps: update (from the second step on) and stencil with the step's reductions
     auto enqueue_steps = [&](hipStream_t stream) -> hipError_t {
         for (int j = 0; j < k; ++j) {
@@ -283,7 +374,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             }
             if (timing) (void)hipEventRecord(h->ev[4 * j + 2], stream);
             launch_tsl_stencil<T>(g, dir, nrhs, p, U, dU, md, st, co, partials, counters, j,
-                                  h->opt.breakdown_tol, stream);
+                                  h->opt.breakdown_tol, stream, var);
             if (timing) (void)hipEventRecord(h->ev[4 * j + 3], stream);
         }
         return hipGetLastError();
@@ -297,7 +388,8 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         const std::vector<uintptr_t> key = {
             sizeof(T), (uintptr_t)dir, (uintptr_t)nrhs, (uintptr_t)k, (uintptr_t)ring, (uintptr_t)basis,
             (uintptr_t)basis_w, (uintptr_t)xproj, (uintptr_t)U, (uintptr_t)dU, (uintptr_t)st, (uintptr_t)coef,
-            (uintptr_t)partials, (uintptr_t)counters, (uintptr_t)tb, (uintptr_t)mb, (uintptr_t)g.V};
+            (uintptr_t)partials, (uintptr_t)counters, (uintptr_t)tb, (uintptr_t)mb, (uintptr_t)g.V,
+            (uintptr_t)var.map, (uintptr_t)var.gpb};
         hipGraphExec_t exec = nullptr;
         for (auto& e : h->graphs)
             if (e.key == key) exec = e.exec;
@@ -618,6 +710,9 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.quad_step = 0.1;
     h->opt.step_timing = 0;
     h->opt.use_graph = 1;
+    h->opt.autotune = 1;
+    h->opt.shape_map = -1;
+    h->opt.shape_gpb = 0;
     if (opt) {
         h->opt = *opt;
         if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
@@ -690,20 +785,46 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
     }
     HIPCHK(hipMemcpyAsync(emu, he.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, h->stream));
     Timer t;
-    if (h->opt.precision == OVD_MIXED) {
+    const double md = h->m0 + 4 * h->r;
+    const bool f32 = h->opt.precision == OVD_MIXED;
+    const std::string key = std::string("op:") + (f32 ? "f" : "d") + ":" + std::to_string(op) + ":" +
+                            std::to_string(nrhs);
+    if (f32) {
         WS(a, c32, "op_in", (size_t)nrhs * fsz);
         WS(b, c32, "op_out", (size_t)nrhs * fsz);
         launch_pack_spinor<float>(g, nrhs, in, a, fsz, h->stream);
+        auto launch = [&](StencilVariant v) {
+            launch_apply_op<float>(g, op, nrhs, emu, h->U32, h->dU32, md, a, b, h->stream, v);
+        };
+        StencilVariant fv;
+        if (forced_shape(h, nrhs, 4, &fv)) {
+            if (fv.gpb != 2) fv.gpb = 4;
+            h->tuned[key] = fv;
+        } else if (!h->tuned.count(key)) {
+            h->tuned[key] = h->opt.autotune ? autotune(h, shape_candidates(nrhs, {4, 2}), launch, [] {})
+                                            : StencilVariant{default_map(nrhs), 4};
+        }
         t.start(h->stream);
-        launch_apply_op<float>(g, op, nrhs, emu, h->U32, h->dU32, h->m0 + 4 * h->r, a, b, h->stream);
+        launch(h->tuned[key]);
         t.stop(h->stream);
         launch_unpack_spinor<float>(g, nrhs, b, fsz, out, h->stream);
     } else {
         WS(a, c64, "op_in", (size_t)nrhs * fsz);
         WS(b, c64, "op_out", (size_t)nrhs * fsz);
         launch_pack_spinor<double>(g, nrhs, in, a, fsz, h->stream);
+        auto launch = [&](StencilVariant v) {
+            launch_apply_op<double>(g, op, nrhs, emu, h->U64, h->dU64, md, a, b, h->stream, v);
+        };
+        StencilVariant fv;
+        if (forced_shape(h, nrhs, 4, &fv)) {
+            if (fv.gpb != 2) fv.gpb = 4;
+            h->tuned[key] = fv;
+        } else if (!h->tuned.count(key)) {
+            h->tuned[key] = h->opt.autotune ? autotune(h, shape_candidates(nrhs, {4, 2}), launch, [] {})
+                                            : StencilVariant{default_map(nrhs), 4};
+        }
         t.start(h->stream);
-        launch_apply_op<double>(g, op, nrhs, emu, h->U64, h->dU64, h->m0 + 4 * h->r, a, b, h->stream);
+        launch(h->tuned[key]);
         t.stop(h->stream);
         launch_unpack_spinor<double>(g, nrhs, b, fsz, out, h->stream);
     }
@@ -734,6 +855,42 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
     if (s != OVD_OK) return s;
     if (h->opt.precision == OVD_MIXED) return deriv_impl<float>(h, nrhs, mu, dirk, k, b, y, dy, x, xdy, st);
     return deriv_impl<double>(h, nrhs, mu, dirk, k, b, y, dy, x, xdy, st);
+}
+
+ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs) {
+    if (njobs < 1 || !jobs) return OVD_EINVAL;
+    for (int i = 0; i < njobs; ++i) {
+        if (!jobs[i].h) return OVD_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (jobs[j].h == jobs[i].h) {
+                jobs[i].status = fail(jobs[i].h, OVD_EINVAL, "a handle appears twice in one batch");
+                return OVD_EINVAL;
+            }
+    }
+    // one host thread per lattice: each call enqueues on its handle's stream
+    // and waits only for its own results, so the lattices run side by side
+    auto run = [&](int i) {
+        ovd_deriv_job& J = jobs[i];
+        J.status = ovd_sign_apply_deriv(J.h, J.nrhs, J.mu, J.dir, J.k, J.b, J.y, J.dy, J.x, J.xdy, J.st);
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(njobs - 1);
+    for (int i = 1; i < njobs; ++i) pool.emplace_back(run, i);
+    run(0);
+    for (auto& t : pool) t.join();
+    for (int i = 0; i < njobs; ++i)
+        if (jobs[i].status != OVD_OK) return jobs[i].status;
+    return OVD_OK;
+}
+
+ovd_status ovd_get_tuned(ovd_h h, char* buf, int len) {
+    if (!h || !buf || len < 1) return OVD_EINVAL;
+    std::string out;
+    for (const auto& kv : h->tuned)
+        out += kv.first + "=map" + std::to_string(kv.second.map) + ",gpb" + std::to_string(kv.second.gpb) + ";";
+    std::strncpy(buf, out.c_str(), (size_t)len - 1);
+    buf[len - 1] = 0;
+    return OVD_OK;
 }
 
 ovd_status ovd_get_tridiag(ovd_h h, int rhs, int k, double* alpha, double* beta, double* delta) {

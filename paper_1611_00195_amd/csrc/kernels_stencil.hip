@@ -341,21 +341,22 @@ __device__ __forceinline__ void hops(cpx<T> (&acc)[12], const cpx<T>* __restrict
 // XCD keeps its neighbour data in L2 only if it sweeps a compact piece of
 // work in site order.  The (rhs, site group) work items are therefore split
 // into 8 compact chunks, one per XCD:
-//   nrhs >= 16 and a multiple of 8:  XCD x takes right-hand sides x m .. x m + m - 1
+//   map 0 (nrhs a multiple of 8): XCD x takes right-hand sides x m .. x m + m - 1
 //                          (m = nrhs / 8) over the whole lattice, site group
 //                          major, so those m share each link read;
-//   otherwise:             XCD x takes a contiguous range of site groups for
+//   map 1:                 XCD x takes a contiguous range of site groups for
 //                          all right-hand sides (rhs innermost), so that the
 //                          links and neighbours of a range stay in its L2.
-// The choice follows measurements of Dw.v at 14^4 (1, 8 and 48 sources).
+// Measured on Dw.v at 14^4, map 0 wins from 16 sources up and map 1 below
+// (the default); the autotuner of the library times both.
 // nb (site groups per rhs, padded) is a multiple of 8.
 struct Work {
     int rhs, grp;
 };
-__device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs) {
+__device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs, int map) {
     const int x = bid & 7, idx = bid >> 3;
     Work w;
-    if ((nrhs & 7) == 0 && nrhs >= 16) {
+    if (map == 0 && (nrhs & 7) == 0) {
         const int m = nrhs >> 3;
         w.grp = idx / m;
         w.rhs = x * m + idx % m;
@@ -370,15 +371,15 @@ __device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs) {
 // ---------------------------------------------------------------------------
 // standalone operator
 // ---------------------------------------------------------------------------
-template <typename T, int OP>
+template <typename T, int OP, int GPB>
 __global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_kernel(Geom g, const double* __restrict__ emu,
                                                        const cpx<T>* __restrict__ U,
                                                        const cpx<T>* __restrict__ dU, T mdiag,
                                                        const cpx<T>* __restrict__ in,
-                                                       cpx<T>* __restrict__ out, int ngroups, int nrhs) {
-    const Work w = xcd_work(blockIdx.x, gridDim.x / nrhs, nrhs);
+                                                       cpx<T>* __restrict__ out, int ngroups, int nrhs, int map) {
+    const Work w = xcd_work(blockIdx.x, gridDim.x / nrhs, nrhs, map);
     const int rhs = w.rhs;
-    const int grp = w.grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int grp = w.grp * GPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int s = grp * 64 + (threadIdx.x & 63);
     if (grp >= ngroups || s >= g.V) return;
     const int Vp = g.Vp;
@@ -408,24 +409,37 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_kernel(Geom g, const 
     store12(out + roff, s, Vp, acc);
 }
 
+template <typename T, int OP>
+static void launch_apply_op_v(const Geom& g, int nrhs, const double* d_emu, const cpx<T>* U, const cpx<T>* dU, T md,
+                              const cpx<T>* in, cpx<T>* out, StencilVariant v, hipStream_t s) {
+    const int ngroups = (g.V + 63) / 64;
+    const int gpb = v.gpb == 2 ? 2 : 4;
+    const int nq = ((ngroups + gpb - 1) / gpb + 7) / 8 * 8;   // blocks of gpb site groups, padded to 8
+    dim3 grid(nq * nrhs), block(64 * gpb);
+    if (gpb == 2)
+        apply_op_kernel<T, OP, 2><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs, v.map);
+    else
+        apply_op_kernel<T, OP, 4><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs, v.map);
+}
+
 template <typename T>
 void launch_apply_op(const Geom& g, int op, int nrhs, const double* d_emu, const cpx<T>* U,
-                     const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s) {
-    const int ngroups = (g.V + 63) / 64;
-    const int nq = ((ngroups + 3) / 4 + 7) / 8 * 8;   // blocks of 4 site groups, padded to 8
-    dim3 grid(nq * nrhs), block(256);
+                     const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s,
+                     StencilVariant v) {
+    if (v.map < 0) v.map = default_map(nrhs);
+    if (v.gpb <= 0) v.gpb = 4;
     const T md = T(m_diag);
     switch (op) {
-        case 0: apply_op_kernel<T, 0><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
-        case 1: apply_op_kernel<T, 1><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
-        case 2: apply_op_kernel<T, 2><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
-        default: apply_op_kernel<T, 3><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs); break;
+        case 0: launch_apply_op_v<T, 0>(g, nrhs, d_emu, U, dU, md, in, out, v, s); break;
+        case 1: launch_apply_op_v<T, 1>(g, nrhs, d_emu, U, dU, md, in, out, v, s); break;
+        case 2: launch_apply_op_v<T, 2>(g, nrhs, d_emu, U, dU, md, in, out, v, s); break;
+        default: launch_apply_op_v<T, 3>(g, nrhs, d_emu, U, dU, md, in, out, v, s); break;
     }
 }
 template void launch_apply_op<double>(const Geom&, int, int, const double*, const c64*, const c64*, double,
-                                      const c64*, c64*, hipStream_t);
+                                      const c64*, c64*, hipStream_t, StencilVariant);
 template void launch_apply_op<float>(const Geom&, int, int, const double*, const c32*, const c32*, double,
-                                     const c32*, c32*, hipStream_t);
+                                     const c32*, c32*, hipStream_t, StencilVariant);
 
 // ---------------------------------------------------------------------------
 // deterministic block reduction of NV doubles (fixed shuffle tree, then waves
@@ -661,22 +675,19 @@ __device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[1
     for (int c = 0; c < 12; ++c) part[i] += norm2(cast<double>(a[c]));
 }
 
-// site groups (of 64) per block: DIR 0 has one pair per site (4 groups per
-// block), DIR 1/2 two pairs per site (2 groups x (v, w) waves)
-template <int DIR> constexpr int tsl_groups_per_block() { return DIR == 0 ? 4 : 2; }
-
-template <typename T, int DIR>
+// GPB site groups (of 64) per block: DIR 0 has one pair per site (GPB waves),
+// DIR 1/2 two pairs per site (GPB groups x (v, w) waves)
+template <typename T, int DIR, int GPB>
 __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
                                                           const cpx<T>* __restrict__ dU, T mdiag,
                                                           TslState* __restrict__ st, TslCoeffs co,
                                                           double* __restrict__ partials,
                                                           unsigned* __restrict__ counters, int j, double tau,
-                                                          int ngroups, int nrhs) {
-    constexpr int GPB = tsl_groups_per_block<DIR>();
+                                                          int ngroups, int nrhs, int map) {
     __shared__ double lds[16 * 8];
     __shared__ int am_last;
     const int nb = gridDim.x / nrhs;                // blocks per rhs
-    const Work wk = xcd_work(blockIdx.x, nb, nrhs);
+    const Work wk = xcd_work(blockIdx.x, nb, nrhs, map);
     const int rhs = wk.rhs;
     TslState* S = st + rhs;
     if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
@@ -858,32 +869,42 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
         tsl_update_kernel<T, 2><<<grid, 256, 0, s>>>(p, fsz, st);
 }
 
-int tsl_stencil_blocks(const Geom& g, int dir) {
+int tsl_stencil_blocks(const Geom& g, int dir, int gpb) {
     const int ngroups = (g.V + 63) / 64;
-    const int gpb = dir == 0 ? tsl_groups_per_block<0>() : tsl_groups_per_block<1>();
+    if (gpb <= 0) gpb = dir == 0 ? 4 : 2;
     return ((ngroups + gpb - 1) / gpb + 7) / 8 * 8;   // nb * nrhs is a multiple of 8
 }
 
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
-                        unsigned* counters, int j, double tau, hipStream_t s) {
+                        unsigned* counters, int j, double tau, hipStream_t s, StencilVariant v) {
     const int ngroups = (g.V + 63) / 64;
-    dim3 grid(tsl_stencil_blocks(g, dir) * nrhs), block(256);
+    if (v.map < 0) v.map = default_map(nrhs);
+    if (v.gpb <= 0) v.gpb = dir == 0 ? 4 : 2;
+    dim3 grid(tsl_stencil_blocks(g, dir, v.gpb) * nrhs);
     const T md = T(m_diag);
-    if (dir == 0)
-        tsl_stencil_kernel<T, 0><<<grid, block, 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
-    else if (dir == 1)
-        tsl_stencil_kernel<T, 1><<<grid, block, 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
-    else
-        tsl_stencil_kernel<T, 2><<<grid, block, 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, ngroups, nrhs);
+#define OVD_TSL(D, G, THREADS)                                                                                 \
+    tsl_stencil_kernel<T, D, G><<<grid, dim3(THREADS), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, \
+                                                              ngroups, nrhs, v.map)
+    if (dir == 0) {
+        if (v.gpb == 2) OVD_TSL(0, 2, 128);
+        else OVD_TSL(0, 4, 256);
+    } else if (dir == 1) {
+        if (v.gpb == 1) OVD_TSL(1, 1, 128);
+        else OVD_TSL(1, 2, 256);
+    } else {
+        if (v.gpb == 1) OVD_TSL(2, 1, 128);
+        else OVD_TSL(2, 2, 256);
+    }
+#undef OVD_TSL
 }
 
 #define OVD_INST(T)                                                                                        \
     template void launch_tsl_update<T>(int, int, long long, const StepPtrs&, const TslState*, hipStream_t); \
     template void launch_tsl_stencil<T>(const Geom&, int, int, const StepPtrs&, const cpx<T>*, const cpx<T>*, \
                                         double, TslState*, TslCoeffs, double*, unsigned*, int, double,     \
-                                        hipStream_t);
+                                        hipStream_t, StencilVariant);
 OVD_INST(double)
 OVD_INST(float)
 #undef OVD_INST

@@ -132,10 +132,21 @@ void launch_pack_spinor(const Geom& g, int n, const void* in_aos, cpx<T>* out, l
 template <typename T>
 void launch_unpack_spinor(const Geom& g, int n, const cpx<T>* in, long long stride, void* out_aos, hipStream_t s);
 
+// launch shape of the stencil kernels: XCD work order (0: nrhs/8 sources per
+// XCD over the whole lattice, needs nrhs % 8 == 0; 1: contiguous site-group
+// ranges per XCD, rhs innermost; < 0: default) and site groups per block
+// (apply_op: 2 or 4; Lanczos stencil DIR 0: 2 or 4, DIR 1/2: 1 or 2; <= 0: default)
+struct StencilVariant {
+    int map = -1;
+    int gpb = 0;
+};
+inline int default_map(int nrhs) { return (nrhs >= 16 && nrhs % 8 == 0) ? 0 : 1; }
+
 // standalone operator: out = op(in) on SoA fields, per-rhs mu
 template <typename T>
 void launch_apply_op(const Geom& g, int op, int nrhs, const double* d_emu, const cpx<T>* U,
-                     const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s);
+                     const cpx<T>* dU, double m_diag, const cpx<T>* in, cpx<T>* out, hipStream_t s,
+                     StencilVariant v = StencilVariant{});
 
 // Lanczos step part 1: vhat/what = a X + b Y (+ c Z) element-wise on both
 // sides (nterms 2 or 3), fsz elements per rhs and side.
@@ -145,11 +156,11 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
 // Lanczos step part 2: stencil on outV/outW into outU/outZ plus the step's
 // reductions and scalar recurrence.  dir: 0 plain H, 1 block d/dmu, 2 block d/dlink.
 // blocks per right-hand side of the stencil kernel (size of its partial sums)
-int tsl_stencil_blocks(const Geom& g, int dir);
+int tsl_stencil_blocks(const Geom& g, int dir, int gpb = 0);
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
-                        unsigned* counters, int j, double tau, hipStream_t s);
+                        unsigned* counters, int j, double tau, hipStream_t s, StencilVariant v = StencilVariant{});
 
 // sgn(T_k) e_1 for nrhs tridiagonal matrices by the resolvent quadrature.
 void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scratch,

@@ -30,7 +30,7 @@ EXPORTS = [
     "ovd_create_lattice", "ovd_destroy", "ovd_last_error", "ovd_set_stream", "ovd_set_links",
     "ovd_apply_op", "ovd_set_deflation", "ovd_clear_deflation", "ovd_sign_apply",
     "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag", "ovd_compute_deflation",
-    "ovd_get_deflation",
+    "ovd_get_deflation", "ovd_sign_apply_deriv_batch", "ovd_get_tuned",
 ]
 
 
@@ -47,7 +47,8 @@ class Breakdown(OvdError):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("left_start", ctypes.c_int),
                 ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
-                ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int)]
 
 
 class _EigStats(ctypes.Structure):
@@ -66,6 +67,13 @@ class _Stats(ctypes.Structure):
                 ("sign_check", ctypes.c_double), ("ms_lanczos", ctypes.c_double),
                 ("ms_small_sign", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_stencil", ctypes.c_double), ("ms_update", ctypes.c_double)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("mu", ctypes.POINTER(ctypes.c_double)),
+                ("dir", ctypes.c_void_p), ("k", ctypes.c_int), ("b", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("dy", ctypes.c_void_p), ("x", ctypes.c_void_p), ("xdy", ctypes.POINTER(ctypes.c_double)),
+                ("st", ctypes.POINTER(_Stats)), ("status", ctypes.c_int)]
 
 
 @dataclass
@@ -96,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ovd_apply_op": (i, [vp, i, d, ctypes.POINTER(_Dir), i, vp, vp, dp]),
         "ovd_set_deflation": (i, [vp, d, i, dp, vp, vp, i, vp, vp, ctypes.POINTER(_Dir)]),
         "ovd_clear_deflation": (i, [vp]),
+        "ovd_get_tuned": (i, [vp, ctypes.c_char_p, i]),
+        "ovd_sign_apply_deriv_batch": (i, [i, ctypes.POINTER(_Job)]),
         "ovd_get_deflation": (i, [vp, d, ctypes.POINTER(i), ctypes.POINTER(i), dp, vp, vp, vp, vp]),
         "ovd_compute_deflation": (i, [vp, d, i, i, ctypes.POINTER(_Dir), d, dp, ctypes.POINTER(_EigStats)]),
         "ovd_sign_apply": (i, [vp, i, dp, i, vp, vp, ctypes.POINTER(_Stats)]),
@@ -145,7 +155,8 @@ class Lattice:
     workspaces live on the current device."""
 
     def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
-                 breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True):
+                 breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True,
+                 autotune=True, shape=None):
         self.dims = tuple(int(d) for d in dims)
         self.V = 1
         for d in self.dims:
@@ -155,7 +166,9 @@ class Lattice:
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
-        opt = _Options(precision, left_start, breakdown_tol, quad_step, int(bool(step_timing)), int(bool(use_graph)))
+        opt = _Options(precision, left_start, breakdown_tol, quad_step, int(bool(step_timing)), int(bool(use_graph)),
+                       int(bool(autotune)), -1 if shape is None else int(shape[0]),
+                       0 if shape is None else int(shape[1]))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
@@ -306,6 +319,12 @@ class Lattice:
         stats = {f: getattr(st, f) for f, _ in _EigStats._fields_}
         return lv, stats
 
+    def tuned_shapes(self):
+        """Launch shapes chosen by the autotuner so far (see ovd_get_tuned)."""
+        buf = ctypes.create_string_buffer(4096)
+        self._call("ovd_get_tuned", buf, 4096)
+        return buf.value.decode()
+
     def get_deflation(self, mu):
         """(lam, R, L, dR, dL) of the deflation set of mu; dR, dL None if l = 0."""
         m, l = ctypes.c_int(0), ctypes.c_int(0)
@@ -333,6 +352,41 @@ class Lattice:
         self._call("ovd_get_tridiag", int(rhs), int(k), a, b, d)
         cv = lambda arr: [complex(arr[2 * i], arr[2 * i + 1]) for i in range(k)]
         return cv(a), cv(b), cv(d)
+
+
+def sign_apply_deriv_batch(jobs):
+    """Uneven batch: jobs = [(lattice, b, mu, k, x), ...], one per lattice
+    (distinct handles, ideally created on distinct streams); every lattice's
+    derivative <x|d/dmu sgn(H) b> runs concurrently (ovd_sign_apply_deriv_batch).
+    Returns a list of per-lattice lists of complex values."""
+    n = len(jobs)
+    arr = (_Job * n)()
+    keep = []
+    outs = []
+    for i, (lat, b, mu, k, x) in enumerate(jobs):
+        nr = b.shape[0]
+        _check_field(b, (nr, lat.V, 4, 3), "b")
+        _check_field(x, (nr, lat.V, 4, 3), "x")
+        mus = [float(mu)] * nr if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        mu_c = _dbl(mus)
+        xdy = (ctypes.c_double * (2 * nr))()
+        st = _Stats()
+        keep += [mu_c, xdy, st, b, x]
+        arr[i] = _Job(lat._h.value if hasattr(lat._h, "value") else lat._h, nr,
+                      ctypes.cast(mu_c, ctypes.POINTER(ctypes.c_double)), None, int(k), b.data_ptr(), None, None,
+                      x.data_ptr(), ctypes.cast(xdy, ctypes.POINTER(ctypes.c_double)), ctypes.pointer(st), 0)
+        outs.append((xdy, nr, lat, st))
+    status = lib().ovd_sign_apply_deriv_batch(n, arr)
+    if status != OVD_OK:
+        for i in range(n):
+            if arr[i].status != OVD_OK:
+                outs[i][2]._raise(arr[i].status)
+        raise OvdError(status, "ovd_sign_apply_deriv_batch failed")
+    res = []
+    for xdy, nr, lat, st in outs:
+        lat.last_stats = Lattice._stats(st)
+        res.append([complex(xdy[2 * j], xdy[2 * j + 1]) for j in range(nr)])
+    return res
 
 
 def create_lattice(dims, **kw) -> Lattice:
