@@ -171,6 +171,15 @@ def run_gpu(args):
     out["forms"] = forms
     if not args.skip_forms:
         out["vjp"] = time_vjp(args, U, V)
+        vm = time_vjp(args, U, V, prec=ovderiv.MIXED)
+        F64, F32 = out["vjp"].pop("F"), vm.pop("F")
+        import torch as _t
+        vm["max_rel_dev_from_fp64"] = {
+            "s": abs(complex(*vm["s"]) - complex(*out["vjp"]["s"])) / abs(complex(*out["vjp"]["s"])),
+            "ds_dmu": abs(complex(*vm["ds_dmu"]) - complex(*out["vjp"]["ds_dmu"])) / abs(complex(*out["vjp"]["ds_dmu"])),
+            "force": float(_t.linalg.vector_norm(F32 - F64) / _t.linalg.vector_norm(F64)),
+        }
+        out["vjp_mixed"] = vm
         out["uneven"] = time_uneven(args)
     # Dw.v bandwidth: nrhs fields per launch so that the traffic exceeds the 256 MB MALL
     nd = args.dwv_nrhs
@@ -194,7 +203,7 @@ def run_gpu(args):
     return out
 
 
-def time_vjp(args, U, V):
+def time_vjp(args, U, V, prec=0):
     """The gradient of s = <x|sgn(H)|b> w.r.t. mu and all 4 V links (FP64, one
     source pair, both Krylov bases stored): calls per second and the MFMA rate
     of the Z = W M'^dag product (8 N k^2 flops)."""
@@ -204,7 +213,7 @@ def time_vjp(args, U, V):
     from paper_1611_00195_amd import ovderiv
 
     dims = tuple(args.dims)
-    lat = ovderiv.Lattice(dims, m0=args.m0)
+    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
     lat.set_links(U)
     b = torch.from_numpy(synth.make_sources(dims, 1, 4000)).cuda()
     x = torch.from_numpy(synth.make_sources(dims, 1, 5000)).cuda()
@@ -218,8 +227,8 @@ def time_vjp(args, U, V):
     dt = (time.perf_counter() - t0) / reps
     lat.close()
     return {"calls_per_s": round(1.0 / dt, 3), "ms_per_call": round(1e3 * dt, 2), "s": [s.real, s.imag],
-            "ds_dmu": [dsdmu.real, dsdmu.imag], "precision": "fp64", "k": args.k,
-            "zgemm_flops": 8.0 * 12 * V * args.k ** 2}
+            "ds_dmu": [dsdmu.real, dsdmu.imag], "precision": "fp64" if prec == 0 else "mixed", "k": args.k,
+            "zgemm_flops": 8.0 * 12 * V * args.k ** 2, "F": F}
 
 
 def time_uneven(args):
@@ -399,6 +408,7 @@ def main():
             "forms": g["forms"],
             "dw_v": g["dw_v"],
             "vjp": g.get("vjp"),
+            "vjp_mixed": g.get("vjp_mixed"),
             "uneven_batch": g.get("uneven"),
             "min_margin": g["min_margin"],
             "sign_check": g["sign_check"],

@@ -250,7 +250,10 @@ ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs);
  *   dsdU, dsdUc  device complex128 [4][V][3][3] or NULL: Wirtinger derivatives
  *             ds/dU_nu(y)[a][b] and ds/dconj(U_nu(y)[a][b]) with the links taken
  *             as unconstrained complex matrices (for automatic differentiation)
- * The Krylov bases V_k, W_k are stored (2 k 12 V complex128 of workspace). */
+ * The Krylov bases V_k, W_k are stored (2 k 12 V complex128 of workspace).
+ * With OVD_MIXED the Lanczos run keeps FP32 vectors (FP64 scalars, as in
+ * ovd_sign_apply) and its bases are widened to FP64 for M_k, Z and the force
+ * (2 k 12 V complex64 more workspace). */
 ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b,
                               double* s, double* ds_dmu, void* F, void* dsdU, void* dsdUc,
                               ovd_stats* st);

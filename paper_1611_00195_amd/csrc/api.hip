@@ -1122,21 +1122,38 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const long long fsz = (long long)12 * g.Vp;
-    // bilinear two-sided Lanczos in FP64: right start b, left start x, both bases kept
-    WS(srcv, c64, "vjp_src_v", fsz);
-    WS(srcw, c64, "vjp_src_w", fsz);
+    // bilinear two-sided Lanczos: right start b, left start x, both bases kept
+    // (FP64, or FP32 vectors for OVD_MIXED, widened to FP64 for the gradient)
     WS(bv, c64, "vjp_basis_v", (size_t)k * fsz);
     WS(bw, c64, "vjp_basis_w", (size_t)k * fsz);
     WS(c, c64, "ritz_c", k);
-    HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c64) * fsz, h->stream));
-    HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c64) * fsz, h->stream));
-    launch_pack_spinor<double>(g, 1, b, srcv, fsz, h->stream);
-    launch_pack_spinor<double>(g, 1, x, srcw, fsz, h->stream);
     Timer tt;
     tt.start(h->stream);
     const double mus[1] = {mu};
-    s = run_tsl<double>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv, c, st, bw);
-    if (s != OVD_OK) return s;
+    if (h->opt.precision == OVD_MIXED) {
+        WS(srcv, c32, "vjp_src_v32", fsz);
+        WS(srcw, c32, "vjp_src_w32", fsz);
+        WS(bv32, c32, "vjp_basis_v32", (size_t)k * fsz);
+        WS(bw32, c32, "vjp_basis_w32", (size_t)k * fsz);
+        HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c32) * fsz, h->stream));
+        HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c32) * fsz, h->stream));
+        launch_pack_spinor<float>(g, 1, b, srcv, fsz, h->stream);
+        launch_pack_spinor<float>(g, 1, x, srcw, fsz, h->stream);
+        s = run_tsl<float>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv32, c, st, bw32);
+        if (s != OVD_OK) return s;
+        launch_widen_field(g, k, bv32, fsz, bv, fsz, h->stream);
+        launch_widen_field(g, k, bw32, fsz, bw, fsz, h->stream);
+        HIPCHK(hipGetLastError());
+    } else {
+        WS(srcv, c64, "vjp_src_v", fsz);
+        WS(srcw, c64, "vjp_src_w", fsz);
+        HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c64) * fsz, h->stream));
+        HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c64) * fsz, h->stream));
+        launch_pack_spinor<double>(g, 1, b, srcv, fsz, h->stream);
+        launch_pack_spinor<double>(g, 1, x, srcw, fsz, h->stream);
+        s = run_tsl<double>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv, c, st, bw);
+        if (s != OVD_OK) return s;
+    }
     const TslCoeffs co = h->last_co;
     // s = (x^dag b) [sgn(T_k)]_11, x^dag b = beta_0 delta_0
     c64 c0, b0, d0;

@@ -198,6 +198,22 @@ void launch_convert_field(const Geom& g, int n, const c64* in, long long sin, cp
 template void launch_convert_field<double>(const Geom&, int, const c64*, long long, c64*, long long, hipStream_t);
 template void launch_convert_field<float>(const Geom&, int, const c64*, long long, c32*, long long, hipStream_t);
 
+// FP32 internal layout -> FP64 internal layout (padding sites zero)
+__global__ void widen_field_kernel(Geom g, const c32* __restrict__ in, long long sin, c64* __restrict__ out,
+                                   long long sout) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= g.Vp) return;
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+        out[r * sout + (size_t)c * g.Vp + s] = s < g.V ? cast<double>(in[r * sin + fidx<float>(c, s, g.Vp)]) : c64{0.0, 0.0};
+}
+
+void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64* out, long long sout, hipStream_t s) {
+    dim3 grid((g.Vp + 255) / 256, n);
+    widen_field_kernel<<<grid, 256, 0, s>>>(g, in, sin, out, sout);
+}
+
 }  // namespace ovd
 
 namespace ovd {

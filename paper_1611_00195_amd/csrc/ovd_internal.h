@@ -198,6 +198,9 @@ template <typename T>
 void launch_convert_field(const Geom& g, int n, const c64* in, long long sin, cpx<T>* out, long long sout,
                           hipStream_t s);
 
+// FP32 internal fields -> FP64 internal fields (n fields, strides in elements)
+void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64* out, long long sout, hipStream_t s);
+
 // gradient of <x|sgn(H)|b> (kernels_defl.hip / kernels_stencil.hip)
 void launch_zgemm_wmh(const c64* W, long long sW, int k, const c64* Mp, c64* Z, long long sZ, long long nf,
                       hipStream_t s);

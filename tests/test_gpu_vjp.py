@@ -146,3 +146,25 @@ def test_vjp_dsdmu_agrees_with_block_derivative():
     trunc = abs(vals[1] - vals[0])
     assert trunc < 1e-8 * abs(vals[1])
     assert abs(dm - vals[1]) < 1e-8 * abs(vals[1])
+
+
+def test_vjp_mixed_precision_bounds():
+    """FP32 Lanczos vectors (FP64 scalars and gradient algebra) against the FP64
+    gradient at the same k; bounds measured here (4^4, k = 96)."""
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, print_case, rel
+    dims, k = (4, 4, 4, 4), 96
+    print_case(test="vjp_mixed", dims=dims, k=k)
+    U = synth.make_links(dims, 0.4, 531)
+    x = synth.make_source(dims, 532)
+    b = synth.make_source(dims, 533)
+    out = {}
+    for prec in (0, 1):
+        lat = ovderiv.Lattice(dims, precision=prec)
+        lat.set_links(dev(U))
+        out[prec] = lat.sign_apply_vjp(dev(x[None]), dev(b[None]), MU, k, force=True, wirtinger=False)
+    e_s = abs(out[1][0] - out[0][0]) / abs(out[0][0])
+    e_d = abs(out[1][1] - out[0][1]) / abs(out[0][1])
+    e_f = rel(host(out[1][2]), host(out[0][2]))
+    print(f"mixed gradient deviations: s {e_s:.1e}, ds/dmu {e_d:.1e}, force {e_f:.1e}")
+    assert e_s < 1e-5 and e_d < 1e-4 and e_f < 1e-4
