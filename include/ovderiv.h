@@ -82,7 +82,9 @@ typedef struct {
                                sources per XCD, only when nrhs % 8 == 0; 1: contiguous site
                                ranges per XCD); -1 (default): tuned or default */
     int shape_gpb;          /* > 0: force the site groups per block (Lanczos stencil: 1 or 2
-                               for derivatives, 2 or 4 otherwise; Dw.v: 2 or 4); 0: tuned */
+                               for derivatives, 2 or 4 otherwise, or 8: one block per
+                               xy-plane staged in LDS, when 128 <= Lx Ly <= 256; Dw.v: 2 or 4);
+                               0: tuned */
 } ovd_options;
 
 typedef struct {

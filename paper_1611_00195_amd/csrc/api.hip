@@ -317,8 +317,9 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
                                 std::to_string(nrhs);
         auto it = h->tuned.find(key);
         if (forced_shape(h, nrhs, dir == 0 ? 4 : 2, &var)) {
-            if (dir == 0 && var.gpb != 2) var.gpb = 4;
-            if (dir != 0 && var.gpb != 1) var.gpb = 2;
+            if (var.gpb == 8 && !tsl_plane_ok(g)) var.gpb = 0;
+            if (dir == 0 && var.gpb != 2 && var.gpb != 8) var.gpb = 4;
+            if (dir != 0 && var.gpb != 1 && var.gpb != 8) var.gpb = 2;
         } else if (it != h->tuned.end()) {
             var = it->second;
         } else if (h->opt.autotune) {
@@ -336,7 +337,9 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             p0.xproj = xproj;
             p0.sx = (long long)12 * g.Vp;
             var = autotune(
-                h, shape_candidates(nrhs, dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1}),
+                h,
+                shape_candidates(nrhs, tsl_plane_ok(g) ? (dir == 0 ? std::vector<int>{4, 2, 8} : std::vector<int>{2, 1, 8})
+                                                       : (dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1})),
                 [&](StencilVariant v) {
                     launch_tsl_stencil<T>(g, dir, nrhs, p0, U, dU, md, tst, tco, tpart, tcnt, 0, h->opt.breakdown_tol,
                                           h->stream, v);

@@ -555,11 +555,10 @@ __device__ __forceinline__ void link_mul(const cpx<T> (&u)[9], const cpx<T> (&h0
 // factors (time hops of the mu derivative, else 0); with DIR 2 the second
 // link field W2 carries the derivative hop of B into top (v side) or of A into
 // bottom (w side).
-template <typename T, int I, int DIR>
-__device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12], const char* __restrict__ A,
-                                         const char* __restrict__ B, const char* __restrict__ W,
-                                         const char* __restrict__ W2, uint32_t Vp16, uint32_t noff, uint32_t loff,
-                                         T cA, T cB, T xAB, T xBA, bool vside) {
+template <typename T, int I, int DIR, typename LoadA, typename LoadB>
+__device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12], LoadA loadA, LoadB loadB,
+                                         const char* __restrict__ W, const char* __restrict__ W2, uint32_t Vp16,
+                                         uint32_t loff, T cA, T cB, T xAB, T xBA, bool vside) {
     constexpr bool fwd = (I & 1) == 0;
     constexpr bool mix = (DIR == 1) && (I >= 6);
     cpx<T> u[9];
@@ -567,7 +566,7 @@ __device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12],
     cpx<T> a0[3], a1[3], b0[3], b1[3], g0[3], g1[3];
     {
         cpx<T> v[12];
-        ld_site<T>(A, Vp16, noff, v);
+        loadA(v);
         proj_ct<T, I>(v, a0, a1);
     }
     if constexpr (!mix) {
@@ -582,7 +581,7 @@ __device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12],
         OVD_PAIR_FENCE;
         {
             cpx<T> v[12];
-            ld_site<T>(B, Vp16, noff, v);
+            loadB(v);
             proj_ct<T, I>(v, b0, b1);
         }
         if constexpr (DIR == 2) {
@@ -609,7 +608,7 @@ __device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12],
         // time hops of the mu derivative: top += x_AB B, bottom += x_BA A
         {
             cpx<T> v[12];
-            ld_site<T>(B, Vp16, noff, v);
+            loadB(v);
             proj_ct<T, I>(v, b0, b1);
         }
         cpx<T> h0[3], h1[3];
@@ -630,7 +629,7 @@ __device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12],
     }
 }
 
-template <typename T, int DIR>
+template <typename T, int DIR, bool PLANE = false>
 __device__ __forceinline__ void pair_hops(cpx<T> (&accA)[12], cpx<T> (&accB)[12], const cpx<T>* Af,
                                           const cpx<T>* Bf, const cpx<T>* Wf, const cpx<T>* W2f, const Nbr& N, int s,
                                           int Vp, T cfA, T cbA, T cfB, T cbB, T xfAB, T xbAB, T xfBA, T xbBA, int bc,
@@ -642,14 +641,21 @@ __device__ __forceinline__ void pair_hops(cpx<T> (&accA)[12], cpx<T> (&accB)[12]
     const uint32_t Vp16 = (uint32_t)Vp * 16u;
     const uint32_t so = (uint32_t)s * 16u;
     const T h = T(-0.5), z = T(0);
-#define OVD_PH(I, NB, LS, CA, CB, XAB, XBA)                                                                       \
-    pair_hop<T, I, DIR>(accA, accB, A, B, W, W2, Vp16, (uint32_t)(NB) * 16u, (uint32_t)(LS) * 16u, CA, CB, XAB, \
-                        XBA, vside);                                                                             \
+#define OVD_PH(I, NB, LS, CA, CB, XAB, XBA)                                                                    \
+    {                                                                                                          \
+        const uint32_t noff = (uint32_t)(NB) * 16u;                                                            \
+        pair_hop<T, I, DIR>(                                                                                   \
+            accA, accB, [&](cpx<T>(&v)[12]) { ld_site<T>(A, Vp16, noff, v); },                                 \
+            [&](cpx<T>(&v)[12]) { ld_site<T>(B, Vp16, noff, v); }, W, W2, Vp16, (uint32_t)(LS) * 16u, CA, CB, \
+            XAB, XBA, vside);                                                                                  \
+    }                                                                                                          \
     OVD_HOP_FENCE;
-    OVD_PH(0, N.f[0], s, h, h, z, z)
-    OVD_PH(1, N.b[0], N.b[0], h, h, z, z)
-    OVD_PH(2, N.f[1], s, h, h, z, z)
-    OVD_PH(3, N.b[1], N.b[1], h, h, z, z)
+    if constexpr (!PLANE) {   // x and y hops from memory (with a plane in LDS the caller has done them)
+        OVD_PH(0, N.f[0], s, h, h, z, z)
+        OVD_PH(1, N.b[0], N.b[0], h, h, z, z)
+        OVD_PH(2, N.f[1], s, h, h, z, z)
+        OVD_PH(3, N.b[1], N.b[1], h, h, z, z)
+    }
     OVD_PH(4, N.f[2], s, h, h, z, z)
     OVD_PH(5, N.b[2], N.b[2], h, h, z, z)
     const T sf = N.wf ? T(bc) : T(1), sb = N.wb ? T(bc) : T(1);
@@ -677,6 +683,11 @@ __device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[1
 
 // GPB site groups (of 64) per block: DIR 0 has one pair per site (GPB waves),
 // DIR 1/2 two pairs per site (GPB groups x (v, w) waves)
+// GPB == PLANE_GPB: one block per (xy-plane, rhs, side) (DIR 0: (xy-plane,
+// rhs)), thread t at site t of the plane (Lx Ly <= 256), the plane's two input
+// fields staged in LDS for the x and y hops.
+constexpr int PLANE_GPB = 8;
+
 template <typename T, int DIR, int GPB>
 __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
                                                           const cpx<T>* __restrict__ dU, T mdiag,
@@ -684,6 +695,9 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
                                                           double* __restrict__ partials,
                                                           unsigned* __restrict__ counters, int j, double tau,
                                                           int ngroups, int nrhs, int map) {
+    constexpr bool PLANE = GPB == PLANE_GPB;
+    constexpr int NQ = sizeof(T) == 8 ? 12 : 6;     // 16-byte entries per site
+    extern __shared__ float4 plane_lds[];           // PLANE: [2][NQ][P]
     __shared__ double lds[16 * 8];
     __shared__ int am_last;
     const int nb = gridDim.x / nrhs;                // blocks per rhs
@@ -693,10 +707,21 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
     if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
     const int Vp = g.Vp;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const bool vside = (DIR == 0) || (wave & 1) == 0;
-    const int grp = (DIR == 0) ? wk.grp * GPB + wave : wk.grp * GPB + (wave >> 1);
-    const int s = grp * 64 + (threadIdx.x & 63);
-    const bool active = (grp < ngroups) && (s < g.V);
+    const int P = g.L[0] * g.L[1];
+    bool vside;
+    int s;
+    bool active;
+    if constexpr (PLANE) {
+        const int plane = (DIR == 0) ? wk.grp : (wk.grp >> 1);
+        vside = (DIR == 0) || (wk.grp & 1) == 0;
+        s = plane * P + (int)threadIdx.x;
+        active = plane < g.V / P && (int)threadIdx.x < P;
+    } else {
+        vside = (DIR == 0) || (wave & 1) == 0;
+        const int grp = (DIR == 0) ? wk.grp * GPB + wave : wk.grp * GPB + (wave >> 1);
+        s = grp * 64 + (threadIdx.x & 63);
+        active = (grp < ngroups) && (s < g.V);
+    }
     const T ep = T(S->emu), em = T(S->emu_inv);
     const size_t HALF = (size_t)12 * Vp;
     const cpx<T>* Vf = (const cpx<T>*)p.outV + rhs * p.sV;
@@ -720,20 +745,50 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
             else { xfBA = T(-1); xbBA = T(1); }          // bottom += (d/dmu H)^dag wt
         }
     }
+    // LDS entry q of field f at plane site t (PLANE only)
+    auto lds_at = [&](int f, int q, int t) -> float4& { return plane_lds[((size_t)f * NQ + q) * P + t]; };
+    auto to_lds = [&](int f, int t, const cpx<T> (&v)[12]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float4 e;
+            if constexpr (sizeof(T) == 8) {
+                const double2 d{(double)v[q].re, (double)v[q].im};
+                e = *reinterpret_cast<const float4*>(&d);
+            } else {
+                e = float4{(float)v[2 * q].re, (float)v[2 * q].im, (float)v[2 * q + 1].re, (float)v[2 * q + 1].im};
+            }
+            lds_at(f, q, t) = e;
+        }
+    };
+    auto from_lds = [&](int f, int t, cpx<T> (&v)[12]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float4 e = lds_at(f, q, t);
+            if constexpr (sizeof(T) == 8) {
+                const double2 d = *reinterpret_cast<const double2*>(&e);
+                v[q] = cpx<T>{(T)d.x, (T)d.y};
+            } else {
+                v[2 * q] = cpx<T>{(T)e.x, (T)e.y};
+                v[2 * q + 1] = cpx<T>{(T)e.z, (T)e.w};
+            }
+        }
+    };
+    (void)to_lds;
+    (void)from_lds;
 
     double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const char* Ab = reinterpret_cast<const char*>(Ain);
+    const char* Bb = reinterpret_cast<const char*>(Bin);
+    const char* Xb = p.xproj ? reinterpret_cast<const char*>((const cpx<T>*)p.xproj + rhs * p.sx) : nullptr;
+    const uint32_t Vp16 = (uint32_t)Vp * 16u, so = (uint32_t)s * 16u;
+    cpx<T> accA[12], accB[12];
     if (active) {
-        const Nbr N = neighbours(g, s);
-        const char* Ab = reinterpret_cast<const char*>(Ain);
-        const char* Bb = reinterpret_cast<const char*>(Bin);
-        const char* Xb = p.xproj ? reinterpret_cast<const char*>((const cpx<T>*)p.xproj + rhs * p.sx) : nullptr;
-        const uint32_t Vp16 = (uint32_t)Vp * 16u, so = (uint32_t)s * 16u;
-        cpx<T> accA[12], accB[12];
         // own site: mass term, and the reductions that need only the inputs,
         // one loaded field at a time (fences keep the loads of the phases apart)
         {
             cpx<T> a[12];
             ld_site<T>(Ab, Vp16, so, a);
+            if constexpr (PLANE) to_lds(0, (int)threadIdx.x, a);
 #pragma unroll
             for (int c = 0; c < 12; ++c) accA[c] = mdiag * a[c];
             nrm_acc(part, (DIR == 0 || vside) ? 6 : 7, a);
@@ -756,6 +811,7 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
         {
             cpx<T> b[12];
             ld_site<T>(Bb, Vp16, so, b);
+            if constexpr (PLANE) to_lds(1, (int)threadIdx.x, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) accB[c] = mdiag * b[c];
             nrm_acc(part, (DIR != 0 && vside) ? 6 : 7, b);
@@ -766,8 +822,32 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        pair_hops<T, DIR>(accA, accB, Ain, Bin, U, dU, N, s, Vp, cfA, cbA, cfB, cbB, xfAB, xbAB, xfBA, xbBA,
-                          g.bc_t, vside);
+    }
+    if constexpr (PLANE) __syncthreads();   // the plane's inputs are in LDS
+    if (active) {
+        const Nbr N = neighbours(g, s);
+        if constexpr (PLANE) {
+            // x and y hops from the plane in LDS (periodic within the plane)
+            const char* W = reinterpret_cast<const char*>(U);
+            const char* W2 = reinterpret_cast<const char*>(dU);
+            const int t = (int)threadIdx.x, Lx = g.L[0], Ly = g.L[1];
+            const int x = t % Lx, y = t / Lx;
+            const int txf = y * Lx + (x == Lx - 1 ? 0 : x + 1), txb = y * Lx + (x == 0 ? Lx - 1 : x - 1);
+            const int tyf = (y == Ly - 1 ? 0 : y + 1) * Lx + x, tyb = (y == 0 ? Ly - 1 : y - 1) * Lx + x;
+            const T h = T(-0.5), z = T(0);
+#define OVD_PL(I, TN, LS)                                                                                   \
+    pair_hop<T, I, DIR>(                                                                                    \
+        accA, accB, [&](cpx<T>(&v)[12]) { from_lds(0, TN, v); }, [&](cpx<T>(&v)[12]) { from_lds(1, TN, v); }, \
+        W, W2, Vp16, (uint32_t)(LS) * 16u, h, h, z, z, vside);                                              \
+    OVD_HOP_FENCE;
+            OVD_PL(0, txf, s)
+            OVD_PL(1, txb, N.b[0])
+            OVD_PL(2, tyf, s)
+            OVD_PL(3, tyb, N.b[1])
+#undef OVD_PL
+        }
+        pair_hops<T, DIR, PLANE>(accA, accB, Ain, Bin, U, dU, N, s, Vp, cfA, cbA, cfB, cbB, xfAB, xbAB, xfBA,
+                                 xbBA, g.bc_t, vside);
 #pragma unroll
         for (int c = 6; c < 12; ++c) {   // gamma5
             accA[c] = -accA[c];
@@ -870,9 +950,18 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
 }
 
 int tsl_stencil_blocks(const Geom& g, int dir, int gpb) {
+    if (gpb == PLANE_GPB) {   // one block per plane (and side)
+        const int items = (g.V / (g.L[0] * g.L[1])) * (dir == 0 ? 1 : 2);
+        return (items + 7) / 8 * 8;
+    }
     const int ngroups = (g.V + 63) / 64;
     if (gpb <= 0) gpb = dir == 0 ? 4 : 2;
     return ((ngroups + gpb - 1) / gpb + 7) / 8 * 8;   // nb * nrhs is a multiple of 8
+}
+
+bool tsl_plane_ok(const Geom& g) {
+    const int P = g.L[0] * g.L[1];
+    return P >= 128 && P <= 256;
 }
 
 template <typename T>
@@ -884,19 +973,37 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
     if (v.gpb <= 0) v.gpb = dir == 0 ? 4 : 2;
     dim3 grid(tsl_stencil_blocks(g, dir, v.gpb) * nrhs);
     const T md = T(m_diag);
-#define OVD_TSL(D, G, THREADS)                                                                                 \
-    tsl_stencil_kernel<T, D, G><<<grid, dim3(THREADS), 0, s>>>(g, p, U, dU, md, st, co, partials, counters, j, tau, \
-                                                              ngroups, nrhs, v.map)
+    // dynamic LDS: the plane's two input fields (PLANE_GPB only)
+    const size_t plds = (size_t)2 * 12 * g.L[0] * g.L[1] * sizeof(cpx<T>);
+#define OVD_TSL(D, G, THREADS, SHM)                                                                        \
+    tsl_stencil_kernel<T, D, G><<<grid, dim3(THREADS), SHM, s>>>(g, p, U, dU, md, st, co, partials, counters, j, \
+                                                                tau, ngroups, nrhs, v.map)
+#define OVD_TSL_PLANE(D)                                                                                   \
+    do {                                                                                                   \
+        static bool attr = false;                                                                          \
+        if (!attr) {                                                                                       \
+            (void)hipFuncSetAttribute((const void*)tsl_stencil_kernel<T, D, PLANE_GPB>,                     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);      \
+            attr = true;                                                                                   \
+        }                                                                                                  \
+        OVD_TSL(D, PLANE_GPB, 256, plds);                                                                  \
+    } while (0)
+    if (v.gpb == PLANE_GPB && !tsl_plane_ok(g)) v.gpb = dir == 0 ? 4 : 2;
+    grid = dim3(tsl_stencil_blocks(g, dir, v.gpb) * nrhs);
     if (dir == 0) {
-        if (v.gpb == 2) OVD_TSL(0, 2, 128);
-        else OVD_TSL(0, 4, 256);
+        if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(0);
+        else if (v.gpb == 2) OVD_TSL(0, 2, 128, 0);
+        else OVD_TSL(0, 4, 256, 0);
     } else if (dir == 1) {
-        if (v.gpb == 1) OVD_TSL(1, 1, 128);
-        else OVD_TSL(1, 2, 256);
+        if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(1);
+        else if (v.gpb == 1) OVD_TSL(1, 1, 128, 0);
+        else OVD_TSL(1, 2, 256, 0);
     } else {
-        if (v.gpb == 1) OVD_TSL(2, 1, 128);
-        else OVD_TSL(2, 2, 256);
+        if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(2);
+        else if (v.gpb == 1) OVD_TSL(2, 1, 128, 0);
+        else OVD_TSL(2, 2, 256, 0);
     }
+#undef OVD_TSL_PLANE
 #undef OVD_TSL
 }
 

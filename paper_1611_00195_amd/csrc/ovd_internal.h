@@ -135,7 +135,8 @@ void launch_unpack_spinor(const Geom& g, int n, const cpx<T>* in, long long stri
 // launch shape of the stencil kernels: XCD work order (0: nrhs/8 sources per
 // XCD over the whole lattice, needs nrhs % 8 == 0; 1: contiguous site-group
 // ranges per XCD, rhs innermost; < 0: default) and site groups per block
-// (apply_op: 2 or 4; Lanczos stencil DIR 0: 2 or 4, DIR 1/2: 1 or 2; <= 0: default)
+// (apply_op: 2 or 4; Lanczos stencil DIR 0: 2 or 4, DIR 1/2: 1 or 2, and 8 for one
+// block per xy-plane with the plane in LDS when 128 <= Lx Ly <= 256; <= 0: default)
 struct StencilVariant {
     int map = -1;
     int gpb = 0;
@@ -157,6 +158,8 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
 // reductions and scalar recurrence.  dir: 0 plain H, 1 block d/dmu, 2 block d/dlink.
 // blocks per right-hand side of the stencil kernel (size of its partial sums)
 int tsl_stencil_blocks(const Geom& g, int dir, int gpb = 0);
+// the plane-in-LDS launch shape (gpb 8) applies: 128 <= Lx Ly <= 256
+bool tsl_plane_ok(const Geom& g);
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,

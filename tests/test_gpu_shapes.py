@@ -9,29 +9,30 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (0, 4), (1, 4)])
+@pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (0, 4), (1, 4), (0, 8), (1, 8)])
 def test_forced_shapes_deriv_and_sign(shape):
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, host, ops, print_case, rel
-    dims, k, nrhs, mu = (4, 4, 4, 4), 32, 8, 0.3
+    # xy-plane of 12 x 11 = 132 sites: the plane-in-LDS shape (8) applies
+    dims, k, nrhs, mu = ((12, 11, 2, 4) if shape[1] == 8 else (4, 4, 4, 4)), 32, 8, 0.3
     print_case(test="shapes", shape=shape, dims=dims, nrhs=nrhs)
     U = synth.make_links(dims, 0.5, 901)
     lat = ovderiv.Lattice(dims, shape=shape)
     lat.set_links(dev(U))
     b = synth.make_sources(dims, nrhs, 902)
     h, hd, dh, dhd = ops(U, dims, mu)
-    if shape[1] in (1, 2):          # derivative stencil shapes
+    if shape[1] in (1, 2, 8):       # derivative stencil shapes
         y, dy, _ = lat.sign_apply_deriv(dev(b), mu, k)
         for r in (0, nrhs - 1):
             dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[r].ravel(), k)
             assert rel(host(dy)[r], dref) < 1e-10 and rel(host(y)[r], yref) < 1e-10
-    if shape[1] in (2, 4):          # plain stencil shapes (sign, Dw.v)
+    if shape[1] in (2, 4, 8):       # plain stencil shapes (sign, Dw.v)
         y = host(lat.sign_apply(dev(b), mu, k))
         for r in (0, nrhs - 1):
             ref, _ = tsl.krylov_sign(h, hd, b[r].ravel(), b[r].ravel(), k)
             assert rel(y[r], ref) < 1e-10
         from oracle import dirac
-        out = host(lat.apply_op(ovderiv.OP_H, mu, dev(b)))
+        out = host(lat.apply_op(ovderiv.OP_H, mu, dev(b)))   # Dw.v: shape 8 falls back to 4
         for r in (0, nrhs - 1):
             assert rel(out[r], dirac.flat(dirac.apply_h(U, b[r].ravel(), dims, mu))) < 1e-14
 
