@@ -213,6 +213,21 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
                                 int k, const void* b, void* y, void* dy,
                                 const void* x, double* xdy, ovd_stats* st);
 
+/* The overlap operator of eq. 1 (lattice spacing a = 1) and its derivative:
+ *   Db  = D_ov b = b + gamma5 sgn(H(mu)) b,     dDb = d/dt D_ov b = gamma5 d/dt sgn(H) b,
+ * with sgn(H) b and its derivative from ovd_sign_apply / ovd_sign_apply_deriv
+ * (same k, deflation and precision rules).  Db, dDb: device complex128
+ * [nrhs][V][4][3], either may be NULL (not both); dir as in
+ * ovd_sign_apply_deriv (used only for dDb). */
+ovd_status ovd_overlap_apply(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* b,
+                             void* Db, void* dDb, ovd_stats* st);
+
+/* Error estimate of Sec. 4 from sgn(A)^2 = 1: eps = |sgn(H)(sgn(H) b) - b| / (2 |b|)
+ * per source, with the k-step approximation applied twice.  eps: host
+ * double[nrhs]. */
+ovd_status ovd_sign_error_estimate(ovd_h h, int nrhs, const double* mu, int k, const void* b, double* eps,
+                                   ovd_stats* st);
+
 /* One lattice's share of an uneven batch: the arguments of
  * ovd_sign_apply_deriv for handle h, and its status on return. */
 typedef struct {

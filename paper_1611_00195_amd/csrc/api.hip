@@ -860,6 +860,52 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
     return deriv_impl<double>(h, nrhs, mu, dirk, k, b, y, dy, x, xdy, st);
 }
 
+ovd_status ovd_overlap_apply(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* b,
+                             void* Db, void* dDb, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !b || (!Db && !dDb)) return fail(h, OVD_EINVAL, "bad ovd_overlap_apply arguments");
+    const long long ns = (long long)nrhs * h->g.V;
+    if (!dDb) {
+        s = ovd_sign_apply(h, nrhs, mu, k, b, Db, st);                       // Db = sgn(H) b
+        if (s != OVD_OK) return s;
+        launch_gamma5_axpy(ns, 1.0, b, 1.0, Db, Db, h->stream);             // Db = b + gamma5 sgn(H) b
+    } else {
+        ovd_status wst = OVD_OK;
+        void* y = Db;
+        if (!y) {
+            WS(tmp, c64, "overlap_y", (size_t)ns * 12);
+            y = tmp;
+        }
+        s = ovd_sign_apply_deriv(h, nrhs, mu, dir, k, b, y, dDb, nullptr, nullptr, st);
+        if (s != OVD_OK) return s;
+        launch_gamma5_axpy(ns, 0.0, nullptr, 1.0, dDb, dDb, h->stream);      // d D b = gamma5 d sgn(H) b
+        if (Db) launch_gamma5_axpy(ns, 1.0, b, 1.0, Db, Db, h->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return OVD_OK;
+}
+
+ovd_status ovd_sign_error_estimate(ovd_h h, int nrhs, const double* mu, int k, const void* b, double* eps,
+                                   ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !b || !eps) return fail(h, OVD_EINVAL, "bad ovd_sign_error_estimate arguments");
+    ovd_status wst = OVD_OK;
+    const long long ns = (long long)nrhs * h->g.V;
+    WS(y, c64, "eps_y", (size_t)ns * 12);
+    WS(z, c64, "eps_z", (size_t)ns * 12);
+    WS(e, double, "eps_out", nrhs);
+    s = ovd_sign_apply(h, nrhs, mu, k, b, y, st);
+    if (s != OVD_OK) return s;
+    s = ovd_sign_apply(h, nrhs, mu, k, y, z, nullptr);
+    if (s != OVD_OK) return s;
+    launch_half_rel_diff(nrhs, (long long)h->g.V * 12, z, b, e, h->stream);
+    HIPCHK(hipMemcpyAsync(eps, e, sizeof(double) * nrhs, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return OVD_OK;
+}
+
 ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs) {
     if (njobs < 1 || !jobs) return OVD_EINVAL;
     for (int i = 0; i < njobs; ++i) {

@@ -131,4 +131,51 @@ void launch_scalar_dot(int nrhs, int k, const c64* c, const c64* proj, int ld, c
     scalar_dot_kernel<<<nrhs, 256, 0, s>>>(k, c, proj, ld, scale, out);
 }
 
+// AoS complex128 [n][V][4][3]: out = cb b + cy gamma5 y  (gamma5 = diag(1, 1, -1, -1) on the spin)
+__global__ void gamma5_axpy_kernel(long long n_sites, double cb, const c64* __restrict__ b, double cy,
+                                   const c64* __restrict__ y, c64* __restrict__ out) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_sites * 12) return;
+    const int spin = (int)((t % 12) / 3);
+    const double g = spin < 2 ? cy : -cy;
+    c64 r = g * y[t];
+    if (b) r += cb * b[t];
+    out[t] = r;
+}
+
+void launch_gamma5_axpy(long long n_sites, double cb, const void* b, double cy, const void* y, void* out,
+                        hipStream_t s) {
+    const long long n = n_sites * 12;
+    gamma5_axpy_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n_sites, cb, (const c64*)b, cy, (const c64*)y,
+                                                                   (c64*)out);
+}
+
+// per field: out[r] = |a[r] - b[r]| / (2 |b[r]|)  (AoS complex128, m elements each); one block per field
+__global__ void half_rel_diff_kernel(long long m, const c64* __restrict__ a, const c64* __restrict__ b,
+                                     double* __restrict__ out) {
+    __shared__ double sd[256], sb[256];
+    const c64* A = a + (size_t)blockIdx.x * m;
+    const c64* B = b + (size_t)blockIdx.x * m;
+    double d = 0.0, n = 0.0;
+    for (long long i = threadIdx.x; i < m; i += blockDim.x) {
+        d += norm2(A[i] - B[i]);
+        n += norm2(B[i]);
+    }
+    sd[threadIdx.x] = d;
+    sb[threadIdx.x] = n;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            sd[threadIdx.x] += sd[threadIdx.x + k];
+            sb[threadIdx.x] += sb[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(sd[0]) / (2.0 * sqrt(sb[0]));
+}
+
+void launch_half_rel_diff(int n, long long m, const void* a, const void* b, double* out, hipStream_t s) {
+    half_rel_diff_kernel<<<n, 256, 0, s>>>(m, (const c64*)a, (const c64*)b, out);
+}
+
 }  // namespace ovd

@@ -201,6 +201,12 @@ template <typename T>
 void launch_convert_field(const Geom& g, int n, const c64* in, long long sin, cpx<T>* out, long long sout,
                           hipStream_t s);
 
+// AoS complex128 fields: out = cb b + cy gamma5 y (b may be null)
+void launch_gamma5_axpy(long long n_sites, double cb, const void* b, double cy, const void* y, void* out,
+                        hipStream_t s);
+// out[r] = |a_r - b_r| / (2 |b_r|) for n AoS complex128 fields of m complex each (device out)
+void launch_half_rel_diff(int n, long long m, const void* a, const void* b, double* out, hipStream_t s);
+
 // FP32 internal fields -> FP64 internal fields (n fields, strides in elements)
 void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64* out, long long sout, hipStream_t s);
 

@@ -30,7 +30,8 @@ EXPORTS = [
     "ovd_create_lattice", "ovd_destroy", "ovd_last_error", "ovd_set_stream", "ovd_set_links",
     "ovd_apply_op", "ovd_set_deflation", "ovd_clear_deflation", "ovd_sign_apply",
     "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag", "ovd_compute_deflation",
-    "ovd_get_deflation", "ovd_sign_apply_deriv_batch", "ovd_get_tuned",
+    "ovd_get_deflation", "ovd_sign_apply_deriv_batch", "ovd_get_tuned", "ovd_overlap_apply",
+    "ovd_sign_error_estimate",
 ]
 
 
@@ -104,6 +105,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ovd_apply_op": (i, [vp, i, d, ctypes.POINTER(_Dir), i, vp, vp, dp]),
         "ovd_set_deflation": (i, [vp, d, i, dp, vp, vp, i, vp, vp, ctypes.POINTER(_Dir)]),
         "ovd_clear_deflation": (i, [vp]),
+        "ovd_overlap_apply": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, ctypes.POINTER(_Stats)]),
+        "ovd_sign_error_estimate": (i, [vp, i, dp, i, vp, dp, ctypes.POINTER(_Stats)]),
         "ovd_get_tuned": (i, [vp, ctypes.c_char_p, i]),
         "ovd_sign_apply_deriv_batch": (i, [i, ctypes.POINTER(_Job)]),
         "ovd_get_deflation": (i, [vp, d, ctypes.POINTER(i), ctypes.POINTER(i), dp, vp, vp, vp, vp]),
@@ -264,6 +267,31 @@ class Lattice:
         if xdy is not None:
             s = [complex(xdy[2 * i], xdy[2 * i + 1]) for i in range(n)]
         return y, dy, s
+
+    def overlap_apply(self, b, mu, k, deriv=False, direction="mu", dU=None):
+        """D_ov b = b + gamma5 sgn(H) b (eq. 1, a = 1), and with deriv=True also
+        d/dt D_ov b = gamma5 d/dt sgn(H) b.  Returns Db or (Db, dDb)."""
+        n = b.shape[0]
+        _check_field(b, (n, self.V, 4, 3), "b")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        d, keep = self._dir(direction if deriv else None, dU)
+        Db = torch.empty_like(b)
+        dDb = torch.empty_like(b) if deriv else None
+        st = _Stats()
+        self._call("ovd_overlap_apply", n, _dbl(mus), ctypes.byref(d), int(k), _ptr(b), _ptr(Db), _ptr(dDb),
+                   ctypes.byref(st))
+        self.last_stats = self._stats(st)
+        return (Db, dDb) if deriv else Db
+
+    def sign_error_estimate(self, b, mu, k):
+        """Sec. 4 estimate |sgn(H)^2 b - b| / (2 |b|) per source (k steps, applied twice)."""
+        n = b.shape[0]
+        _check_field(b, (n, self.V, 4, 3), "b")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        eps = (ctypes.c_double * n)()
+        st = _Stats()
+        self._call("ovd_sign_error_estimate", n, _dbl(mus), int(k), _ptr(b), eps, ctypes.byref(st))
+        return [eps[i] for i in range(n)]
 
     def sign_apply_vjp(self, x, b, mu, k, force=True, wirtinger=False, grad=True):
         """s = <x|sgn(H(mu))|b>, ds/dmu and the link gradients (FP64).

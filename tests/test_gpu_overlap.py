@@ -1,0 +1,50 @@
+"""GPU parity of the overlap operator (eq. 1), its mu-derivative and the
+Sec. 4 error estimate against the oracle at the same Krylov size."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, estimator, overlap, tsl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_overlap_and_derivative_parity():
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, print_case, rel
+    dims, k, mu = (4, 4, 4, 4), 48, 0.3
+    print_case(test="overlap", dims=dims, k=k)
+    U = synth.make_links(dims, 0.5, 941)
+    b = synth.make_sources(dims, 2, 942)
+    lat = ovderiv.Lattice(dims)
+    lat.set_links(dev(U))
+    Db = host(lat.overlap_apply(dev(b), mu, k))
+    Db2, dDb = lat.overlap_apply(dev(b), mu, k, deriv=True)
+    for r in range(2):
+        assert rel(Db[r], overlap.krylov_overlap(U, dims, mu, b[r], k)) < 1e-10
+        assert rel(host(dDb)[r], overlap.krylov_overlap_deriv(U, dims, mu, b[r], k)) < 1e-10
+    # the function half of the block run is a different Krylov approximation of the same D b
+    assert rel(host(Db2), Db) < 1e-3
+
+
+def test_error_estimate_parity():
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, print_case
+    dims, mu = (4, 4, 4, 4), 0.3
+    print_case(test="eps_estimate", dims=dims)
+    U = synth.make_links(dims, 0.5, 943)
+    b = synth.make_sources(dims, 2, 944)
+    lat = ovderiv.Lattice(dims)
+    lat.set_links(dev(U))
+    h = lambda v: dirac.flat(dirac.apply_h(U, v, dims, mu))
+    hd = lambda v: dirac.flat(dirac.apply_hdag(U, v, dims, mu))
+    prev = None
+    for k in (32, 64):
+        eps = lat.sign_error_estimate(dev(b), mu, k)
+        for r in range(2):
+            ref = estimator.eps_sign(lambda v: tsl.krylov_sign(h, hd, v, v, k)[0], b[r])
+            assert abs(eps[r] - ref) < 1e-6 * ref
+        if prev is not None:
+            assert max(eps) < max(prev)
+        prev = eps
