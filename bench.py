@@ -44,11 +44,13 @@ def update_bytes_per_site(prec_bytes: int) -> float:
     return 2 * (3 + 1) * 2 * 12 * 2 * prec_bytes
 
 
-def measured_traffic(pb: int, nrhs: int):
+def measured_traffic(pb: int, nrhs: int, shapes: str = ""):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current stencil source and this workload;
-    else None."""
+    summary, if it was taken on the current stencil source, this workload and
+    the launch shape (groups per block) the autotuner kept in this run; else
+    None."""
     import hashlib
+    import re
     src = os.path.join(ROOT, "paper_1611_00195_amd", "csrc", "kernels_stencil.hip")
     path = os.path.join(ROOT, "profiles", "tsl_stencil_14x14cubed_traffic.txt")
     if not os.path.exists(path):
@@ -61,6 +63,11 @@ def measured_traffic(pb: int, nrhs: int):
             kv[a.strip()] = b.strip()
     key = f"bytes_per_launch_{'fp64' if pb == 8 else 'fp32'}_nrhs{nrhs}"
     if kv.get("kernels_stencil_sha256_16") != digest or key not in kv:
+        return None
+    tag = "fp64" if pb == 8 else "fp32"
+    prof_gpb = re.search(r",\s*(\d+)>", kv.get(f"kernel_{tag}_nrhs{nrhs}", ""))
+    run_gpb = re.search(r"gpb(\d+)", shapes)
+    if prof_gpb and run_gpb and prof_gpb.group(1) != run_gpb.group(1):
         return None
     return float(kv[key])
 
@@ -101,6 +108,7 @@ def time_form(args, U, prec, n, steps, warmup, V, step_timing=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     res = {key: v / steps for key, v in acc.items()}
+    res.update(shapes=lat.tuned_shapes())
     res.update(evals_per_s=n * steps / dt, ms_per_step=1e3 * dt / steps, vals=vals,
                min_margin=lat.last_stats.min_margin, sign_check=lat.last_stats.sign_check)
     lat.close()
@@ -142,8 +150,9 @@ def run_gpu(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(pb, n),
+            "traffic": measured_traffic(pb, n, prof["shapes"]),
             "kernel": "tsl_stencil_kernel",
+            "launch_shape": prof["shapes"],
             "bytes_per_launch": bytes_launch,
             "us_per_launch": round(st_ms * 1e3, 2),
         },
