@@ -85,6 +85,12 @@ typedef struct {
                                for derivatives, 2 or 4 otherwise, or 8: one block per
                                xy-plane staged in LDS, when 128 <= Lx Ly <= 256; Dw.v: 2 or 4);
                                0: tuned */
+    int shape_seq;          /* Lanczos stencil without the derivative of a link field, not the
+                               LDS-plane shape: 1 forces the sequential form (each thread
+                               finishes one of its two outputs before the other: half the
+                               live accumulators, twice the waves per SIMD in FP64), 0 the
+                               paired form (both outputs at once, every link loaded once);
+                               -1 (default): tuned, else paired */
 } ovd_options;
 
 typedef struct {
@@ -255,8 +261,8 @@ typedef struct {
 ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs);
 
 /* Gradient of s = <x|sgn(H(mu))|b> (the bilinear the paper's currents and
- * fermionic force are built from, Sec. 1), FP64 whatever the handle's
- * precision: two-sided Lanczos with right start b and left start x,
+ * fermionic force are built from, Sec. 1): two-sided Lanczos with right
+ * start b and left start x (precision below),
  * s ~ (x^dag b)[sgn(T_k)]_11, and with M_k = L_sgn(T_k, e_1 e_1^T) the
  * derivative ds/dt ~ (x^dag b) tr(M_k W_k^dag (dH/dt) V_k), evaluated for every
  * link at once through Z = W_k M_k^dag.  Deflation is not applied.
@@ -275,8 +281,9 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
                               double* s, double* ds_dmu, void* F, void* dsdU, void* dsdUc,
                               ovd_stats* st);
 
-/* Launch shapes chosen by the autotuner so far, as text
- * "kernel:precision:dir-or-op:nrhs=map<m>,gpb<g>;..." into buf (host, len
+/* Launch shapes in use so far (chosen by the autotuner, or forced through the
+ * options), as text
+ * "kernel:precision:dir-or-op:nrhs=map<m>,gpb<g>[,seq];..." into buf (host, len
  * bytes, truncated and NUL-terminated). */
 ovd_status ovd_get_tuned(ovd_h h, char* buf, int len);
 

@@ -161,18 +161,24 @@ StencilVariant autotune(ovd_h h, const std::vector<StencilVariant>& cands, Launc
 
 // a shape forced through the options, completed with defaults; false if none is forced
 bool forced_shape(ovd_h h, int nrhs, int def_gpb, StencilVariant* v) {
-    if (h->opt.shape_map < 0 && h->opt.shape_gpb <= 0) return false;
+    if (h->opt.shape_map < 0 && h->opt.shape_gpb <= 0 && h->opt.shape_seq < 0) return false;
     v->map = h->opt.shape_map >= 0 ? h->opt.shape_map : default_map(nrhs);
     if (v->map == 0 && nrhs % 8 != 0) v->map = 1;
     v->gpb = h->opt.shape_gpb > 0 ? h->opt.shape_gpb : def_gpb;
+    v->seq = h->opt.shape_seq > 0 ? 1 : 0;
     return true;
 }
 
-std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& gpbs) {
+// launch shapes to time: both work orders, the given groups per block, and
+// with seq_too the sequential form of each (the LDS-plane shape has none)
+std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& gpbs, bool seq_too = false) {
     std::vector<StencilVariant> c;
     for (int map : {1, 0}) {
         if (map == 0 && nrhs % 8 != 0) continue;
-        for (int gpb : gpbs) c.push_back(StencilVariant{map, gpb});
+        for (int gpb : gpbs) {
+            c.push_back(StencilVariant{map, gpb, 0});
+            if (seq_too && gpb != 8) c.push_back(StencilVariant{map, gpb, 1});
+        }
     }
     return c;
 }
@@ -320,6 +326,8 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             if (var.gpb == 8 && !tsl_plane_ok(g)) var.gpb = 0;
             if (dir == 0 && var.gpb != 2 && var.gpb != 8) var.gpb = 4;
             if (dir != 0 && var.gpb != 1 && var.gpb != 8) var.gpb = 2;
+            if (dir == 2 || var.gpb == 8) var.seq = 0;
+            h->tuned[key] = var;
         } else if (it != h->tuned.end()) {
             var = it->second;
         } else if (h->opt.autotune) {
@@ -338,8 +346,10 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             p0.sx = (long long)12 * g.Vp;
             var = autotune(
                 h,
-                shape_candidates(nrhs, tsl_plane_ok(g) ? (dir == 0 ? std::vector<int>{4, 2, 8} : std::vector<int>{2, 1, 8})
-                                                       : (dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1})),
+                shape_candidates(nrhs,
+                                 tsl_plane_ok(g) ? (dir == 0 ? std::vector<int>{4, 2, 8} : std::vector<int>{2, 1, 8})
+                                                 : (dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1}),
+                                 dir != 2),
                 [&](StencilVariant v) {
                     launch_tsl_stencil<T>(g, dir, nrhs, p0, U, dU, md, tst, tco, tpart, tcnt, 0, h->opt.breakdown_tol,
                                           h->stream, v);
@@ -392,7 +402,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             sizeof(T), (uintptr_t)dir, (uintptr_t)nrhs, (uintptr_t)k, (uintptr_t)ring, (uintptr_t)basis,
             (uintptr_t)basis_w, (uintptr_t)xproj, (uintptr_t)U, (uintptr_t)dU, (uintptr_t)st, (uintptr_t)coef,
             (uintptr_t)partials, (uintptr_t)counters, (uintptr_t)tb, (uintptr_t)mb, (uintptr_t)g.V,
-            (uintptr_t)var.map, (uintptr_t)var.gpb};
+            (uintptr_t)var.map, (uintptr_t)var.gpb, (uintptr_t)var.seq};
         hipGraphExec_t exec = nullptr;
         for (auto& e : h->graphs)
             if (e.key == key) exec = e.exec;
@@ -716,6 +726,7 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.autotune = 1;
     h->opt.shape_map = -1;
     h->opt.shape_gpb = 0;
+    h->opt.shape_seq = -1;
     if (opt) {
         h->opt = *opt;
         if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
@@ -802,6 +813,7 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
         StencilVariant fv;
         if (forced_shape(h, nrhs, 4, &fv)) {
             if (fv.gpb != 2) fv.gpb = 4;
+            fv.seq = 0;
             h->tuned[key] = fv;
         } else if (!h->tuned.count(key)) {
             h->tuned[key] = h->opt.autotune ? autotune(h, shape_candidates(nrhs, {4, 2}), launch, [] {})
@@ -821,6 +833,7 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
         StencilVariant fv;
         if (forced_shape(h, nrhs, 4, &fv)) {
             if (fv.gpb != 2) fv.gpb = 4;
+            fv.seq = 0;
             h->tuned[key] = fv;
         } else if (!h->tuned.count(key)) {
             h->tuned[key] = h->opt.autotune ? autotune(h, shape_candidates(nrhs, {4, 2}), launch, [] {})
@@ -936,7 +949,8 @@ ovd_status ovd_get_tuned(ovd_h h, char* buf, int len) {
     if (!h || !buf || len < 1) return OVD_EINVAL;
     std::string out;
     for (const auto& kv : h->tuned)
-        out += kv.first + "=map" + std::to_string(kv.second.map) + ",gpb" + std::to_string(kv.second.gpb) + ";";
+        out += kv.first + "=map" + std::to_string(kv.second.map) + ",gpb" + std::to_string(kv.second.gpb) +
+               (kv.second.seq ? ",seq;" : ";");
     std::strncpy(buf, out.c_str(), (size_t)len - 1);
     buf[len - 1] = 0;
     return OVD_OK;

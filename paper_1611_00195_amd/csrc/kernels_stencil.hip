@@ -20,6 +20,8 @@
 // gives each of the eight XCDs a contiguous slab of sites.  Every hop issues
 // all of its loads before any arithmetic (branch-free, one load batch per
 // hop), which is what keeps enough bytes in flight.
+#include <type_traits>
+
 #include "ovd_internal.h"
 
 // scheduling fence between the hops of a site (limits how far the compiler
@@ -31,6 +33,12 @@
 // scheduling fence between the two inputs of a paired hop; empty = none
 #ifndef OVD_PAIR_FENCE
 #define OVD_PAIR_FENCE
+#endif
+
+// scheduling fence between the hops of the sequential form (without it the
+// compiler hoists the loads of all eight hops and spills); empty = none
+#ifndef OVD_SEQ_FENCE
+#define OVD_SEQ_FENCE __builtin_amdgcn_sched_barrier(0)
 #endif
 
 // occupancy hint for the stencil kernels (waves per SIMD), by precision T;
@@ -665,6 +673,83 @@ __device__ __forceinline__ void pair_hops(cpx<T> (&accA)[12], cpx<T> (&accB)[12]
     (void)so;
 }
 
+// One output of a pair, hop I ("sequential" form: the thread finishes one
+// output before it starts the other, so only one 12-entry accumulator is live):
+//   acc += recon(link * proj(c P(n) + c x Q(n)))
+// where Q, the other input of the pair, enters only on the time hops of the mu
+// derivative for the output that has them (MIX; x = its mix factor).
+template <typename T, int I, bool MIX, typename LoadP, typename LoadQ>
+__device__ __forceinline__ void single_hop(cpx<T> (&acc)[12], LoadP loadP, LoadQ loadQ, const char* __restrict__ W,
+                                           uint32_t Vp16, uint32_t loff, T c, T x) {
+    constexpr bool fwd = (I & 1) == 0;
+    cpx<T> u[9];
+    ld_link<T>(W, Vp16, I >> 1, loff, u);
+    cpx<T> h0[3], h1[3], g0[3], g1[3];
+    {
+        cpx<T> v[12];
+        loadP(v);
+        proj_ct<T, I>(v, h0, h1);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        h0[a] = c * h0[a];
+        h1[a] = c * h1[a];
+    }
+    if constexpr (MIX) {
+        cpx<T> v[12], q0[3], q1[3];
+        loadQ(v);
+        proj_ct<T, I>(v, q0, q1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0[a] += (c * x) * q0[a];
+            h1[a] += (c * x) * q1[a];
+        }
+    }
+    link_mul<T, fwd>(u, h0, h1, g0, g1);
+    recon_add<T, I>(acc, g0, g1);
+}
+
+// The same pointer, opaque to the optimiser: the loads of the second pass of
+// the sequential form are issued again instead of being forwarded from the
+// first pass (which would keep all eight links live between the passes).
+template <typename P>
+__device__ __forceinline__ P opaque_ptr(P p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// All eight hops of one output (DIR 0 or 1): P the input of this output, Q the
+// other input of the pair, cf/cb the forward/backward hop factors; USEQ: the
+// output has the mix terms xf/xb on its time hops.
+template <typename T, bool USEQ>
+__device__ __forceinline__ void single_hops(cpx<T> (&acc)[12], const cpx<T>* Pf, const cpx<T>* Qf,
+                                            const cpx<T>* Wf, const Nbr& N, int s, int Vp, T cf, T cb, T xf, T xb,
+                                            int bc) {
+    const char* P = reinterpret_cast<const char*>(Pf);
+    const char* Q = reinterpret_cast<const char*>(Qf);
+    const char* W = reinterpret_cast<const char*>(Wf);
+    const uint32_t Vp16 = (uint32_t)Vp * 16u;
+    const T h = T(-0.5), z = T(0);
+#define OVD_SH(I, NB, LS, C, X)                                                                               \
+    {                                                                                                         \
+        const uint32_t noff = (uint32_t)(NB) * 16u;                                                           \
+        single_hop<T, I, USEQ && (I >= 6)>(                                                                   \
+            acc, [&](cpx<T>(&v)[12]) { ld_site<T>(P, Vp16, noff, v); },                                       \
+            [&](cpx<T>(&v)[12]) { ld_site<T>(Q, Vp16, noff, v); }, W, Vp16, (uint32_t)(LS) * 16u, C, X);      \
+    }                                                                                                         \
+    OVD_SEQ_FENCE;
+    OVD_SH(0, N.f[0], s, h, z)
+    OVD_SH(1, N.b[0], N.b[0], h, z)
+    OVD_SH(2, N.f[1], s, h, z)
+    OVD_SH(3, N.b[1], N.b[1], h, z)
+    OVD_SH(4, N.f[2], s, h, z)
+    OVD_SH(5, N.b[2], N.b[2], h, z)
+    const T sf = N.wf ? T(bc) : T(1), sb = N.wb ? T(bc) : T(1);
+    OVD_SH(6, N.f[3], s, h * cf * sf, xf)
+    OVD_SH(7, N.b[3], N.b[3], h * cb * sb, xb)
+#undef OVD_SH
+}
+
 // partial sums of the step: 0,1 omega; 2,3 gamma; 4,5 p; 6 |vhat|^2; 7 |what|^2
 template <typename T>
 __device__ __forceinline__ void dot_acc(double* part, int i, const cpx<T> (&a)[12], const cpx<T> (&b)[12]) {
@@ -688,7 +773,7 @@ __device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[1
 // fields staged in LDS for the x and y hops.
 constexpr int PLANE_GPB = 8;
 
-template <typename T, int DIR, int GPB>
+template <typename T, int DIR, int GPB, bool SEQ>
 __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
                                                           const cpx<T>* __restrict__ dU, T mdiag,
                                                           TslState* __restrict__ st, TslCoeffs co,
@@ -696,6 +781,7 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
                                                           unsigned* __restrict__ counters, int j, double tau,
                                                           int ngroups, int nrhs, int map) {
     constexpr bool PLANE = GPB == PLANE_GPB;
+    static_assert(!SEQ || (!PLANE && DIR != 2), "sequential form: DIR 0/1 without the plane in LDS");
     constexpr int NQ = sizeof(T) == 8 ? 12 : 6;     // 16-byte entries per site
     extern __shared__ float4 plane_lds[];           // PLANE: [2][NQ][P]
     __shared__ double lds[16 * 8];
@@ -781,98 +867,173 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
     const char* Bb = reinterpret_cast<const char*>(Bin);
     const char* Xb = p.xproj ? reinterpret_cast<const char*>((const cpx<T>*)p.xproj + rhs * p.sx) : nullptr;
     const uint32_t Vp16 = (uint32_t)Vp * 16u, so = (uint32_t)s * 16u;
-    cpx<T> accA[12], accB[12];
-    if (active) {
-        // own site: mass term, and the reductions that need only the inputs,
-        // one loaded field at a time (fences keep the loads of the phases apart)
-        {
-            cpx<T> a[12];
-            ld_site<T>(Ab, Vp16, so, a);
-            if constexpr (PLANE) to_lds(0, (int)threadIdx.x, a);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) accA[c] = mdiag * a[c];
-            nrm_acc(part, (DIR == 0 || vside) ? 6 : 7, a);
-            if ((DIR == 0 || vside) && Xb) {          // p = x^dag vhat_top
-                cpx<T> x[12];
-                ld_site<T>(Xb, Vp16, so, x);
-                dot_acc(part, 4, x, a);
-            }
-            if (DIR == 0) {                           // omega = what^dag vhat
-                cpx<T> b[12];
-                ld_site<T>(Bb, Vp16, so, b);
-                dot_acc(part, 0, b, a);
-            } else if (!vside) {                      // omega, top halves: wt^dag vt
-                cpx<T> v[12];
-                ld_site<T>(reinterpret_cast<const char*>(Vf), Vp16, so, v);
-                dot_acc(part, 0, a, v);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        {
-            cpx<T> b[12];
-            ld_site<T>(Bb, Vp16, so, b);
-            if constexpr (PLANE) to_lds(1, (int)threadIdx.x, b);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) accB[c] = mdiag * b[c];
-            nrm_acc(part, (DIR != 0 && vside) ? 6 : 7, b);
-            if (DIR != 0 && !vside) {                 // omega, bottom halves: wb^dag vb
-                cpx<T> v[12];
-                ld_site<T>(reinterpret_cast<const char*>(Vf + HALF), Vp16, so, v);
-                dot_acc(part, 0, b, v);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    if constexpr (PLANE) __syncthreads();   // the plane's inputs are in LDS
-    if (active) {
-        const Nbr N = neighbours(g, s);
-        if constexpr (PLANE) {
-            // x and y hops from the plane in LDS (periodic within the plane)
-            const char* W = reinterpret_cast<const char*>(U);
-            const char* W2 = reinterpret_cast<const char*>(dU);
-            const int t = (int)threadIdx.x, Lx = g.L[0], Ly = g.L[1];
-            const int x = t % Lx, y = t / Lx;
-            const int txf = y * Lx + (x == Lx - 1 ? 0 : x + 1), txb = y * Lx + (x == 0 ? Lx - 1 : x - 1);
-            const int tyf = (y == Ly - 1 ? 0 : y + 1) * Lx + x, tyb = (y == 0 ? Ly - 1 : y - 1) * Lx + x;
-            const T h = T(-0.5), z = T(0);
-#define OVD_PL(I, TN, LS)                                                                                   \
-    pair_hop<T, I, DIR>(                                                                                    \
-        accA, accB, [&](cpx<T>(&v)[12]) { from_lds(0, TN, v); }, [&](cpx<T>(&v)[12]) { from_lds(1, TN, v); }, \
-        W, W2, Vp16, (uint32_t)(LS) * 16u, h, h, z, z, vside);                                              \
-    OVD_HOP_FENCE;
-            OVD_PL(0, txf, s)
-            OVD_PL(1, txb, N.b[0])
-            OVD_PL(2, tyf, s)
-            OVD_PL(3, tyb, N.b[1])
-#undef OVD_PL
-        }
-        pair_hops<T, DIR, PLANE>(accA, accB, Ain, Bin, U, dU, N, s, Vp, cfA, cbA, cfB, cbB, xfAB, xbAB, xfBA,
-                                 xbBA, g.bc_t, vside);
-#pragma unroll
-        for (int c = 6; c < 12; ++c) {   // gamma5
-            accA[c] = -accA[c];
-            accB[c] = -accB[c];
-        }
-        store_site<T>(reinterpret_cast<char*>(Aout), Vp16, so, accA);
-        store_site<T>(reinterpret_cast<char*>(Bout), Vp16, so, accB);
-        // gamma = what^dag (A vhat)
-        if (DIR == 0) {                // = (A^dag what)^dag vhat = accB^dag vhat
-            cpx<T> v[12];
-            ld_site<T>(Ab, Vp16, so, v);
-            dot_acc(part, 2, accB, v);
-        } else if (vside) {
+    if constexpr (SEQ) {
+        // the two outputs one after the other, each with its own-site terms,
+        // eight hops, store and gamma contribution; one straight-line body per
+        // side (VS: the v side; DIR 0 has one side)
+        auto body = [&](auto vs_tag) {
+            constexpr bool VS = decltype(vs_tag)::value;
+            const Nbr N = neighbours(g, s);
+            cpx<T> acc[12];
             {
+                cpx<T> a[12];
+                ld_site<T>(Ab, Vp16, so, a);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[c] = mdiag * a[c];
+                nrm_acc(part, (DIR == 0 || VS) ? 6 : 7, a);
+                if ((DIR == 0 || VS) && Xb) {             // p = x^dag vhat_top
+                    cpx<T> x[12];
+                    ld_site<T>(Xb, Vp16, so, x);
+                    dot_acc(part, 4, x, a);
+                }
+                if constexpr (DIR == 0) {                 // omega = what^dag vhat
+                    cpx<T> b[12];
+                    ld_site<T>(Bb, Vp16, so, b);
+                    dot_acc(part, 0, b, a);
+                } else if constexpr (!VS) {               // omega, top halves: wt^dag vt
+                    cpx<T> v[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Vf), Vp16, so, v);
+                    dot_acc(part, 0, a, v);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            single_hops<T, DIR == 1 && VS>(acc, Ain, Bin, U, N, s, Vp, cfA, cbA, xfAB, xbAB, g.bc_t);
+#pragma unroll
+            for (int c = 6; c < 12; ++c) acc[c] = -acc[c];   // gamma5
+            store_site<T>(reinterpret_cast<char*>(Aout), Vp16, so, acc);
+            if constexpr (DIR == 1 && VS) {               // gamma, top halves: wt^dag (A vhat)_top
                 cpx<T> w[12];
                 ld_site<T>(reinterpret_cast<const char*>(Wf), Vp16, so, w);
-                dot_acc(part, 2, w, accA);
+                dot_acc(part, 2, w, acc);
             }
             __builtin_amdgcn_sched_barrier(0);
             {
+                cpx<T> b[12];
+                ld_site<T>(Bb, Vp16, so, b);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[c] = mdiag * b[c];
+                nrm_acc(part, (DIR != 0 && VS) ? 6 : 7, b);
+                if constexpr (DIR != 0 && !VS) {          // omega, bottom halves: wb^dag vb
+                    cpx<T> v[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Vf + HALF), Vp16, so, v);
+                    dot_acc(part, 0, b, v);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            single_hops<T, DIR == 1 && !VS>(acc, opaque_ptr(Bin), opaque_ptr(Ain), opaque_ptr(U), N, s, Vp, cfB, cbB,
+                                            xfBA, xbBA, g.bc_t);
+#pragma unroll
+            for (int c = 6; c < 12; ++c) acc[c] = -acc[c];   // gamma5
+            store_site<T>(reinterpret_cast<char*>(Bout), Vp16, so, acc);
+            if constexpr (DIR == 0) {                     // gamma = (A^dag what)^dag vhat
+                cpx<T> v[12];
+                ld_site<T>(Ab, Vp16, so, v);
+                dot_acc(part, 2, acc, v);
+            } else if constexpr (VS) {                    // gamma, bottom halves: wb^dag (A vhat)_bottom
                 cpx<T> w[12];
                 ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
-                dot_acc(part, 2, w, accB);
+                dot_acc(part, 2, w, acc);
+            }
+        };
+        if (active) {
+            if (DIR == 0 || vside) body(std::integral_constant<bool, true>{});
+            else body(std::integral_constant<bool, false>{});
+        }
+    } else {
+        cpx<T> accA[12], accB[12];
+        if (active) {
+            // own site: mass term, and the reductions that need only the inputs,
+            // one loaded field at a time (fences keep the loads of the phases apart)
+            {
+                cpx<T> a[12];
+                ld_site<T>(Ab, Vp16, so, a);
+                if constexpr (PLANE) to_lds(0, (int)threadIdx.x, a);
+    #pragma unroll
+                for (int c = 0; c < 12; ++c) accA[c] = mdiag * a[c];
+                nrm_acc(part, (DIR == 0 || vside) ? 6 : 7, a);
+                if ((DIR == 0 || vside) && Xb) {          // p = x^dag vhat_top
+                    cpx<T> x[12];
+                    ld_site<T>(Xb, Vp16, so, x);
+                    dot_acc(part, 4, x, a);
+                }
+                if (DIR == 0) {                           // omega = what^dag vhat
+                    cpx<T> b[12];
+                    ld_site<T>(Bb, Vp16, so, b);
+                    dot_acc(part, 0, b, a);
+                } else if (!vside) {                      // omega, top halves: wt^dag vt
+                    cpx<T> v[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Vf), Vp16, so, v);
+                    dot_acc(part, 0, a, v);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                cpx<T> b[12];
+                ld_site<T>(Bb, Vp16, so, b);
+                if constexpr (PLANE) to_lds(1, (int)threadIdx.x, b);
+    #pragma unroll
+                for (int c = 0; c < 12; ++c) accB[c] = mdiag * b[c];
+                nrm_acc(part, (DIR != 0 && vside) ? 6 : 7, b);
+                if (DIR != 0 && !vside) {                 // omega, bottom halves: wb^dag vb
+                    cpx<T> v[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Vf + HALF), Vp16, so, v);
+                    dot_acc(part, 0, b, v);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (PLANE) __syncthreads();   // the plane's inputs are in LDS
+        if (active) {
+            const Nbr N = neighbours(g, s);
+            if constexpr (PLANE) {
+                // x and y hops from the plane in LDS (periodic within the plane)
+                const char* W = reinterpret_cast<const char*>(U);
+                const char* W2 = reinterpret_cast<const char*>(dU);
+                const int t = (int)threadIdx.x, Lx = g.L[0], Ly = g.L[1];
+                const int x = t % Lx, y = t / Lx;
+                const int txf = y * Lx + (x == Lx - 1 ? 0 : x + 1), txb = y * Lx + (x == 0 ? Lx - 1 : x - 1);
+                const int tyf = (y == Ly - 1 ? 0 : y + 1) * Lx + x, tyb = (y == 0 ? Ly - 1 : y - 1) * Lx + x;
+                const T h = T(-0.5), z = T(0);
+    #define OVD_PL(I, TN, LS)                                                                                   \
+        pair_hop<T, I, DIR>(                                                                                    \
+            accA, accB, [&](cpx<T>(&v)[12]) { from_lds(0, TN, v); }, [&](cpx<T>(&v)[12]) { from_lds(1, TN, v); }, \
+            W, W2, Vp16, (uint32_t)(LS) * 16u, h, h, z, z, vside);                                              \
+        OVD_HOP_FENCE;
+                OVD_PL(0, txf, s)
+                OVD_PL(1, txb, N.b[0])
+                OVD_PL(2, tyf, s)
+                OVD_PL(3, tyb, N.b[1])
+    #undef OVD_PL
+            }
+            pair_hops<T, DIR, PLANE>(accA, accB, Ain, Bin, U, dU, N, s, Vp, cfA, cbA, cfB, cbB, xfAB, xbAB, xfBA,
+                                     xbBA, g.bc_t, vside);
+    #pragma unroll
+            for (int c = 6; c < 12; ++c) {   // gamma5
+                accA[c] = -accA[c];
+                accB[c] = -accB[c];
+            }
+            store_site<T>(reinterpret_cast<char*>(Aout), Vp16, so, accA);
+            store_site<T>(reinterpret_cast<char*>(Bout), Vp16, so, accB);
+            // gamma = what^dag (A vhat)
+            if (DIR == 0) {                // = (A^dag what)^dag vhat = accB^dag vhat
+                cpx<T> v[12];
+                ld_site<T>(Ab, Vp16, so, v);
+                dot_acc(part, 2, accB, v);
+            } else if (vside) {
+                {
+                    cpx<T> w[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Wf), Vp16, so, w);
+                    dot_acc(part, 2, w, accA);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    cpx<T> w[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
+                    dot_acc(part, 2, w, accB);
+                }
             }
         }
+
     }
 
     block_reduce<8>(part, lds);
@@ -975,33 +1136,44 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
     const T md = T(m_diag);
     // dynamic LDS: the plane's two input fields (PLANE_GPB only)
     const size_t plds = (size_t)2 * 12 * g.L[0] * g.L[1] * sizeof(cpx<T>);
-#define OVD_TSL(D, G, THREADS, SHM)                                                                        \
-    tsl_stencil_kernel<T, D, G><<<grid, dim3(THREADS), SHM, s>>>(g, p, U, dU, md, st, co, partials, counters, j, \
-                                                                tau, ngroups, nrhs, v.map)
+#define OVD_TSL(D, G, THREADS, SHM, SQ)                                                                    \
+    tsl_stencil_kernel<T, D, G, SQ><<<grid, dim3(THREADS), SHM, s>>>(g, p, U, dU, md, st, co, partials, counters, \
+                                                                    j, tau, ngroups, nrhs, v.map)
 #define OVD_TSL_PLANE(D)                                                                                   \
     do {                                                                                                   \
         static bool attr = false;                                                                          \
         if (!attr) {                                                                                       \
-            (void)hipFuncSetAttribute((const void*)tsl_stencil_kernel<T, D, PLANE_GPB>,                     \
+            (void)hipFuncSetAttribute((const void*)tsl_stencil_kernel<T, D, PLANE_GPB, false>,              \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);      \
             attr = true;                                                                                   \
         }                                                                                                  \
-        OVD_TSL(D, PLANE_GPB, 256, plds);                                                                  \
+        OVD_TSL(D, PLANE_GPB, 256, plds, false);                                                           \
     } while (0)
     if (v.gpb == PLANE_GPB && !tsl_plane_ok(g)) v.gpb = dir == 0 ? 4 : 2;
+    const bool seq = v.seq && dir != 2 && v.gpb != PLANE_GPB;
     grid = dim3(tsl_stencil_blocks(g, dir, v.gpb) * nrhs);
     if (dir == 0) {
         if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(0);
-        else if (v.gpb == 2) OVD_TSL(0, 2, 128, 0);
-        else OVD_TSL(0, 4, 256, 0);
+        else if (v.gpb == 2) {
+            if (seq) OVD_TSL(0, 2, 128, 0, true);
+            else OVD_TSL(0, 2, 128, 0, false);
+        } else {
+            if (seq) OVD_TSL(0, 4, 256, 0, true);
+            else OVD_TSL(0, 4, 256, 0, false);
+        }
     } else if (dir == 1) {
         if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(1);
-        else if (v.gpb == 1) OVD_TSL(1, 1, 128, 0);
-        else OVD_TSL(1, 2, 256, 0);
+        else if (v.gpb == 1) {
+            if (seq) OVD_TSL(1, 1, 128, 0, true);
+            else OVD_TSL(1, 1, 128, 0, false);
+        } else {
+            if (seq) OVD_TSL(1, 2, 256, 0, true);
+            else OVD_TSL(1, 2, 256, 0, false);
+        }
     } else {
         if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(2);
-        else if (v.gpb == 1) OVD_TSL(2, 1, 128, 0);
-        else OVD_TSL(2, 2, 256, 0);
+        else if (v.gpb == 1) OVD_TSL(2, 1, 128, 0, false);
+        else OVD_TSL(2, 2, 256, 0, false);
     }
 #undef OVD_TSL_PLANE
 #undef OVD_TSL

@@ -140,6 +140,7 @@ void launch_unpack_spinor(const Geom& g, int n, const cpx<T>* in, long long stri
 struct StencilVariant {
     int map = -1;
     int gpb = 0;
+    int seq = 0;   // 1: the two outputs of a pair one after the other (DIR 0/1, not the plane shape)
 };
 inline int default_map(int nrhs) { return (nrhs >= 16 && nrhs % 8 == 0) ? 0 : 1; }
 

@@ -49,7 +49,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("left_start", ctypes.c_int),
                 ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
                 ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int)]
+                ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int), ("shape_seq", ctypes.c_int)]
 
 
 class _EigStats(ctypes.Structure):
@@ -171,7 +171,8 @@ class Lattice:
         self._stream = stream
         opt = _Options(precision, left_start, breakdown_tol, quad_step, int(bool(step_timing)), int(bool(use_graph)),
                        int(bool(autotune)), -1 if shape is None else int(shape[0]),
-                       0 if shape is None else int(shape[1]))
+                       0 if shape is None else int(shape[1]),
+                       -1 if shape is None or len(shape) < 3 else int(shape[2]))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),

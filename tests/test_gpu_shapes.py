@@ -1,5 +1,6 @@
-"""Every launch shape of the stencils (XCD work order x site groups per block),
-forced through the options, against the oracle; and the autotuner's choice."""
+"""Every launch shape of the stencils (XCD work order x site groups per block x
+paired or sequential form), forced through the options, against the oracle;
+and the autotuner's choice."""
 import pytest
 
 import synth
@@ -9,7 +10,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (0, 4), (1, 4), (0, 8), (1, 8)])
+@pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (0, 4), (1, 4), (0, 8), (1, 8),
+                                   (0, 1, 1), (0, 2, 1), (1, 1, 1), (1, 2, 1), (0, 4, 1), (1, 4, 1), (1, 8, 1)])
 def test_forced_shapes_deriv_and_sign(shape):
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, host, ops, print_case, rel
@@ -49,3 +51,45 @@ def test_autotuner_records_a_shape():
     lat.apply_op(ovderiv.OP_H, 0.3, b)
     shapes = lat.tuned_shapes()
     assert "tsl:d:1:8=" in shapes and "op:d:0:8=" in shapes
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sequential_and_paired_forms_against_oracle(prec):
+    """Both forms of the stencil (paired and sequential) against the oracle on
+    a lattice whose volume is not a multiple of the 64-site group, with the
+    x-projection of the scalar mode: FP64 to 1e-10; mixed precision to the
+    bounds of the mixed-precision parity test (1e-4 sign, 1e-3 derivative).
+    The two forms round differently where the mu-derivative terms enter, so
+    they are compared with the oracle, not bit for bit with each other."""
+    import numpy as np
+
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k, nrhs, mu = (5, 3, 4, 3), 24, 3, 0.25
+    print_case(test="seq_and_paired", prec=prec, dims=dims, nrhs=nrhs)
+    p = ovderiv.FP64 if prec == "fp64" else ovderiv.MIXED
+    Uh = synth.make_links(dims, 0.5, 905)
+    bh = synth.make_sources(dims, nrhs, 906)
+    xh = synth.make_sources(dims, nrhs, 907)
+    h, hd, dh, dhd = ops(Uh, dims, mu)
+    refs = []
+    for r in range(nrhs):
+        dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, bh[r].ravel(), k)
+        sref, _ = tsl.krylov_sign(h, hd, bh[r].ravel(), bh[r].ravel(), k)
+        refs.append((yref, dref, np.vdot(xh[r].ravel(), dref), sref))
+    t_sign, t_der = (1e-10, 1e-10) if prec == "fp64" else (1e-4, 1e-3)
+    U, b, x = dev(Uh), dev(bh), dev(xh)
+    for seq in (0, 1):
+        lat = ovderiv.Lattice(dims, precision=p, shape=(1, 2, seq))
+        lat.set_links(U)
+        y, dy, s = lat.sign_apply_deriv(b, mu, k, x=x)
+        ys = host(lat.sign_apply(b, mu, k))
+        assert ("seq" in lat.tuned_shapes()) == bool(seq)
+        lat.close()
+        y, dy = host(y), host(dy)
+        for r in range(nrhs):
+            yref, dref, sref_x, sref = refs[r]
+            assert rel(y[r], yref) < t_sign
+            assert rel(ys[r], sref) < t_sign
+            assert rel(dy[r], dref) < t_der
+            assert abs(complex(s[r]) - sref_x) <= t_der * np.linalg.norm(xh[r]) * np.linalg.norm(dref)

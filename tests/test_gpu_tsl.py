@@ -201,8 +201,11 @@ def test_free_field_converges_at_headline_size():
 @pytest.mark.parametrize("nrhs", [5, 16])
 def test_batch_shapes_match_single_source(nrhs):
     """Ragged (5) and XCD-split (16, a multiple of 8 >= 16) batches of the
-    derivative: every source's <x|dy> equals its single-source value, and the
-    first and last agree with the oracle."""
+    derivative: every source's <x|dy> equals its single-source value to 1e-11,
+    and the first and last agree with the oracle.  The batch and the single
+    source may run different launch shapes (block partition of the step's
+    reductions; paired or sequential stencil, which contract the mu-derivative
+    terms differently), so the two differ by rounding amplified over k steps."""
     from gpu_helpers import dev, host, ops, print_case, rel
     dims, k, mu = (4, 4, 4, 6), 40, 0.3
     print_case(test="batch_shapes", dims=dims, k=k, nrhs=nrhs)
@@ -213,7 +216,7 @@ def test_batch_shapes_match_single_source(nrhs):
     y, dy, s = lat.sign_apply_deriv(dev(b), mus, k, x=dev(x))
     for r in range(nrhs):
         _, _, s1 = lat.sign_apply_deriv(dev(b[r:r + 1]), [mus[r]], k, x=dev(x[r:r + 1]), want_vectors=False)
-        assert abs(s[r] - s1[0]) < 1e-12 * abs(s1[0]), r
+        assert abs(s[r] - s1[0]) < 1e-11 * abs(s1[0]), r
     for r in (0, nrhs - 1):
         h, hd, dh, dhd = ops(U, dims, mus[r])
         dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[r].ravel(), k)
