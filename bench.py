@@ -47,8 +47,8 @@ def update_bytes_per_site(prec_bytes: int) -> float:
 def measured_traffic(pb: int, nrhs: int, shapes: str = ""):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
     summary, if it was taken on the current stencil source, this workload and
-    the launch shape (groups per block) the autotuner kept in this run; else
-    None."""
+    the launch shape (groups per block, paired or sequential form) that the
+    autotuner kept in this run; else None."""
     import hashlib
     import re
     src = os.path.join(ROOT, "paper_1611_00195_amd", "csrc", "kernels_stencil.hip")
@@ -65,9 +65,13 @@ def measured_traffic(pb: int, nrhs: int, shapes: str = ""):
     if kv.get("kernels_stencil_sha256_16") != digest or key not in kv:
         return None
     tag = "fp64" if pb == 8 else "fp32"
-    prof_gpb = re.search(r",\s*(\d+)>", kv.get(f"kernel_{tag}_nrhs{nrhs}", ""))
-    run_gpb = re.search(r"gpb(\d+)", shapes)
-    if prof_gpb and run_gpb and prof_gpb.group(1) != run_gpb.group(1):
+    # kernel name "tsl_stencil_kernel<double, 1, G, false|true>" against the
+    # tuned entry "tsl:d:1:<nrhs>=map<m>,gpb<G>[,seq];" of this run
+    prof = re.search(r"<\w+, \d+, (\d+), (true|false)>", kv.get(f"kernel_{tag}_nrhs{nrhs}", ""))
+    run = re.search(rf"tsl:{'d' if pb == 8 else 'f'}:1:{nrhs}=map\d+,gpb(\d+)(,seq)?;", shapes)
+    if prof is None or (shapes and run is None):
+        return None
+    if run is not None and (prof.group(1) != run.group(1) or (prof.group(2) == "true") != bool(run.group(2))):
         return None
     return float(kv[key])
 
