@@ -193,6 +193,13 @@ def run_gpu(args):
             "force": float(_t.linalg.vector_norm(F32 - F64) / _t.linalg.vector_norm(F64)),
         }
         out["vjp_mixed"] = vm
+        vr = time_vjp(args, U, V, recompute=True)
+        Fr = vr.pop("F")
+        vr["max_rel_dev_from_stored"] = {
+            "s": abs(complex(*vr["s"]) - complex(*out["vjp"]["s"])) / abs(complex(*out["vjp"]["s"])),
+            "force": float(_t.linalg.vector_norm(Fr - F64) / _t.linalg.vector_norm(F64)),
+        }
+        out["vjp_recompute"] = vr
         out["uneven"] = time_uneven(args)
     # Dw.v bandwidth: nrhs fields per launch so that the traffic exceeds the 256 MB MALL
     nd = args.dwv_nrhs
@@ -216,9 +223,10 @@ def run_gpu(args):
     return out
 
 
-def time_vjp(args, U, V, prec=0):
-    """The gradient of s = <x|sgn(H)|b> w.r.t. mu and all 4 V links (FP64, one
-    source pair, both Krylov bases stored): calls per second and the MFMA rate
+def time_vjp(args, U, V, prec=0, recompute=False):
+    """The gradient of s = <x|sgn(H)|b> w.r.t. mu and all 4 V links (one source
+    pair; both Krylov bases stored, or with recompute the right basis
+    regenerated by a second Lanczos run): calls per second and the MFMA work
     of the Z = W M'^dag product (8 N k^2 flops)."""
     import torch
 
@@ -226,11 +234,12 @@ def time_vjp(args, U, V, prec=0):
     from paper_1611_00195_amd import ovderiv
 
     dims = tuple(args.dims)
-    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, vjp_recompute=recompute)
     lat.set_links(U)
     b = torch.from_numpy(synth.make_sources(dims, 1, 4000)).cuda()
     x = torch.from_numpy(synth.make_sources(dims, 1, 5000)).cuda()
     lat.sign_apply_vjp(x, b, args.mu, args.k, force=True, wirtinger=True)
+    assert lat.last_stats.vjp_recomputed == int(recompute)
     torch.cuda.synchronize()
     reps = 2
     t0 = time.perf_counter()
@@ -241,7 +250,7 @@ def time_vjp(args, U, V, prec=0):
     lat.close()
     return {"calls_per_s": round(1.0 / dt, 3), "ms_per_call": round(1e3 * dt, 2), "s": [s.real, s.imag],
             "ds_dmu": [dsdmu.real, dsdmu.imag], "precision": "fp64" if prec == 0 else "mixed", "k": args.k,
-            "zgemm_flops": 8.0 * 12 * V * args.k ** 2, "F": F}
+            "basis": "recomputed" if recompute else "stored", "zgemm_flops": 8.0 * 12 * V * args.k ** 2, "F": F}
 
 
 def time_uneven(args):
@@ -422,6 +431,7 @@ def main():
             "dw_v": g["dw_v"],
             "vjp": g.get("vjp"),
             "vjp_mixed": g.get("vjp_mixed"),
+            "vjp_recompute": g.get("vjp_recompute"),
             "uneven_batch": g.get("uneven"),
             "min_margin": g["min_margin"],
             "sign_check": g["sign_check"],

@@ -91,6 +91,12 @@ typedef struct {
                                live accumulators, twice the waves per SIMD in FP64), 0 the
                                paired form (both outputs at once, every link loaded once);
                                -1 (default): tuned, else paired */
+    int vjp_recompute;      /* ovd_sign_apply_vjp: 0 keeps both Krylov bases and Z (3 k FP64
+                               fields); 1 keeps only the left basis, turned into Z in place,
+                               and regenerates the right basis with a second, identical
+                               Lanczos run, C = min(k, 32) vectors at a time (k + 2C fields,
+                               twice the Lanczos time); -1 (default): recompute only when the
+                               stored form does not fit in the free device memory */
 } ovd_options;
 
 typedef struct {
@@ -110,6 +116,7 @@ typedef struct {
     double ms_total;        /* device time of the whole call */
     double ms_stencil;      /* summed device time of the k stencil launches (HIP events) */
     double ms_update;       /* summed device time of the k - 1 three-term update launches */
+    int vjp_recomputed;     /* ovd_sign_apply_vjp: 1 if the right basis was regenerated */
 } ovd_stats;
 
 /* Create a handle for one lattice.  Sec. 4 lattices are Lt x Ls^3 (e.g. 14 x 14^3).

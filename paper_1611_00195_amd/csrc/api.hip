@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <type_traits>
 #include <string>
@@ -264,7 +265,8 @@ ovd_status check_handle(ovd_h h) {
 template <typename T>
 ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cpx<T>* src_v,
                    const cpx<T>* src_w, const cpx<T>* xproj, cpx<T>* basis, c64* c_out, ovd_stats* stats,
-                   cpx<T>* basis_w = nullptr) {
+                   cpx<T>* basis_w = nullptr, int basis_ring = 0,
+                   const std::function<void(int, hipStream_t)>* after_step = nullptr) {
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const int halves = dir == 0 ? 1 : 2;
@@ -293,11 +295,16 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
 
     // rotating buffers: V-hat x3, U-hat x2, W-hat x3, Z-hat x2
     auto slot = [&](int base, int i) { return ring + (size_t)(base + i) * nrhs * fsz; };
-    auto Vs = [&](int i) -> cpx<T>* { return basis ? basis + (size_t)(i - 1) * fsz : slot(0, i % 3); };
+    // basis: all k right vectors, or with basis_ring > 0 a ring of that many
+    // (vector i in slot (i - 1) % basis_ring)
+    auto Vs = [&](int i) -> cpx<T>* {
+        if (!basis) return slot(0, i % 3);
+        return basis + (size_t)(basis_ring > 0 ? (i - 1) % basis_ring : i - 1) * fsz;
+    };
     auto Us = [&](int i) -> cpx<T>* { return slot(3, i % 2); };
     auto Ws = [&](int i) -> cpx<T>* { return basis_w ? basis_w + (size_t)(i - 1) * fsz : slot(5, i % 3); };
     auto Zs = [&](int i) -> cpx<T>* { return slot(8, i % 2); };
-    const long long sV = basis ? (long long)k * fsz : fsz;
+    const long long sV = basis ? (long long)(basis_ring > 0 ? basis_ring : k) * fsz : fsz;
     const long long sW = basis_w ? (long long)k * fsz : fsz;
 
     Timer tl, ts;
@@ -389,11 +396,12 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             launch_tsl_stencil<T>(g, dir, nrhs, p, U, dU, md, st, co, partials, counters, j,
                                   h->opt.breakdown_tol, stream, var);
             if (timing) (void)hipEventRecord(h->ev[4 * j + 3], stream);
+            if (after_step) (*after_step)(j, stream);   // right vectors 1 .. j + 1 are final
         }
         return hipGetLastError();
     };
     bool launched = false;
-    if (h->opt.use_graph && !timing) {   // per-kernel events are not recorded into graphs
+    if (h->opt.use_graph && !timing && !after_step) {   // events and per-call hooks stay out of graphs
         double tau = h->opt.breakdown_tol;
         uint64_t tb, mb;
         std::memcpy(&tb, &tau, 8);
@@ -727,6 +735,7 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.shape_map = -1;
     h->opt.shape_gpb = 0;
     h->opt.shape_seq = -1;
+    h->opt.vjp_recompute = -1;
     if (opt) {
         h->opt = *opt;
         if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
@@ -1185,31 +1194,64 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const long long fsz = (long long)12 * g.Vp;
-    // bilinear two-sided Lanczos: right start b, left start x, both bases kept
-    // (FP64, or FP32 vectors for OVD_MIXED, widened to FP64 for the gradient)
-    WS(bv, c64, "vjp_basis_v", (size_t)k * fsz);
+    const bool mixed = h->opt.precision == OVD_MIXED;
+    const bool grad = ds_dmu || F || dsdU || dsdUc;
+    // stored form: both bases and Z (3 k FP64 fields, plus the two FP32 bases
+    // in mixed precision); recompute form: the left basis only (turned into Z
+    // in place), the right basis regenerated by a second, identical run
+    bool recompute = grad && h->opt.vjp_recompute > 0;
+    if (grad && h->opt.vjp_recompute < 0) {
+        const size_t f64 = sizeof(c64) * fsz, f32 = sizeof(c32) * fsz;
+        const size_t need = (size_t)3 * k * f64 + (mixed ? (size_t)2 * k * f32 : 0);
+        size_t held = 0;
+        for (const char* n : {"vjp_basis_v", "vjp_basis_w", "vjp_Z", "vjp_basis_v32", "vjp_basis_w32"}) {
+            auto it = h->ws.find(n);
+            if (it != h->ws.end()) held += it->second.second;
+        }
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        recompute = need > held + fr / 10 * 9;
+    }
+    if (st) st->vjp_recomputed = recompute ? 1 : 0;
+    // bilinear two-sided Lanczos: right start b, left start x (FP64, or FP32
+    // vectors for OVD_MIXED, widened to FP64 for the gradient)
     WS(bw, c64, "vjp_basis_w", (size_t)k * fsz);
+    c64* bv = nullptr;
+    if (!recompute) {
+        WS(bv_, c64, "vjp_basis_v", (size_t)k * fsz);
+        bv = bv_;
+    }
     WS(c, c64, "ritz_c", k);
     Timer tt;
     tt.start(h->stream);
     const double mus[1] = {mu};
-    if (h->opt.precision == OVD_MIXED) {
+    c32 *srcv32 = nullptr, *srcw32 = nullptr;
+    c64 *srcv64 = nullptr, *srcw64 = nullptr;
+    if (mixed) {
         WS(srcv, c32, "vjp_src_v32", fsz);
         WS(srcw, c32, "vjp_src_w32", fsz);
-        WS(bv32, c32, "vjp_basis_v32", (size_t)k * fsz);
         WS(bw32, c32, "vjp_basis_w32", (size_t)k * fsz);
+        c32* bv32 = nullptr;
+        if (!recompute) {
+            WS(bv32_, c32, "vjp_basis_v32", (size_t)k * fsz);
+            bv32 = bv32_;
+        }
+        srcv32 = srcv;
+        srcw32 = srcw;
         HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c32) * fsz, h->stream));
         HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c32) * fsz, h->stream));
         launch_pack_spinor<float>(g, 1, b, srcv, fsz, h->stream);
         launch_pack_spinor<float>(g, 1, x, srcw, fsz, h->stream);
         s = run_tsl<float>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv32, c, st, bw32);
         if (s != OVD_OK) return s;
-        launch_widen_field(g, k, bv32, fsz, bv, fsz, h->stream);
+        if (bv32) launch_widen_field(g, k, bv32, fsz, bv, fsz, h->stream);
         launch_widen_field(g, k, bw32, fsz, bw, fsz, h->stream);
         HIPCHK(hipGetLastError());
     } else {
         WS(srcv, c64, "vjp_src_v", fsz);
         WS(srcw, c64, "vjp_src_w", fsz);
+        srcv64 = srcv;
+        srcw64 = srcw;
         HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c64) * fsz, h->stream));
         HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c64) * fsz, h->stream));
         launch_pack_spinor<double>(g, 1, b, srcv, fsz, h->stream);
@@ -1230,20 +1272,69 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         s_out[0] = sv.re;
         s_out[1] = sv.im;
     }
-    if (ds_dmu || F || dsdU || dsdUc) {
+    if (grad) {
         // M = L_sgn(T_k, e_1 e_1^T), M' = (x^dag b) M / (delta_p beta_q), Z = W-hat M'^dag
         WS(scr, c64, "frechet_scr", small_frechet_scratch_elems(k));
         WS(M, c64, "vjp_M", (size_t)k * k);
         WS(Mp, c64, "vjp_Mp", (size_t)k * k);
-        WS(Z, c64, "vjp_Z", (size_t)k * fsz);
         WS(trF, c64, "vjp_trF", g.V);
         WS(dsum, c64, "vjp_dsum", 1);
         double chk = 0.0;
         launch_small_frechet(k, co, h->opt.quad_step, scr, M, &chk, h->stream);
         launch_vjp_scale_m(k, co, M, Mp, h->stream);
-        launch_zgemm_wmh(bw, fsz, k, Mp, Z, fsz, fsz, h->stream);
-        launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
-                         h->stream);
+        if (!recompute) {
+            WS(Z, c64, "vjp_Z", (size_t)k * fsz);
+            launch_zgemm_wmh(bw, fsz, k, Mp, Z, fsz, fsz, h->stream);
+            launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
+                             h->stream);
+        } else {
+            // Z over W in place, a slab of field elements at a time through a
+            // k x E copy
+            const long long E = ((fsz + 15) / 16 + 15) / 16 * 16;
+            WS(slab, c64, "vjp_zslab", (size_t)k * E);
+            for (long long e0 = 0; e0 < fsz; e0 += E) {
+                const long long ne = std::min(E, fsz - e0);
+                HIPCHK(hipMemcpy2DAsync(slab, sizeof(c64) * E, bw + e0, sizeof(c64) * fsz, sizeof(c64) * ne, k,
+                                        hipMemcpyDeviceToDevice, h->stream));
+                launch_zgemm_wmh(slab, E, k, Mp, bw + e0, fsz, ne, h->stream);
+            }
+            // the Lanczos run again: same kernels, launch shape and inputs, so
+            // the same right vectors, now in a ring of 2C; after every C steps
+            // the C finished vectors enter the force sum (Kf, Kb carried in Kacc)
+            const int C = std::min(k, 32);
+            WS(Kacc, c64, "vjp_kacc", (size_t)18 * 4 * g.V);
+            c32* ring32 = nullptr;
+            c64* ring64 = nullptr;
+            c64* chunk64 = nullptr;
+            if (mixed) {
+                WS(r32, c32, "vjp_vring32", (size_t)2 * C * fsz);
+                WS(ch, c64, "vjp_vchunk", (size_t)C * fsz);
+                ring32 = r32;
+                chunk64 = ch;
+            } else {
+                WS(r64, c64, "vjp_vring", (size_t)2 * C * fsz);
+                ring64 = r64;
+            }
+            int done = 0;   // right vectors already in the force sum
+            const double emu = std::exp(mu);
+            const std::function<void(int, hipStream_t)> hook = [&](int j, hipStream_t stream) {
+                const int avail = j + 1;   // right vectors 1 .. j + 1 are final
+                if (avail - done < C && avail < k) return;
+                const int n = avail - done;
+                const size_t slot0 = (size_t)(done % (2 * C));   // done is a multiple of C: no wrap
+                const c64* vch = ring64 ? ring64 + slot0 * fsz : chunk64;
+                if (ring32) launch_widen_field(g, n, ring32 + slot0 * fsz, fsz, chunk64, fsz, stream);
+                launch_vjp_force(g, n, vch, fsz, bw + (size_t)done * fsz, fsz, h->U64, emu, (c64*)F, (c64*)dsdU,
+                                 (c64*)dsdUc, trF, stream, Kacc, done == 0, avail == k);
+                done = avail;
+            };
+            ovd_stats st2{};
+            if (mixed) s = run_tsl<float>(h, 1, k, 0, mus, srcv32, srcw32, nullptr, ring32, c, &st2, nullptr, 2 * C, &hook);
+            else s = run_tsl<double>(h, 1, k, 0, mus, srcv64, srcw64, nullptr, ring64, c, &st2, nullptr, 2 * C, &hook);
+            if (s != OVD_OK) return s;
+            if (done != k) return fail(h, OVD_EHIP, "gradient: the regenerated basis did not reach step k");
+            if (st) st->ms_lanczos += st2.ms_lanczos;
+        }
         launch_sum_c64(g.V, trF, dsum, h->stream);
         c64 dm;
         HIPCHK(hipMemcpyAsync(&dm, dsum, sizeof(c64), hipMemcpyDeviceToHost, h->stream));

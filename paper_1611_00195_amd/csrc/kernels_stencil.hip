@@ -1199,14 +1199,20 @@ OVD_INST(float)
 // cf = e^{mu}, cb = e^{-mu} on time links (1 in space), sgn the boundary
 // factor of the hop.  One thread per (site, direction), direction fastest.
 // trF[y] = tr F_t(y), summed later into ds/dmu.
+// The sum over p may be split into chunks (the basis regenerated a chunk at a
+// time): Kacc [18][4V] carries Kf, Kb between the launches of one gradient;
+// `first` starts from zero instead of Kacc, `last` turns K into the outputs
+// (else K is stored to Kacc).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64* __restrict__ Vb, long long sV,
                                                         const c64* __restrict__ Zb, long long sZ,
                                                         const c64* __restrict__ U, double emu,
                                                         c64* __restrict__ F, c64* __restrict__ dU,
-                                                        c64* __restrict__ dUc, c64* __restrict__ trF) {
+                                                        c64* __restrict__ dUc, c64* __restrict__ trF,
+                                                        c64* __restrict__ Kacc, int first, int last) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 4 * g.V) return;
+    const size_t n4 = (size_t)4 * g.V;
     const int y = t >> 2, nu = t & 3;
     const int Vp = g.Vp;
     const Nbr N = neighbours(g, y);
@@ -1215,7 +1221,10 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
     const double cf = nu == 3 ? emu : 1.0, cb = nu == 3 ? 1.0 / emu : 1.0;
     c64 Kf[9], Kb[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Kf[i] = Kb[i] = c64{0.0, 0.0};
+    for (int i = 0; i < 9; ++i) {
+        Kf[i] = first ? c64{0.0, 0.0} : Kacc[(size_t)i * n4 + t];
+        Kb[i] = first ? c64{0.0, 0.0} : Kacc[(size_t)(9 + i) * n4 + t];
+    }
     const int cfw = kHop[2 * nu], cbw = kHop[2 * nu + 1];
     for (int p = 0; p < k; ++p) {
         const c64* Vp_ = Vb + (size_t)p * sV;
@@ -1244,6 +1253,14 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
             }
         }
     }
+    if (!last) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            Kacc[(size_t)i * n4 + t] = Kf[i];
+            Kacc[(size_t)(9 + i) * n4 + t] = Kb[i];
+        }
+        return;
+    }
     // link U_nu(y) from the FP64 internal link field
     c64 u[9];
     load_link(U, nu, y, Vp, u);
@@ -1269,8 +1286,10 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
 }
 
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
-                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s) {
-    vjp_force_kernel<<<(4 * g.V + 255) / 256, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF);
+                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s, c64* Kacc, bool first,
+                      bool last) {
+    vjp_force_kernel<<<(4 * g.V + 255) / 256, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF, Kacc,
+                                                           first ? 1 : 0, last ? 1 : 0);
 }
 
 // out = sum_y trF[y] (one block, fixed order)

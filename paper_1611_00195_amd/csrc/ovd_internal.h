@@ -215,8 +215,12 @@ void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64*
 void launch_zgemm_wmh(const c64* W, long long sW, int k, const c64* Mp, c64* Z, long long sZ, long long nf,
                       hipStream_t s);
 void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t s);
+// force of the gradient from the basis pairs p < k; the sum over p may be
+// split over launches that carry Kf, Kb in Kacc ([18][4V], needed unless
+// first && last): first starts from zero, last writes F, dU, dUc, trF
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
-                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s);
+                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s, c64* Kacc = nullptr,
+                      bool first = true, bool last = true);
 void launch_sum_c64(int n, const c64* v, c64* out, hipStream_t s);
 
 // eigenpairs of smallest |lambda| and eigenvector derivatives for deflation (eigs.hip)

@@ -168,3 +168,50 @@ def test_vjp_mixed_precision_bounds():
     e_f = rel(host(out[1][2]), host(out[0][2]))
     print(f"mixed gradient deviations: s {e_s:.1e}, ds/dmu {e_d:.1e}, force {e_f:.1e}")
     assert e_s < 1e-5 and e_d < 1e-4 and e_f < 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [20, 70])
+def test_vjp_recomputed_basis_matches_stored(prec, k):
+    """The recompute form (left basis only, turned into Z in place; the right
+    basis regenerated by a second run and folded into the force 32 vectors at
+    a time, here one partial chunk at k = 20 and chunks 32 + 32 + 6 at k = 70)
+    against the stored form on a lattice whose volume is not a multiple of 64:
+    the regenerated vectors are the same, so s, ds/dmu, the force and the
+    Wirtinger derivatives agree to 1e-13; in FP64 the stored form also matches
+    the oracle's Krylov gradient to 1e-10."""
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, print_case, rel
+    dims = (5, 3, 4, 3)
+    print_case(test="vjp_recompute", dims=dims, k=k, prec=prec)
+    U = synth.make_links(dims, 0.5, 541)
+    x = synth.make_source(dims, 542)
+    b = synth.make_source(dims, 543)
+    out = {}
+    for rc in (0, 1):
+        lat = ovderiv.Lattice(dims, precision=prec, vjp_recompute=bool(rc))
+        lat.set_links(dev(U))
+        out[rc] = lat.sign_apply_vjp(dev(x[None]), dev(b[None]), MU, k, force=True, wirtinger=True)
+        assert lat.last_stats.vjp_recomputed == rc
+        lat.close()
+    (s0, d0, F0, U0, C0), (s1, d1, F1, U1, C1) = out[0], out[1]
+    assert abs(s1 - s0) <= 1e-13 * abs(s0)
+    assert abs(d1 - d0) <= 1e-13 * abs(d0)
+    for a, c in ((F1, F0), (U1, U0), (C1, C0)):
+        assert rel(host(a), host(c)) < 1e-13
+    if prec == 0:
+        s_r, dm_r, F_r, _ = vjp.krylov_vjp(U, dims, MU, x, b, k)
+        assert abs(s0 - s_r) < 1e-10 * abs(s_r) and abs(d0 - dm_r) < 1e-10 * abs(dm_r)
+        assert rel(host(F0), F_r) < 1e-10
+
+
+def test_vjp_auto_mode_stores_when_memory_allows():
+    """Default (auto) mode: a small lattice's gradient fits, so the bases are stored."""
+    from gpu_helpers import dev, print_case
+    dims = (4, 4, 4, 4)
+    print_case(test="vjp_auto", dims=dims)
+    U = synth.make_links(dims, 0.5, 551)
+    lat = _lat(dims, U)
+    x = synth.make_source(dims, 552)
+    lat.sign_apply_vjp(dev(x[None]), dev(x[None]), MU, 16)
+    assert lat.last_stats.vjp_recomputed == 0
