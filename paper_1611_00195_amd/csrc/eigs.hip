@@ -306,9 +306,9 @@ bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, i
     c64* B1 = c.fields(p);
     c64* B2 = c.fields(p);
     c64* T = c.fields(p);
-    c64* Qm = c.fields(m);
-    c64* Wm = c.fields(m);
-    c64* Zm = c.fields(m);
+    c64* Qm = c.fields(p);
+    c64* Wm = c.fields(p);
+    c64* Zm = c.fields(p);
     if (!X || !B0 || !B1 || !B2 || !T || !Qm || !Wm || !Zm) return false;
     {
         const long long ne = (long long)p * c.nf;
@@ -341,26 +341,47 @@ bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, i
         // next start: all p Ritz vectors of H^2
         if (!c.ok(hipMemsetAsync(X, 0, sizeof(c64) * (size_t)p * c.nf, c.s), "memset")) return false;
         if (!c.comb(Q, p, S2, p, X)) return false;
-        // the m best: orthonormalise, project H, residuals |H r - lambda r|
-        if (!c.copy(Qm, X, m)) return false;
-        if (!orthonormalise(c, Qm, Zm, m)) return false;
-        if (!c.apply(0, mu, Qm, Wm, m)) return false;
+        // H is projected on the first mq >= m Ritz vectors of H^2, mq at the
+        // largest relative gap of |theta^2| in [m, p - 4].  A weak gauge field
+        // leaves the spectrum of H close to symmetric (lambda next to some
+        // -lambda'), H^2 cannot tell such a pair apart and its Ritz vectors mix
+        // the two; H separates them only when the whole cluster is in the space.
+        int mq = m;
+        {
+            double gbest = -1.0;
+            const int jmax = std::min(p - 1, std::max(m, p - 4));
+            for (int j = m; j <= jmax; ++j) {
+                const double gap = (std::abs(w2[j]) - std::abs(w2[j - 1])) / std::max(std::abs(w2[j - 1]), 1e-300);
+                if (gap > gbest) {
+                    gbest = gap;
+                    mq = j;
+                }
+            }
+        }
+        // orthonormalise, project H, keep the m smallest |lambda|, residuals |H r - lambda r|
+        if (!c.copy(Qm, X, mq)) return false;
+        if (!orthonormalise(c, Qm, Zm, mq)) return false;
+        if (!c.apply(0, mu, Qm, Wm, mq)) return false;
         std::vector<cd> G, w, S;
-        if (!c.proj(Qm, m, Wm, m, G)) return false;
-        if (!dense::eig_general(m, G, w, S)) {
+        if (!c.proj(Qm, mq, Wm, mq, G)) return false;
+        if (!dense::eig_general(mq, G, w, S)) {
             c.err = "QR iteration of the projected problem did not converge";
             return false;
         }
-        sort_by_modulus(m, w, S);
+        sort_by_modulus(mq, w, S);
         std::vector<double> res;
-        if (!ritz_residuals(c, Qm, Wm, Zm, m, G, S, m, res)) return false;
+        if (!ritz_residuals(c, Qm, Wm, Zm, mq, G, S, m, res)) return false;
         const double rmax = *std::max_element(res.begin(), res.end());
-        sr.theta = w;
+        sr.theta.assign(w.begin(), w.begin() + m);
         sr.outer = it;
         sr.max_res = rmax;
         if (verbose()) {
-            std::fprintf(stderr, "eigs mu=%+.3f outer %d: max residual %.3e, |lambda_m| %.6f, a %.4f\n", mu, it, rmax,
-                         std::abs(w[m - 1]), a);
+            int nconv = 0;
+            while (nconv < m && res[nconv] <= tol) ++nconv;
+            std::fprintf(stderr,
+                         "eigs mu=%+.3f outer %d: max residual %.3e, first %d converged, res_1 %.1e, |lambda_m| %.6f, "
+                         "a %.4f, H on %d of %d\n",
+                         mu, it, rmax, nconv, res[0], std::abs(w[m - 1]), a, mq, p);
             std::fflush(stderr);
         }
         // stagnation: no halving of the best residual in 20 outer iterations
@@ -370,9 +391,12 @@ bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, i
         }
         const bool stalled = it - best_it >= 20;
         if (rmax <= tol || it == max_outer || stalled) {
-            // eigenvectors r = Qm s (unit norm)
+            // eigenvectors r = Qm s (unit norm), the first m columns of S
+            std::vector<cd> Sm((size_t)mq * m);
+            for (int i = 0; i < mq; ++i)
+                for (int j = 0; j < m; ++j) Sm[(size_t)i * m + j] = S[(size_t)i * mq + j];
             if (!c.ok(hipMemsetAsync(Out, 0, sizeof(c64) * (size_t)m * c.nf, c.s), "memset")) return false;
-            if (!c.comb(Qm, m, S, m, Out)) return false;
+            if (!c.comb(Qm, mq, Sm, m, Out)) return false;
             break;
         }
         // damp everything above the largest Ritz value of H^2 in the subspace
@@ -496,6 +520,7 @@ int eigs_compute(const EigParams& P, EigResult& out) {
     c.nf = (long long)12 * P.g.Vp;
     const int m = P.m, l = P.l;
     const int p = P.p > m ? P.p : m + std::max(16, m / 2);
+    const int degree = P.degree;
     out = EigResult{};
     auto fail = [&](int code) {
         out.err = c.err.empty() ? "eigensolver failed" : c.err;
@@ -505,8 +530,8 @@ int eigs_compute(const EigParams& P, EigResult& out) {
     c64* Lraw = c.fields(m);
     if (!Rv || !Lraw) return fail(-2);
     SideResult right, left;
-    if (!subspace_side(c, P.mu, m, p, P.tol, P.max_outer, P.degree, P.seed, Rv, right)) return fail(-3);
-    if (!subspace_side(c, -P.mu, m, p, P.tol, P.max_outer, P.degree, P.seed + 1, Lraw, left)) return fail(-3);
+    if (!subspace_side(c, P.mu, m, p, P.tol, P.max_outer, degree, P.seed, Rv, right)) return fail(-3);
+    if (!subspace_side(c, -P.mu, m, p, P.tol, P.max_outer, degree, P.seed + 1, Lraw, left)) return fail(-3);
     out.outer_right = right.outer;
     out.outer_left = left.outer;
     out.res_right = right.max_res;
