@@ -164,7 +164,7 @@ ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam,
                              const void* dR, const void* dL, const ovd_dir* dir);
 /* Statistics of ovd_compute_deflation. */
 typedef struct {
-    int outer_right, outer_left;      /* filtered subspace iterations on H(mu) and H(-mu) = H(mu)^dag */
+    int outer_right, outer_left;      /* Arnoldi restart cycles on H(mu)^-1 and H(-mu)^-1 = (H(mu)^dag)^-1 */
     double max_res_right, max_res_left; /* max |H r - lambda r| (|r| = 1) of the m pairs, both sides */
     double max_biorth;                /* max |L^dag R - 1| */
     int gmres_iters;                  /* total GMRES iterations of the 2 l derivative solves */
@@ -181,8 +181,10 @@ typedef struct {
  *   dR_j = sum_{i != j} R_i (L_i^dag dH R_j)/(lambda_j - lambda_i) + (lambda_j - H)^{-1} (1 - P) dH R_j
  *   dL_j = sum_{i != j} L_i conj((L_j^dag dH R_i)/(lambda_j - lambda_i)) + (conj(lambda_j) - H^dag)^{-1} (1 - P)^dag dH^dag L_j
  * with P = sum_{i<m} R_i L_i^dag and the resolvents taken on the range of 1 - P.
- * Method: Chebyshev-filtered subspace iteration on H^2 (and H^dag^2) with
- * Rayleigh-Ritz on H, FP64; restarted GMRES for the shifted solves.
+ * Method: thick-restart Arnoldi on H^-1 (and H^dag^-1), whose eigenvalues of
+ * largest modulus are 1/lambda for the wanted lambda, every application a
+ * conjugate-gradient solve of the normal equations, FP64; restarted GMRES for
+ * the shifted solves of the derivatives.
  *   tol   residual bound |H r - lambda r| for |r| = 1 (<= 0: 1e-10)
  *   lam   host double[2 m] (re, im), increasing |lambda|, or NULL
  * The set replaces any set of the same mu, exactly as ovd_set_deflation.

@@ -4,16 +4,17 @@
 // link direction (Sec. 3, eq. 10-11 with the eigenvector derivative of the
 // perturbation expansion).
 //
-// Eigenpairs: Chebyshev-filtered subspace iteration on H^2.  The wanted
-// eigenvalues are the smallest |lambda|, interior for H but at the lower end
-// of the spectrum of H^2 (lambda^2, close to the positive real axis), so a
-// Chebyshev polynomial of H^2 that is bounded on [a, b] (b an upper bound of
-// |lambda|^2, a the largest Ritz value of the current subspace) amplifies
-// them.  Each outer iteration: filter the p = m + extra vectors, orthonormalise
-// (Cholesky QR, twice), Rayleigh-Ritz with H itself (projected p x p problem
-// solved on the host by the QR algorithm), residual norms from the Gram matrix
-// of H Q - Q G.  The same run on H^dag = H(-mu) gives the left subspace; the
-// left vectors are then the dual basis of the right ones in it (L^dag R = 1).
+// Eigenpairs: thick-restart Arnoldi on B = H^{-1}.  The wanted eigenvalues
+// (smallest |lambda|) are interior for H, but 1/lambda are the eigenvalues of
+// largest modulus of B, outside the disk that holds the rest of its spectrum,
+// where a Krylov space converges to them whatever their phase.  Every
+// application of B is a conjugate-gradient solve of the normal equations
+// H^dag H z = H^dag v (H^dag = H(-mu)); the basis is orthogonalised by
+// classical Gram-Schmidt twice (MFMA projections), the projected problem is
+// solved on the host by the QR algorithm, and each restart keeps the Ritz
+// vectors of largest |theta| (a Krylov decomposition with a full leading
+// block).  The same run on H^dag gives the left subspace; the left vectors are
+// then the dual basis of the right ones in it (L^dag R = 1).
 //
 // Derivatives (gauge L_j^dag dR_j = 0, dL_j^dag R_j = 0), with P = sum_{i<m} R_i L_i^dag:
 //   dR_j = sum_{i != j} R_i (L_i^dag dA R_j) / (lambda_j - lambda_i)
@@ -112,6 +113,15 @@ struct Ctx {
         if (e != hipSuccess && err.empty()) err = std::string(what) + ": " + hipGetErrorString(e);
         return e == hipSuccess;
     }
+    // one block of n fields kept for repeated solves (grown on demand)
+    c64* reuse_buf = nullptr;
+    int reuse_n = 0;
+    c64* reuse(int n) {
+        if (n <= reuse_n) return reuse_buf;
+        reuse_buf = fields(n);
+        reuse_n = reuse_buf ? n : 0;
+        return reuse_buf;
+    }
     c64* fields(int n) {
         void* p = nullptr;
         const size_t bytes = sizeof(c64) * (size_t)(n > 0 ? n : 1) * nf;
@@ -200,67 +210,18 @@ struct Ctx {
     }
 };
 
-// Q = Y R^{-1} with Y^dag Y = R^dag R, twice (Cholesky QR 2); Y is overwritten by Q
-bool orthonormalise(Ctx& c, c64* Y, c64* T, int p) {
-    for (int pass = 0; pass < 2; ++pass) {
-        std::vector<cd> G, R;
-        if (!c.proj(Y, p, Y, p, G)) return false;
-        // symmetrise and lift the diagonal slightly for a safe factorisation
-        for (int i = 0; i < p; ++i)
-            for (int j = i + 1; j < p; ++j) {
-                const cd a = 0.5 * (G[(size_t)i * p + j] + std::conj(G[(size_t)j * p + i]));
-                G[(size_t)i * p + j] = a;
-                G[(size_t)j * p + i] = std::conj(a);
-            }
-        double dmax = 0.0;
-        for (int i = 0; i < p; ++i) dmax = std::max(dmax, G[(size_t)i * p + i].real());
-        for (int i = 0; i < p; ++i) G[(size_t)i * p + i] += 1e-15 * dmax;
-        if (!dense::cholesky_upper(p, G, R)) {
-            c.err = "Cholesky QR failed: the filtered vectors lost rank";
-            return false;
-        }
-        const std::vector<cd> Ri = dense::inv_upper(p, R);
-        if (!c.ok(hipMemsetAsync(T, 0, sizeof(c64) * (size_t)p * c.nf, c.s), "memset")) return false;
-        if (!c.comb(Y, p, Ri, p, T)) return false;
-        if (!c.copy(Y, T, p)) return false;
-    }
-    return true;
-}
-
-// Chebyshev filter of degree d in H(mu)^2 on [a, b]: out = T_d(((H^2) - c)/e) X
-// (three buffers rotate; the result ends up in *res)
-bool cheb_filter(Ctx& c, double mu, const c64* X, c64* B0, c64* B1, c64* B2, c64* T, int p, int d, double a,
-                 double b, c64** res) {
-    const long long ne = (long long)p * c.nf;
-    const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
-    // B1 = (H^2 X - cc X) / e
-    if (!c.apply(0, mu, X, T, p) || !c.apply(0, mu, T, B1, p)) return false;
-    if (!c.lincomb(ne, 1.0 / e, B1, -cc / e, X, 0.0, nullptr, B1)) return false;
-    if (!c.copy(B0, X, p)) return false;
-    c64 *y0 = B0, *y1 = B1, *y2 = B2;
-    for (int k = 2; k <= d; ++k) {
-        if (!c.apply(0, mu, y1, T, p) || !c.apply(0, mu, T, y2, p)) return false;
-        if (!c.lincomb(ne, 2.0 / e, y2, -2.0 * cc / e, y1, -1.0, y0, y2)) return false;
-        c64* t = y0;
-        y0 = y1;
-        y1 = y2;
-        y2 = t;
-    }
-    *res = y1;
-    return true;
-}
-
 struct SideResult {
-    std::vector<cd> theta;   // m Ritz values, increasing |theta|
+    std::vector<cd> theta;   // m eigenvalues of H, increasing |theta|
     int outer = 0;
     double max_res = 0.0;
+    long long solves = 0, cg_iters = 0;
 };
 
-// sort the eigenpairs (w, S) of a p x p projected matrix by |w| (S columns)
-void sort_by_modulus(int p, std::vector<cd>& w, std::vector<cd>& S) {
+// sort the eigenpairs (w, S) of a p x p projected matrix by decreasing |w| (S columns)
+void sort_by_modulus_desc(int p, std::vector<cd>& w, std::vector<cd>& S) {
     std::vector<int> ord(p);
     for (int i = 0; i < p; ++i) ord[i] = i;
-    std::sort(ord.begin(), ord.end(), [&](int i, int j) { return std::abs(w[i]) < std::abs(w[j]); });
+    std::sort(ord.begin(), ord.end(), [&](int i, int j) { return std::abs(w[i]) > std::abs(w[j]); });
     std::vector<cd> Ss((size_t)p * p), ws(p);
     for (int j = 0; j < p; ++j) {
         ws[j] = w[ord[j]];
@@ -270,139 +231,199 @@ void sort_by_modulus(int p, std::vector<cd>& w, std::vector<cd>& S) {
     S.swap(Ss);
 }
 
-// residual norms |(W - Q G) s_j| (Q orthonormal, G = Q^dag W) of the first n columns of S
-bool ritz_residuals(Ctx& c, const c64* Q, const c64* W, c64* Z, int p, const std::vector<cd>& G,
-                    const std::vector<cd>& S, int n, std::vector<double>& res) {
-    if (!c.copy(Z, W, p)) return false;
-    std::vector<cd> mG(G.size());
-    for (size_t i = 0; i < G.size(); ++i) mG[i] = -G[i];
-    if (!c.comb(Q, p, mG, p, Z)) return false;
-    std::vector<cd> E;
-    if (!c.proj(Z, p, Z, p, E)) return false;
-    res.assign(n, 0.0);
-    for (int j = 0; j < n; ++j) {
-        cd acc = 0.0;
-        for (int i = 0; i < p; ++i) {
-            cd t = 0.0;
-            for (int k = 0; k < p; ++k) t += E[(size_t)i * p + k] * S[(size_t)k * p + j];
-            acc += std::conj(S[(size_t)i * p + j]) * t;
-        }
-        res[j] = std::sqrt(std::max(0.0, acc.real()));
+// z = H(mu)^{-1} v by conjugate gradients on the normal equations
+// H^dag H z = H^dag v (H^dag = H(-mu)); r, d, q, t: work fields
+bool solve_h(Ctx& c, double mu, const c64* v, c64* z, c64* r, c64* d, c64* q, c64* t, double tol, int max_it,
+             long long& iters) {
+    auto dot = [&](const c64* x, const c64* y, cd& out) -> bool {
+        std::vector<cd> o;
+        if (!c.proj(x, 1, y, 1, o)) return false;
+        out = o[0];
+        return true;
+    };
+    if (!c.ok(hipMemsetAsync(z, 0, sizeof(c64) * c.nf, c.s), "memset")) return false;
+    if (!c.apply(0, -mu, v, r, 1)) return false;   // r = H^dag v (z = 0)
+    if (!c.copy(d, r, 1)) return false;
+    cd rr;
+    if (!dot(r, r, rr)) return false;
+    const double r0 = std::sqrt(rr.real());
+    if (!(r0 > 0)) return true;
+    for (int it = 0; it < max_it; ++it) {
+        if (!c.apply(0, mu, d, q, 1) || !c.apply(0, -mu, q, t, 1)) return false;   // t = H^dag H d
+        cd qq;
+        if (!dot(q, q, qq)) return false;
+        const cd alpha = rr / qq;
+        if (!c.lincomb(c.nf, 1.0, z, alpha, d, 0.0, nullptr, z)) return false;
+        if (!c.lincomb(c.nf, 1.0, r, -alpha, t, 0.0, nullptr, r)) return false;
+        cd rn;
+        if (!dot(r, r, rn)) return false;
+        ++iters;
+        if (std::sqrt(rn.real()) <= tol * r0) break;
+        if (!c.lincomb(c.nf, 1.0, r, rn / rr, d, 0.0, nullptr, d)) return false;
+        rr = rn;
     }
     return true;
 }
 
-// Subspace iteration for one side (mu or -mu).  The filter and the subspace
-// update use Rayleigh-Ritz with H^2, whose wanted eigenvalues lambda^2 are at
-// the edge of its spectrum (Rayleigh-Ritz with H itself would produce spurious
-// Ritz values near zero from mixtures of eigenvectors of opposite sign); the
-// m best vectors are then projected with H to separate lambda from -lambda and
-// to measure the residual |H r - lambda r|.  The m eigenvectors of H end up in
-// Out (unit norm), increasing |lambda|.
-bool subspace_side(Ctx& c, double mu, int m, int p, double tol, int max_outer, int degree, uint64_t seed, c64* Out,
-                   SideResult& sr) {
-    c64* X = c.fields(p);
-    c64* B0 = c.fields(p);
-    c64* B1 = c.fields(p);
-    c64* B2 = c.fields(p);
-    c64* T = c.fields(p);
-    c64* Qm = c.fields(p);
-    c64* Wm = c.fields(p);
-    c64* Zm = c.fields(p);
-    if (!X || !B0 || !B1 || !B2 || !T || !Qm || !Wm || !Zm) return false;
+// One side (mu, or -mu for the left vectors): the m eigenpairs of H(mu) of
+// smallest |lambda| by thick-restart Arnoldi on B = H(mu)^{-1}.  The wanted
+// eigenvalues 1/lambda are those of largest modulus of B: outside the disk that
+// holds the rest of its spectrum, where a Krylov space finds them whatever
+// their phase (a polynomial filter in H^2 cannot separate |lambda| from the
+// imaginary parts of lambda^2).  Each cycle extends the Arnoldi basis to n
+// vectors (one CG solve per vector), takes the Ritz pairs of the n x n
+// projected matrix, and restarts from the k Ritz vectors of largest |theta|
+// plus the last Arnoldi vector (a Krylov decomposition with a full k x k
+// block).  The m eigenvectors of H end up in Out (unit norm), increasing |lambda|.
+bool arnoldi_side(Ctx& c, double mu, int m, int n, double tol, int max_cycles, uint64_t seed, c64* Out,
+                  SideResult& sr) {
+    const int kkeep = std::min(n - 4, m + std::max(8, (n - m) / 2));
+    c64* Vb = c.fields(n + 1);
+    c64* T = c.fields(n);
+    c64* Zm = c.fields(m);
+    c64* w4[4] = {c.fields(1), c.fields(1), c.fields(1), c.fields(1)};
+    if (!Vb || !T || !Zm || !w4[0] || !w4[1] || !w4[2] || !w4[3]) return false;
+    auto V = [&](int i) { return Vb + (size_t)i * c.nf; };
     {
-        const long long ne = (long long)p * c.nf;
-        fill_random_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, c.s>>>(ne, c.nf, c.g.V, c.g.Vp, seed, X);
+        fill_random_kernel<<<(unsigned)((c.nf + 255) / 256), 256, 0, c.s>>>(c.nf, c.nf, c.g.V, c.g.Vp, seed, Vb);
         if (!c.ok(hipGetLastError(), "fill_random")) return false;
+        const double nv = c.norm(V(0));
+        if (!c.lincomb(c.nf, 1.0 / nv, V(0), 0.0, nullptr, 0.0, nullptr, V(0))) return false;
     }
-    if (!orthonormalise(c, X, T, p)) return false;
-    // upper bound of |lambda|^2: ||Dw|| <= |m0 + 4| + 3 + e^{|mu|} (r = 1, unit-norm links)
+    // ||H|| <= |m0 + 4| + 3 + e^{|mu|} (r = 1, unit-norm links)
     const double hb = std::fabs(c.md) + 3.0 + std::exp(std::fabs(mu));
-    const double b = 1.02 * hb * hb;
-    double a = 0.25 * b;
-    double best = 1e300;
-    int best_it = 0;
-    for (int it = 1; it <= max_outer; ++it) {
-        c64* Y = nullptr;
-        if (!cheb_filter(c, mu, X, B0, B1, B2, T, p, degree, a, b, &Y)) return false;
-        c64* Q = Y;
-        c64* Wb = (Q == B0) ? B1 : B0;     // H Q, then H^2 Q
-        c64* Zb = (Q == B2) ? B1 : B2;
-        if (!orthonormalise(c, Q, T, p)) return false;
-        if (!c.apply(0, mu, Q, T, p) || !c.apply(0, mu, T, Wb, p)) return false;
-        std::vector<cd> G2;
-        if (!c.proj(Q, p, Wb, p, G2)) return false;
-        std::vector<cd> w2, S2;
-        if (!dense::eig_general(p, G2, w2, S2)) {
+    std::vector<cd> Hm((size_t)(n + 1) * n, cd(0));   // (n + 1) x n, row-major
+    auto h = [&](int i, int j) -> cd& { return Hm[(size_t)i * n + j]; };
+    int k = 0;
+    for (int cyc = 1; cyc <= max_cycles; ++cyc) {
+        for (int j = k; j < n; ++j) {
+            if (!solve_h(c, mu, V(j), V(j + 1), w4[0], w4[1], w4[2], w4[3], 1e-13, 5000, sr.cg_iters)) return false;
+            ++sr.solves;
+            std::vector<cd> hc(j + 1, cd(0));
+            for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
+                std::vector<cd> hp;
+                if (!c.proj(Vb, j + 1, V(j + 1), 1, hp)) return false;
+                for (int i = 0; i <= j; ++i) hc[i] += hp[i];
+                for (auto& x : hp) x = -x;
+                if (!c.comb(Vb, j + 1, hp, 1, V(j + 1))) return false;
+            }
+            const double hn = c.norm(V(j + 1));
+            for (int i = 0; i <= j; ++i) h(i, j) = hc[i];
+            h(j + 1, j) = hn;
+            if (!(hn > 0)) {
+                c.err = "Arnoldi breakdown (invariant subspace); choose another seed";
+                return false;
+            }
+            if (!c.lincomb(c.nf, 1.0 / hn, V(j + 1), 0.0, nullptr, 0.0, nullptr, V(j + 1))) return false;
+        }
+        // Ritz pairs of B in the n-dimensional space, decreasing |theta|
+        std::vector<cd> Hn((size_t)n * n), th, S;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Hn[(size_t)i * n + j] = h(i, j);
+        if (!dense::eig_general(n, Hn, th, S)) {
             c.err = "QR iteration of the projected problem did not converge";
             return false;
         }
-        sort_by_modulus(p, w2, S2);
-        // next start: all p Ritz vectors of H^2
-        if (!c.ok(hipMemsetAsync(X, 0, sizeof(c64) * (size_t)p * c.nf, c.s), "memset")) return false;
-        if (!c.comb(Q, p, S2, p, X)) return false;
-        // H is projected on the first mq >= m Ritz vectors of H^2, mq at the
-        // largest relative gap of |theta^2| in [m, p - 4].  A weak gauge field
-        // leaves the spectrum of H close to symmetric (lambda next to some
-        // -lambda'), H^2 cannot tell such a pair apart and its Ritz vectors mix
-        // the two; H separates them only when the whole cluster is in the space.
-        int mq = m;
+        sort_by_modulus_desc(n, th, S);
+        // estimated residual of H: |H x - lambda x| <= |lambda| ||H|| |B x - theta x|,
+        // |B x - theta x| = |row n of the decomposition . s|
+        double est = 0.0;
+        for (int i = 0; i < m; ++i) {
+            cd rb = 0.0;
+            for (int j = 0; j < n; ++j) rb += h(n, j) * S[(size_t)j * n + i];
+            est = std::max(est, std::abs(rb) * hb / std::abs(th[i]));
+        }
+        sr.outer = cyc;
+        const bool last = cyc == max_cycles;
+        if (est <= tol || last) {
+            // eigenvectors x = V s (unit norm), eigenvalues 1/theta, true residuals |H x - lambda x|
+            std::vector<cd> Sm((size_t)n * m);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < m; ++j) Sm[(size_t)i * m + j] = S[(size_t)i * n + j];
+            if (!c.ok(hipMemsetAsync(Out, 0, sizeof(c64) * (size_t)m * c.nf, c.s), "memset")) return false;
+            if (!c.comb(Vb, n, Sm, m, Out)) return false;
+            if (!c.apply(0, mu, Out, Zm, m)) return false;
+            sr.theta.assign(m, cd(0));
+            double rmax = 0.0;
+            for (int i = 0; i < m; ++i) {
+                c64* xi = Out + (size_t)i * c.nf;
+                c64* zi = Zm + (size_t)i * c.nf;
+                const double nx = c.norm(xi);
+                if (!c.lincomb(c.nf, 1.0 / nx, xi, 0.0, nullptr, 0.0, nullptr, xi)) return false;
+                const cd lam = 1.0 / th[i];
+                sr.theta[i] = lam;
+                if (!c.lincomb(c.nf, 1.0 / nx, zi, -lam, xi, 0.0, nullptr, zi)) return false;
+                rmax = std::max(rmax, c.norm(zi));
+            }
+            sr.max_res = rmax;
+            if (verbose()) {
+                std::fprintf(stderr, "eigs mu=%+.3f cycle %d: estimate %.2e, residual %.3e, |lambda_m| %.6f, %lld solves, %lld CG\n",
+                             mu, cyc, est, rmax, std::abs(sr.theta[m - 1]), sr.solves, sr.cg_iters);
+                std::fflush(stderr);
+            }
+            if (rmax <= tol || last) return true;
+        } else if (verbose()) {
+            std::fprintf(stderr, "eigs mu=%+.3f cycle %d: estimate %.2e, |lambda_m| %.6f, %lld solves, %lld CG\n", mu,
+                         cyc, est, std::abs(1.0 / th[m - 1]), sr.solves, sr.cg_iters);
+            std::fflush(stderr);
+        }
+        // thick restart: keep kk >= kkeep Ritz vectors, kk at the largest
+        // relative gap of |theta| in [kkeep, kkeep + 4] (a cluster at the cut
+        // is kept whole; the rest of the basis is new Krylov directions)
+        int kk = kkeep;
         {
             double gbest = -1.0;
-            const int jmax = std::min(p - 1, std::max(m, p - 4));
-            for (int j = m; j <= jmax; ++j) {
-                const double gap = (std::abs(w2[j]) - std::abs(w2[j - 1])) / std::max(std::abs(w2[j - 1]), 1e-300);
+            for (int j = kkeep; j <= std::min(n - 2, kkeep + 4); ++j) {
+                const double gap = (std::abs(th[j - 1]) - std::abs(th[j])) / std::abs(th[j - 1]);
                 if (gap > gbest) {
                     gbest = gap;
-                    mq = j;
+                    kk = j;
                 }
             }
         }
-        // orthonormalise, project H, keep the m smallest |lambda|, residuals |H r - lambda r|
-        if (!c.copy(Qm, X, mq)) return false;
-        if (!orthonormalise(c, Qm, Zm, mq)) return false;
-        if (!c.apply(0, mu, Qm, Wm, mq)) return false;
-        std::vector<cd> G, w, S;
-        if (!c.proj(Qm, mq, Wm, mq, G)) return false;
-        if (!dense::eig_general(mq, G, w, S)) {
-            c.err = "QR iteration of the projected problem did not converge";
-            return false;
+        // orthonormal basis Q of the kept Ritz vectors (host Gram-Schmidt, twice)
+        std::vector<cd> Q((size_t)n * kk);
+        for (int j = 0; j < kk; ++j) {
+            for (int i = 0; i < n; ++i) Q[(size_t)i * kk + j] = S[(size_t)i * n + j];
+            for (int pass = 0; pass < 2; ++pass)
+                for (int q = 0; q < j; ++q) {
+                    cd d = 0.0;
+                    for (int i = 0; i < n; ++i) d += std::conj(Q[(size_t)i * kk + q]) * Q[(size_t)i * kk + j];
+                    for (int i = 0; i < n; ++i) Q[(size_t)i * kk + j] -= d * Q[(size_t)i * kk + q];
+                }
+            double nq = 0.0;
+            for (int i = 0; i < n; ++i) nq += std::norm(Q[(size_t)i * kk + j]);
+            nq = std::sqrt(nq);
+            for (int i = 0; i < n; ++i) Q[(size_t)i * kk + j] /= nq;
         }
-        sort_by_modulus(mq, w, S);
-        std::vector<double> res;
-        if (!ritz_residuals(c, Qm, Wm, Zm, mq, G, S, m, res)) return false;
-        const double rmax = *std::max_element(res.begin(), res.end());
-        sr.theta.assign(w.begin(), w.begin() + m);
-        sr.outer = it;
-        sr.max_res = rmax;
-        if (verbose()) {
-            int nconv = 0;
-            while (nconv < m && res[nconv] <= tol) ++nconv;
-            std::fprintf(stderr,
-                         "eigs mu=%+.3f outer %d: max residual %.3e, first %d converged, res_1 %.1e, |lambda_m| %.6f, "
-                         "a %.4f, H on %d of %d\n",
-                         mu, it, rmax, nconv, res[0], std::abs(w[m - 1]), a, mq, p);
-            std::fflush(stderr);
+        // new basis [V Q, v_n], new decomposition: B (V Q) = (V Q) (Q^dag H Q) + v_n (h_n Q)
+        if (!c.ok(hipMemsetAsync(T, 0, sizeof(c64) * (size_t)kk * c.nf, c.s), "memset")) return false;
+        if (!c.comb(Vb, n, Q, kk, T)) return false;
+        if (!c.copy(V(kk), V(n), 1)) return false;
+        if (!c.copy(Vb, T, kk)) return false;
+        std::vector<cd> HQ((size_t)n * kk, cd(0)), M((size_t)kk * kk, cd(0)), brow(kk, cd(0));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < kk; ++j) {
+                cd t = 0.0;
+                for (int l = 0; l < n; ++l) t += Hn[(size_t)i * n + l] * Q[(size_t)l * kk + j];
+                HQ[(size_t)i * kk + j] = t;
+            }
+        for (int i = 0; i < kk; ++i)
+            for (int j = 0; j < kk; ++j) {
+                cd t = 0.0;
+                for (int l = 0; l < n; ++l) t += std::conj(Q[(size_t)l * kk + i]) * HQ[(size_t)l * kk + j];
+                M[(size_t)i * kk + j] = t;
+            }
+        for (int j = 0; j < kk; ++j) {
+            cd t = 0.0;
+            for (int l = 0; l < n; ++l) t += h(n, l) * Q[(size_t)l * kk + j];
+            brow[j] = t;
         }
-        // stagnation: no halving of the best residual in 20 outer iterations
-        if (rmax < 0.5 * best) {
-            best = rmax;
-            best_it = it;
-        }
-        const bool stalled = it - best_it >= 20;
-        if (rmax <= tol || it == max_outer || stalled) {
-            // eigenvectors r = Qm s (unit norm), the first m columns of S
-            std::vector<cd> Sm((size_t)mq * m);
-            for (int i = 0; i < mq; ++i)
-                for (int j = 0; j < m; ++j) Sm[(size_t)i * m + j] = S[(size_t)i * mq + j];
-            if (!c.ok(hipMemsetAsync(Out, 0, sizeof(c64) * (size_t)m * c.nf, c.s), "memset")) return false;
-            if (!c.comb(Qm, mq, Sm, m, Out)) return false;
-            break;
-        }
-        // damp everything above the largest Ritz value of H^2 in the subspace
-        a = std::max(w2[p - 1].real(), 1e-6 * b);
-        if (a >= b) a = 0.5 * b;
-        (void)Zb;
+        std::fill(Hm.begin(), Hm.end(), cd(0));
+        for (int i = 0; i < kk; ++i)
+            for (int j = 0; j < kk; ++j) h(i, j) = M[(size_t)i * kk + j];
+        for (int j = 0; j < kk; ++j) h(kk, j) = brow[j];
+        k = kk;
     }
     return true;
 }
@@ -414,11 +435,11 @@ bool gmres_shifted(Ctx& c, double mu, bool adjoint, cd shift, const c64* Rv, con
     const c64* Pa = adjoint ? Rv : Lv;   // projector P z = Pb (Pa^dag z)
     const c64* Pb = adjoint ? Lv : Rv;
     const double amu = adjoint ? -mu : mu;
-    c64* Vb = c.fields(restart + 1);
-    c64* w = c.fields(1);
-    c64* u = c.fields(1);
-    c64* r = c.fields(1);
-    if (!Vb || !w || !u || !r) return false;
+    c64* Vb = c.reuse(restart + 4);   // Krylov basis, then w, u, r
+    if (!Vb) return false;
+    c64* w = Vb + (size_t)(restart + 1) * c.nf;
+    c64* u = w + c.nf;
+    c64* r = u + c.nf;
     // op(z) = shift (1-P) z - A (1-P) z + P z
     auto op = [&](const c64* zin, c64* out) -> bool {
         std::vector<cd> pc;
@@ -519,8 +540,7 @@ int eigs_compute(const EigParams& P, EigResult& out) {
     c.s = P.stream;
     c.nf = (long long)12 * P.g.Vp;
     const int m = P.m, l = P.l;
-    const int p = P.p > m ? P.p : m + std::max(16, m / 2);
-    const int degree = P.degree;
+    const int p = P.p > m ? P.p : 2 * m + 20;   // Arnoldi basis size
     out = EigResult{};
     auto fail = [&](int code) {
         out.err = c.err.empty() ? "eigensolver failed" : c.err;
@@ -530,15 +550,15 @@ int eigs_compute(const EigParams& P, EigResult& out) {
     c64* Lraw = c.fields(m);
     if (!Rv || !Lraw) return fail(-2);
     SideResult right, left;
-    if (!subspace_side(c, P.mu, m, p, P.tol, P.max_outer, degree, P.seed, Rv, right)) return fail(-3);
-    if (!subspace_side(c, -P.mu, m, p, P.tol, P.max_outer, degree, P.seed + 1, Lraw, left)) return fail(-3);
+    if (!arnoldi_side(c, P.mu, m, p, P.tol, P.max_outer, P.seed, Rv, right)) return fail(-3);
+    if (!arnoldi_side(c, -P.mu, m, p, P.tol, P.max_outer, P.seed + 1, Lraw, left)) return fail(-3);
     out.outer_right = right.outer;
     out.outer_left = left.outer;
     out.res_right = right.max_res;
     out.res_left = left.max_res;
     if (right.max_res > P.tol || left.max_res > P.tol) {
         c.err = "eigenpairs not converged: residual " + std::to_string(std::max(right.max_res, left.max_res)) +
-                " after " + std::to_string(std::max(right.outer, left.outer)) + " outer iterations";
+                " after " + std::to_string(std::max(right.outer, left.outer)) + " restart cycles";
         return fail(-7);
     }
     // the two sides must hold the same eigenvalues (conjugated)

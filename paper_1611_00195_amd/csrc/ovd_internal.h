@@ -230,10 +230,10 @@ struct EigParams {
     const c64* dU = nullptr;    // FP64 internal link direction (dir_link)
     double md = 0.0;            // m0 + 4 r
     double mu = 0.0;
-    int m = 0, l = 0, p = 0;    // pairs, derivative pairs, subspace size (0: m + max(16, m/2))
+    int m = 0, l = 0, p = 0;    // pairs, derivative pairs, Arnoldi basis size (0: 2 m + 20)
     bool dir_link = false;
     double tol = 1e-10;         // residual |H r - theta r| of the wanted pairs
-    int max_outer = 80, degree = 80;
+    int max_outer = 80;         // restart cycles of the Arnoldi iteration
     double gmres_tol = 1e-11;
     int gmres_max = 4000;
     uint64_t seed = 1611;
