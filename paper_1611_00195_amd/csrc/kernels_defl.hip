@@ -75,14 +75,19 @@ __global__ void defl_proj_reduce(int m, int nr, int nsplit, const c64* __restric
     C[t] = s;
 }
 
+// reduction index split into chunks of this many elements (a multiple of 4):
+// short enough that a single-vector projection (a Krylov or CG inner product)
+// still runs many independent waves
+constexpr long long kProjChunk = 256;
+
 size_t defl_proj_scratch(int m, int nr, long long nf) {
-    const long long nsplit = (nf + 2047) / 2048;
+    const long long nsplit = (nf + kProjChunk - 1) / kProjChunk;
     return (size_t)nsplit * m * nr;
 }
 
 void launch_defl_proj(const c64* A, long long sA, int m, const c64* B, long long sB, int nr, long long nf,
                       c64* C, c64* scratch, hipStream_t s) {
-    const long long chunk = 2048;   // multiple of 4
+    const long long chunk = kProjChunk;
     const int nsplit = (int)((nf + chunk - 1) / chunk);
     dim3 grid((m + 15) / 16, (nr + 15) / 16, nsplit);
     defl_proj_kernel<<<grid, 64, 0, s>>>(A, sA, m, B, sB, nr, nf, chunk, scratch);
