@@ -167,8 +167,8 @@ typedef struct {
     int outer_right, outer_left;      /* Arnoldi restart cycles on H(mu)^-1 and H(-mu)^-1 = (H(mu)^dag)^-1 */
     double max_res_right, max_res_left; /* max |H r - lambda r| (|r| = 1) of the m pairs, both sides */
     double max_biorth;                /* max |L^dag R - 1| */
-    int gmres_iters;                  /* total GMRES iterations of the 2 l derivative solves */
-    double max_gmres_res;             /* largest relative residual of those solves */
+    int shift_iters;                  /* total iterations of the 2 l shifted solves of the derivatives */
+    double max_shift_res;             /* largest relative residual of those solves */
     double ms;                        /* wall time */
 } ovd_eig_stats;
 
@@ -183,8 +183,8 @@ typedef struct {
  * with P = sum_{i<m} R_i L_i^dag and the resolvents taken on the range of 1 - P.
  * Method: thick-restart Arnoldi on H^-1 (and H^dag^-1), whose eigenvalues of
  * largest modulus are 1/lambda for the wanted lambda, every application a
- * conjugate-gradient solve of the normal equations, FP64; restarted GMRES for
- * the shifted solves of the derivatives.
+ * conjugate-gradient solve of the normal equations, FP64; the shifted solves
+ * of the derivatives by conjugate gradients on their normal equations (CGLS).
  *   tol   residual bound |H r - lambda r| for |r| = 1 (<= 0: 1e-10)
  *   lam   host double[2 m] (re, im), increasing |lambda|, or NULL
  * The set replaces any set of the same mu, exactly as ovd_set_deflation.

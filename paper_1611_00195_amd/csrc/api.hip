@@ -1110,8 +1110,8 @@ ovd_status ovd_compute_deflation(ovd_h h, double mu, int m, int l, const ovd_dir
         st->max_res_right = R.res_right;
         st->max_res_left = R.res_left;
         st->max_biorth = R.biorth;
-        st->gmres_iters = R.gmres_iters;
-        st->max_gmres_res = R.gmres_res;
+        st->shift_iters = R.shift_iters;
+        st->max_shift_res = R.shift_res;
         st->ms = R.ms;
     }
     if (rc != 0) {

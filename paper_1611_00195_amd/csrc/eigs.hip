@@ -21,9 +21,9 @@
 //          + (lambda_j - A)^{-1} (1 - P) dA R_j            (solved on range(1 - P))
 //   dL_j = sum_{i != j} L_i conj((L_j^dag dA R_i) / (lambda_j - lambda_i))
 //          + (conj(lambda_j) - A^dag)^{-1} (1 - P)^dag dA^dag L_j
-// The shifted systems are solved by restarted GMRES with classical
-// Gram-Schmidt applied twice; every long-vector product is a stencil launch
-// or an MFMA projection (kernels_defl.hip), the small problems run on the host.
+// The shifted systems are solved by conjugate gradients on their normal
+// equations (CGLS); every long-vector product is a stencil launch or an MFMA
+// projection (kernels_defl.hip), the small problems run on the host.
 #include "ovd_internal.h"
 #include "dense.hpp"
 
@@ -428,103 +428,71 @@ bool arnoldi_side(Ctx& c, double mu, int m, int n, double tol, int max_cycles, u
     return true;
 }
 
-// restarted GMRES for (shift - A) z = rhs on range(1 - P), P = sum R_i L_i^dag
-// (adjoint side: A^dag = H(-mu), P^dag = sum L_i R_i^dag); z in Z.
-bool gmres_shifted(Ctx& c, double mu, bool adjoint, cd shift, const c64* Rv, const c64* Lv, int m, const c64* rhs,
-                   c64* Z, double tol, int restart, int max_it, int& iters, double& relres) {
-    const c64* Pa = adjoint ? Rv : Lv;   // projector P z = Pb (Pa^dag z)
+// (shift - A) z = rhs on the range of 1 - P (P = sum R_i L_i^dag; adjoint
+// side: A^dag = H(-mu), P^dag = sum L_i R_i^dag), solved as op z = rhs with
+// op = shift (1 - P) - A (1 - P) + P by CGLS: conjugate gradients on the
+// normal equations op^dag op z = op^dag rhs with the residual rhs - op z kept
+// explicitly.  The shift sits inside the spectrum of A (an interior
+// eigenvalue), so op is indefinite with a small gap; CGLS converges
+// monotonically there, where restarted GMRES stalls.  z in Z.
+bool cgls_shifted(Ctx& c, double mu, bool adjoint, cd shift, const c64* Rv, const c64* Lv, int m, const c64* rhs,
+                  c64* Z, double tol, int max_it, int& iters, double& relres) {
+    const c64* Pa = adjoint ? Rv : Lv;   // P z = Pb (Pa^dag z), P^dag y = Pa (Pb^dag y)
     const c64* Pb = adjoint ? Lv : Rv;
     const double amu = adjoint ? -mu : mu;
-    c64* Vb = c.reuse(restart + 4);   // Krylov basis, then w, u, r
-    if (!Vb) return false;
-    c64* w = Vb + (size_t)(restart + 1) * c.nf;
-    c64* u = w + c.nf;
-    c64* r = u + c.nf;
-    // op(z) = shift (1-P) z - A (1-P) z + P z
+    c64* W = c.reuse(6);
+    if (!W) return false;
+    c64 *r = W, *s = W + c.nf, *p = W + 2 * c.nf, *q = W + 3 * c.nf, *u = W + 4 * c.nf, *t = W + 5 * c.nf;
+    // out = op(zin): u = (1 - P) zin, out = shift u - A u + (zin - u)
     auto op = [&](const c64* zin, c64* out) -> bool {
         std::vector<cd> pc;
-        if (!c.proj(Pa, m, zin, 1, pc)) return false;        // Pa^dag z
+        if (!c.proj(Pa, m, zin, 1, pc)) return false;
         if (!c.copy(u, zin, 1)) return false;
         for (auto& v : pc) v = -v;
-        if (!c.comb(Pb, m, pc, 1, u)) return false;          // u = (1 - P) z
-        if (!c.apply(0, amu, u, out, 1)) return false;       // out = A u
-        // out = shift u - A u + (z - u)
+        if (!c.comb(Pb, m, pc, 1, u)) return false;
+        if (!c.apply(0, amu, u, out, 1)) return false;
         return c.lincomb(c.nf, shift - 1.0, u, -1.0, out, 1.0, zin, out);
     };
-    const double bn = c.norm(rhs);
-    if (!(bn > 0)) {
-        iters = 0;
-        relres = 0.0;
-        return c.ok(hipMemsetAsync(Z, 0, sizeof(c64) * c.nf, c.s), "memset");
-    }
-    if (!c.ok(hipMemsetAsync(Z, 0, sizeof(c64) * c.nf, c.s), "memset")) return false;
+    // out = op^dag(y) = (1 - P^dag)(conj(shift) y - A^dag y) + P^dag y = t + Pa (Pb^dag (y - t))
+    auto opd = [&](const c64* y, c64* out) -> bool {
+        if (!c.apply(0, -amu, y, t, 1)) return false;
+        if (!c.lincomb(c.nf, std::conj(shift), y, -1.0, t, 0.0, nullptr, t)) return false;
+        if (!c.lincomb(c.nf, 1.0, y, -1.0, t, 0.0, nullptr, u)) return false;
+        std::vector<cd> pc;
+        if (!c.proj(Pb, m, u, 1, pc)) return false;
+        if (!c.copy(out, t, 1)) return false;
+        return c.comb(Pa, m, pc, 1, out);
+    };
     iters = 0;
+    relres = 0.0;
+    if (!c.ok(hipMemsetAsync(Z, 0, sizeof(c64) * c.nf, c.s), "memset")) return false;
+    const double bn = c.norm(rhs);
+    if (!(bn > 0)) return true;
+    if (!c.copy(r, rhs, 1) || !opd(r, s) || !c.copy(p, s, 1)) return false;
+    double gam = c.norm(s);
+    gam *= gam;
     relres = 1.0;
     while (iters < max_it) {
-        // r = rhs - op(Z)
-        if (!op(Z, w)) return false;
-        if (!c.lincomb(c.nf, 1.0, rhs, -1.0, w, 0.0, nullptr, r)) return false;
-        const double beta = c.norm(r);
-        relres = beta / bn;
+        if (!op(p, q)) return false;
+        double qq = c.norm(q);
+        qq *= qq;
+        if (!(qq > 0)) break;
+        const double alpha = gam / qq;
+        if (!c.lincomb(c.nf, 1.0, Z, alpha, p, 0.0, nullptr, Z)) return false;
+        if (!c.lincomb(c.nf, 1.0, r, -alpha, q, 0.0, nullptr, r)) return false;
+        ++iters;
+        relres = c.norm(r) / bn;
         if (relres <= tol) break;
-        if (!c.lincomb(c.nf, 1.0 / beta, r, 0.0, nullptr, 0.0, nullptr, Vb)) return false;
-        std::vector<cd> H((size_t)(restart + 1) * restart, cd(0)), g(restart + 1, cd(0)), sn(restart);
-        std::vector<double> cs(restart);
-        g[0] = beta;
-        int j = 0;
-        for (; j < restart && iters < max_it; ++j, ++iters) {
-            c64* vj = Vb + (size_t)j * c.nf;
-            c64* vn = Vb + (size_t)(j + 1) * c.nf;
-            if (!op(vj, vn)) return false;
-            // classical Gram-Schmidt, twice
-            std::vector<cd> h(j + 1, cd(0));
-            for (int pass = 0; pass < 2; ++pass) {
-                std::vector<cd> hp;
-                if (!c.proj(Vb, j + 1, vn, 1, hp)) return false;
-                for (int i = 0; i <= j; ++i) h[i] += hp[i];
-                for (auto& v : hp) v = -v;
-                if (!c.comb(Vb, j + 1, hp, 1, vn)) return false;
-            }
-            const double hn = c.norm(vn);
-            for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = h[i];
-            H[(size_t)(j + 1) * restart + j] = hn;
-            // apply the previous rotations, then a new one
-            for (int i = 0; i < j; ++i) {
-                const cd t1 = H[(size_t)i * restart + j], t2 = H[(size_t)(i + 1) * restart + j];
-                H[(size_t)i * restart + j] = cs[i] * t1 + sn[i] * t2;
-                H[(size_t)(i + 1) * restart + j] = -std::conj(sn[i]) * t1 + cs[i] * t2;
-            }
-            dense::givens(H[(size_t)j * restart + j], H[(size_t)(j + 1) * restart + j], cs[j], sn[j]);
-            const cd t1 = H[(size_t)j * restart + j], t2 = H[(size_t)(j + 1) * restart + j];
-            H[(size_t)j * restart + j] = cs[j] * t1 + sn[j] * t2;
-            H[(size_t)(j + 1) * restart + j] = 0.0;
-            const cd g1 = g[j], g2 = g[j + 1];
-            g[j] = cs[j] * g1 + sn[j] * g2;
-            g[j + 1] = -std::conj(sn[j]) * g1 + cs[j] * g2;
-            relres = std::abs(g[j + 1]) / bn;
-            if (hn > 0 && !c.lincomb(c.nf, 1.0 / hn, vn, 0.0, nullptr, 0.0, nullptr, vn)) return false;
-            if (relres <= tol || !(hn > 0)) {
-                ++j;
-                ++iters;
-                break;
-            }
-        }
-        // y = H(0:j, 0:j)^{-1} g, Z += V y
-        std::vector<cd> y(j, cd(0));
-        for (int i = j - 1; i >= 0; --i) {
-            cd t = g[i];
-            for (int k = i + 1; k < j; ++k) t -= H[(size_t)i * restart + k] * y[k];
-            y[i] = t / H[(size_t)i * restart + i];
-        }
-        if (j > 0 && !c.comb(Vb, j, y, 1, Z)) return false;
-        if (relres <= tol) {
-            // true residual of the final iterate
-            if (!op(Z, w)) return false;
-            if (!c.lincomb(c.nf, 1.0, rhs, -1.0, w, 0.0, nullptr, r)) return false;
-            relres = c.norm(r) / bn;
-            break;
-        }
+        if (!opd(r, s)) return false;
+        double gn = c.norm(s);
+        gn *= gn;
+        if (!c.lincomb(c.nf, 1.0, s, gn / gam, p, 0.0, nullptr, p)) return false;
+        gam = gn;
     }
+    // true residual of the final iterate
+    if (!op(Z, q)) return false;
+    if (!c.lincomb(c.nf, 1.0, rhs, -1.0, q, 0.0, nullptr, r)) return false;
+    relres = c.norm(r) / bn;
     return true;
 }
 
@@ -615,8 +583,6 @@ int eigs_compute(const EigParams& P, EigResult& out) {
         if (!c.proj(Lv, m, D, m, C)) return fail(-3);
         std::vector<cd> lam(m);
         for (int i = 0; i < m; ++i) lam[i] = right.theta[i];
-        // GMRES restart length: long (the shifts are interior), at most the dimension
-        const int restart = (int)std::min<long long>(150, 12LL * c.g.V - 1);
         for (int j = 0; j < l; ++j) {
             for (int i = 0; i < m; ++i)
                 if (i != j && std::abs(lam[j] - lam[i]) < 1e-9 * (1.0 + std::abs(lam[j]))) {
@@ -630,14 +596,14 @@ int eigs_compute(const EigParams& P, EigResult& out) {
             if (!c.comb(Rv, m, cj, 1, rhs)) return fail(-3);
             int it = 0;
             double rr = 0.0;
-            if (!gmres_shifted(c, P.mu, false, lam[j], Rv, Lv, m, rhs, z, P.gmres_tol, restart, P.gmres_max, it, rr))
+            if (!cgls_shifted(c, P.mu, false, lam[j], Rv, Lv, m, rhs, z, P.shift_tol, P.shift_max, it, rr))
                 return fail(-3);
             if (verbose()) {
-                std::fprintf(stderr, "eigs dR_%d: %d GMRES iterations, residual %.2e\n", j, it, rr);
+                std::fprintf(stderr, "eigs dR_%d: %d CGLS iterations, residual %.2e\n", j, it, rr);
                 std::fflush(stderr);
             }
-            out.gmres_iters += it;
-            out.gmres_res = std::max(out.gmres_res, rr);
+            out.shift_iters += it;
+            out.shift_res = std::max(out.shift_res, rr);
             c64* dRj = dR + (size_t)j * c.nf;
             if (!c.copy(dRj, z, 1)) return fail(-3);
             std::vector<cd> sr(m, cd(0));
@@ -651,15 +617,14 @@ int eigs_compute(const EigParams& P, EigResult& out) {
             if (!c.copy(rhs, e, 1)) return fail(-3);
             for (auto& v : pr) v = -v;
             if (!c.comb(Lv, m, pr, 1, rhs)) return fail(-3);
-            if (!gmres_shifted(c, P.mu, true, std::conj(lam[j]), Rv, Lv, m, rhs, z, P.gmres_tol, restart, P.gmres_max,
-                               it, rr))
+            if (!cgls_shifted(c, P.mu, true, std::conj(lam[j]), Rv, Lv, m, rhs, z, P.shift_tol, P.shift_max, it, rr))
                 return fail(-3);
             if (verbose()) {
-                std::fprintf(stderr, "eigs dL_%d: %d GMRES iterations, residual %.2e\n", j, it, rr);
+                std::fprintf(stderr, "eigs dL_%d: %d CGLS iterations, residual %.2e\n", j, it, rr);
                 std::fflush(stderr);
             }
-            out.gmres_iters += it;
-            out.gmres_res = std::max(out.gmres_res, rr);
+            out.shift_iters += it;
+            out.shift_res = std::max(out.shift_res, rr);
             c64* dLj = dL + (size_t)j * c.nf;
             if (!c.copy(dLj, z, 1)) return fail(-3);
             std::vector<cd> sl(m, cd(0));
@@ -667,9 +632,9 @@ int eigs_compute(const EigParams& P, EigResult& out) {
                 if (i != j) sl[i] = std::conj(C[(size_t)j * m + i] / (lam[j] - lam[i]));
             if (!c.comb(Lv, m, sl, 1, dLj)) return fail(-3);
         }
-        if (out.gmres_res > 1e3 * P.gmres_tol) {
+        if (out.shift_res > 1e3 * P.shift_tol) {
             c.err = "shifted solves for the eigenvector derivatives did not converge (residual " +
-                    std::to_string(out.gmres_res) + ")";
+                    std::to_string(out.shift_res) + ")";
             return fail(-7);
         }
         out.dR = dR;

@@ -67,12 +67,25 @@ __global__ __launch_bounds__(64) void defl_proj_kernel(const c64* __restrict__ A
     }
 }
 
-__global__ void defl_proj_reduce(int m, int nr, int nsplit, const c64* __restrict__ part, c64* __restrict__ C) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m * nr) return;
+// one block per output: each thread sums a strided subset of the splits, then
+// a tree over the block (fixed order, so the result is deterministic)
+__global__ __launch_bounds__(256) void defl_proj_reduce(int m, int nr, int nsplit, const c64* __restrict__ part,
+                                                        c64* __restrict__ C) {
+    __shared__ double re[256], im[256];
+    const int t = blockIdx.x;
     c64 s{0.0, 0.0};
-    for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * m * nr + t];
-    C[t] = s;
+    for (int z = threadIdx.x; z < nsplit; z += blockDim.x) s += part[(size_t)z * m * nr + t];
+    re[threadIdx.x] = s.re;
+    im[threadIdx.x] = s.im;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            re[threadIdx.x] += re[threadIdx.x + w];
+            im[threadIdx.x] += im[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C[t] = c64{re[0], im[0]};
 }
 
 // reduction index split into chunks of this many elements (a multiple of 4):
@@ -87,11 +100,12 @@ size_t defl_proj_scratch(int m, int nr, long long nf) {
 
 void launch_defl_proj(const c64* A, long long sA, int m, const c64* B, long long sB, int nr, long long nf,
                       c64* C, c64* scratch, hipStream_t s) {
+    if (m <= 0 || nr <= 0) return;
     const long long chunk = kProjChunk;
     const int nsplit = (int)((nf + chunk - 1) / chunk);
     dim3 grid((m + 15) / 16, (nr + 15) / 16, nsplit);
     defl_proj_kernel<<<grid, 64, 0, s>>>(A, sA, m, B, sB, nr, nf, chunk, scratch);
-    defl_proj_reduce<<<(m * nr + 255) / 256, 256, 0, s>>>(m, nr, nsplit, scratch, C);
+    defl_proj_reduce<<<m * nr, 256, 0, s>>>(m, nr, nsplit, scratch, C);
 }
 
 // ---------------------------------------------------------------------------

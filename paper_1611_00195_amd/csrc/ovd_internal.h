@@ -234,8 +234,8 @@ struct EigParams {
     bool dir_link = false;
     double tol = 1e-10;         // residual |H r - theta r| of the wanted pairs
     int max_outer = 80;         // restart cycles of the Arnoldi iteration
-    double gmres_tol = 1e-11;
-    int gmres_max = 4000;
+    double shift_tol = 1e-11;   // relative residual of the shifted derivative solves
+    int shift_max = 20000;      // and their iteration limit
     uint64_t seed = 1611;
     hipStream_t stream = nullptr;
 };
@@ -243,8 +243,8 @@ struct EigResult {
     std::vector<c64> lam;                 // m eigenvalues, increasing |lambda|
     c64 *R = nullptr, *L = nullptr;       // device [m][12][Vp], caller frees
     c64 *dR = nullptr, *dL = nullptr;     // device [l][12][Vp] or null, caller frees
-    int outer_right = 0, outer_left = 0, gmres_iters = 0;
-    double res_right = 0, res_left = 0, biorth = 0, gmres_res = 0, ms = 0;
+    int outer_right = 0, outer_left = 0, shift_iters = 0;
+    double res_right = 0, res_left = 0, biorth = 0, shift_res = 0, ms = 0;
     std::string err;
 };
 // 0 on success; -2 allocation, -3 HIP error, -7 no convergence (err says why)

@@ -56,8 +56,8 @@ class _Options(ctypes.Structure):
 class _EigStats(ctypes.Structure):
     _fields_ = [("outer_right", ctypes.c_int), ("outer_left", ctypes.c_int),
                 ("max_res_right", ctypes.c_double), ("max_res_left", ctypes.c_double),
-                ("max_biorth", ctypes.c_double), ("gmres_iters", ctypes.c_int),
-                ("max_gmres_res", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("max_biorth", ctypes.c_double), ("shift_iters", ctypes.c_int),
+                ("max_shift_res", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 class _Dir(ctypes.Structure):
