@@ -3,9 +3,12 @@ block matrix (eq. 6-7 of the paper), at 14 x 14^3, k = 400, mu = 0.3, on one
 MI355X, plus the Dw.v stencil bandwidth.
 
 One step = one call of ovd_sign_apply_deriv over a batch of `nrhs` synthetic
-(x, b) pairs in the storage-free scalar mode: k fused Lanczos steps on the GPU,
-sgn(T_k) e_1, and the scalar <x|d sgn(H) b> per pair.  Inputs are resident in
-HBM before the timed region.  value = derivative evaluations per second.
+(x, b) pairs in the storage-free scalar mode: the deflation projections of
+the m = 40 eigenpairs of smallest |lambda| (and the derivatives of the first
+6), k fused Lanczos steps on the GPU, sgn(T_k) e_1, and the scalar
+<x|d sgn(H) b> per pair.  The deflation set is computed on the GPU before the
+timed region (its time is reported separately); inputs are resident in HBM.
+value = derivative evaluations per second.
 
 Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -23,6 +26,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "d⟨x|sgn(H(μ))|b⟩/dμ evals/s at 14^4,k=400; Dw·v HBM GB/s vs peak"
+
+
+def progress(msg: str) -> None:
+    """One line on stderr per finished stage (long runs stay visibly alive)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def stencil_bytes_per_site(prec_bytes: int, nrhs: int) -> float:
@@ -81,20 +89,23 @@ def dwv_bytes_per_site(prec_bytes: int) -> float:
     return (12 + 36 + 12) * 2 * prec_bytes
 
 
-def time_form(args, U, prec, n, steps, warmup, V, step_timing=False):
+def time_form(args, U, prec, n, steps, warmup, V, step_timing=False, lat=None):
     """Time `steps` batched derivative evaluations of n sources at one precision.
 
     step_timing=False: the production path (the k Lanczos steps replayed as one
     HIP graph).  step_timing=True: launched one by one with HIP events around
-    every stencil and update kernel on the library's stream, for the roofline."""
+    every stencil and update kernel on the library's stream, for the roofline.
+    lat: a lattice already set up (links, deflation set), kept open."""
     import torch
 
     import synth
     from paper_1611_00195_amd import ovderiv
 
     dims = tuple(args.dims)
-    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, step_timing=step_timing)
-    lat.set_links(U)
+    own = lat is None
+    if own:
+        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, step_timing=step_timing)
+        lat.set_links(U)
     b = torch.from_numpy(synth.make_sources(dims, n, 4000)).cuda()
     x = torch.from_numpy(synth.make_sources(dims, n, 5000)).cuda()
     mus = [args.mu] * n
@@ -115,7 +126,8 @@ def time_form(args, U, prec, n, steps, warmup, V, step_timing=False):
     res.update(shapes=lat.tuned_shapes())
     res.update(evals_per_s=n * steps / dt, ms_per_step=1e3 * dt / steps, vals=vals,
                min_margin=lat.last_stats.min_margin, sign_check=lat.last_stats.sign_check)
-    lat.close()
+    if own:
+        lat.close()
     return res
 
 
@@ -133,7 +145,38 @@ def run_gpu(args):
     U = torch.from_numpy(Uh).cuda()
     prec = ovderiv.MIXED if args.precision == "mixed" else ovderiv.FP64
     n = args.nrhs
-    main = time_form(args, U, prec, n, args.steps, args.warmup, V)
+    # the headline workload: the m eigenpairs of smallest |lambda| deflated
+    # (eq. 8), the first l of them with their derivatives for the derivative
+    # (eq. 9-11); the set is computed on the GPU once, outside the timed region
+    defl = None
+    lat_d = None
+    if args.deflation > 0:
+        lat_d = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+        lat_d.set_links(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            lam, est = lat_d.compute_deflation(args.mu, args.deflation, args.defl_l)
+            torch.cuda.synchronize()
+            defl = {"m": args.deflation, "l": args.defl_l, "setup_s": round(time.perf_counter() - t0, 1),
+                    "lambda_min_max_abs": [float(abs(lam[0])), float(abs(lam[-1]))],
+                    "max_res": max(est["max_res_right"], est["max_res_left"]), "max_biorth": est["max_biorth"],
+                    "arnoldi_cycles": [est["outer_right"], est["outer_left"]], "shift_iters": est["shift_iters"],
+                    "max_shift_res": est["max_shift_res"]}
+            progress(f"deflation set m={args.deflation} l={args.defl_l} in {defl['setup_s']} s")
+        except Exception as e:   # no converged set: the undeflated run is the headline, and says why
+            defl = {"m": args.deflation, "l": args.defl_l, "error": str(e)}
+            lat_d.close()
+            lat_d = None
+    und = time_form(args, U, prec, n, args.steps, args.warmup, V)
+    progress(f"undeflated form: {und['evals_per_s']:.2f} evals/s")
+    main = und
+    if lat_d is not None:
+        main = time_form(args, U, prec, n, args.steps, args.warmup, V, lat=lat_d)
+        lat_d.close()
+        progress(f"deflated form: {main['evals_per_s']:.2f} evals/s")
+        defl["undeflated_evals_per_s"] = round(und["evals_per_s"], 3)
+        defl["max_rel_diff_xdy_vs_undeflated"] = max(abs(a - b) / abs(b) for a, b in zip(main["vals"], und["vals"]))
     # roofline: the same workload launched kernel by kernel with events
     prof = time_form(args, U, prec, n, max(1, min(args.steps, 2)), 0, V, step_timing=True)
     pb = 4 if prec == ovderiv.MIXED else 8
@@ -163,6 +206,8 @@ def run_gpu(args):
         "update_kernel": {"bytes_per_launch": up_bytes, "us_per_launch": round(up_ms * 1e3, 2),
                           "gbs": round(up_bytes / (up_ms * 1e-3) / 1e9, 1)},
         "xdy0": [main["vals"][0].real, main["vals"][0].imag],
+        "deflation": defl,
+        "deflated": lat_d is not None or (defl is not None and "error" not in defl),
         "min_margin": main["min_margin"],
         "sign_check": main["sign_check"],
     }
@@ -200,7 +245,9 @@ def run_gpu(args):
             "force": float(_t.linalg.vector_norm(Fr - F64) / _t.linalg.vector_norm(F64)),
         }
         out["vjp_recompute"] = vr
+        progress("gradient forms done")
         out["uneven"] = time_uneven(args)
+        progress("uneven batch done")
     # Dw.v bandwidth: nrhs fields per launch so that the traffic exceeds the 256 MB MALL
     nd = args.dwv_nrhs
     src = torch.from_numpy(synth.make_sources(dims, 1, 6000)).cuda().repeat(nd, 1, 1, 1).contiguous()
@@ -305,7 +352,10 @@ def time_uneven(args):
 
 def counters_run(args):
     """The workload of the committed counter summaries: the bench lattice and
-    sources, 8 right-hand sides, 20 Lanczos steps, FP64 then mixed."""
+    sources, 8 right-hand sides, 20 Lanczos steps, FP64 then mixed, in the
+    launch shape that the autotuner keeps for this workload in the bench
+    (XCD order 0, 2 groups per block, paired form; forced here because a
+    profiler that serialises every dispatch distorts the tuner's timings)."""
     import torch
 
     import synth
@@ -314,7 +364,7 @@ def counters_run(args):
     dims = tuple(args.dims)
     U = torch.from_numpy(synth.make_links(dims, args.eps, 1611)).cuda()
     for prec in (ovderiv.FP64, ovderiv.MIXED):
-        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, shape=(0, 2, 0))
         lat.set_links(U)
         b = torch.from_numpy(synth.make_sources(dims, 8, 4000)).cuda()
         x = torch.from_numpy(synth.make_sources(dims, 8, 5000)).cuda()
@@ -381,6 +431,10 @@ def main():
     ap.add_argument("--dims", type=int, nargs=4, default=[14, 14, 14, 14])
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--dwv-nrhs", type=int, default=48)
+    ap.add_argument("--deflation", type=int, default=40,
+                    help="eigenpairs of smallest |lambda| deflated (0: none); computed on the GPU before timing")
+    ap.add_argument("--defl-l", type=int, default=6,
+                    help="of those, the pairs whose derivatives enter the deflated derivative")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-forms", action="store_true")
@@ -413,17 +467,22 @@ def main():
         "config": {
             "workload": f"d<x|sgn(H(mu))|b>/dmu, two-sided Lanczos on the block matrix, "
                         f"{'x'.join(map(str, args.dims))} lattice, SU(3) links eps={args.eps}, m0={args.m0}, "
-                        f"mu={args.mu}, k={args.k}, no deflation, storage-free scalar mode",
+                        f"mu={args.mu}, k={args.k}, "
+                        + (f"m={args.deflation} eigenpairs deflated (generalised deflation of the first "
+                           f"{args.defl_l} for the derivative)" if g["deflated"] else "no deflation")
+                        + ", storage-free scalar mode",
             "lattice": args.dims,
             "k": args.k,
             "mu": args.mu,
             "nrhs_per_step": args.nrhs,
             "precision": args.precision,
-            "deflation": 0,
+            "deflation": args.deflation if g["deflated"] else 0,
+            "derivative_deflation_pairs": args.defl_l if g["deflated"] else 0,
         },
         "roofline": g["roofline"],
         "cpu_baseline": cpu,
         "detail": {
+            "deflation": g["deflation"],
             "ms_lanczos_per_step": round(g["ms_lanczos_per_step"], 3),
             "ms_small_sign_per_step": round(g["ms_small_sign_per_step"], 3),
             "update_kernel": g["update_kernel"],
