@@ -91,6 +91,9 @@ typedef struct {
                                live accumulators, twice the waves per SIMD in FP64), 0 the
                                paired form (both outputs at once, every link loaded once);
                                -1 (default): tuned, else paired */
+    int shape_rp;           /* ovd_apply_op with OVD_OP_H or OVD_OP_DW on an even number of
+                               right-hand sides: 2 forces two per thread (each link loaded
+                               once for both), 1 one per thread; 0 (default): tuned */
     int vjp_recompute;      /* ovd_sign_apply_vjp: 0 keeps both Krylov bases and Z (3 k FP64
                                fields); 1 keeps only the left basis, turned into Z in place,
                                and regenerates the right basis with a second, identical

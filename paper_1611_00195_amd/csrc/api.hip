@@ -162,11 +162,12 @@ StencilVariant autotune(ovd_h h, const std::vector<StencilVariant>& cands, Launc
 
 // a shape forced through the options, completed with defaults; false if none is forced
 bool forced_shape(ovd_h h, int nrhs, int def_gpb, StencilVariant* v) {
-    if (h->opt.shape_map < 0 && h->opt.shape_gpb <= 0 && h->opt.shape_seq < 0) return false;
+    if (h->opt.shape_map < 0 && h->opt.shape_gpb <= 0 && h->opt.shape_seq < 0 && h->opt.shape_rp <= 0) return false;
     v->map = h->opt.shape_map >= 0 ? h->opt.shape_map : default_map(nrhs);
     if (v->map == 0 && nrhs % 8 != 0) v->map = 1;
     v->gpb = h->opt.shape_gpb > 0 ? h->opt.shape_gpb : def_gpb;
     v->seq = h->opt.shape_seq > 0 ? 1 : 0;
+    v->rp = h->opt.shape_rp == 2 ? 2 : 1;
     return true;
 }
 
@@ -179,6 +180,22 @@ std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& g
         for (int gpb : gpbs) {
             c.push_back(StencilVariant{map, gpb, 0});
             if (seq_too && gpb != 8) c.push_back(StencilVariant{map, gpb, 1});
+        }
+    }
+    return c;
+}
+
+// Dw.v launch shapes: the stencil shapes, and for H and Dw on an even number
+// of right-hand sides each of them also with two right-hand sides per thread
+std::vector<StencilVariant> op_candidates(int nrhs, int op) {
+    std::vector<StencilVariant> c = shape_candidates(nrhs, {4, 2});
+    if ((op == 0 || op == 1) && nrhs % 2 == 0) {
+        const size_t n = c.size();
+        for (size_t i = 0; i < n; ++i) {
+            StencilVariant v = c[i];
+            v.rp = 2;
+            if (v.map == 0 && (nrhs / 2) % 8 != 0) continue;   // the XCD order over pairs
+            c.push_back(v);
         }
     }
     return c;
@@ -735,6 +752,7 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.shape_map = -1;
     h->opt.shape_gpb = 0;
     h->opt.shape_seq = -1;
+    h->opt.shape_rp = 0;
     h->opt.vjp_recompute = -1;
     if (opt) {
         h->opt = *opt;
@@ -823,9 +841,10 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
         if (forced_shape(h, nrhs, 4, &fv)) {
             if (fv.gpb != 2) fv.gpb = 4;
             fv.seq = 0;
+            if (!(op == 0 || op == 1) || nrhs % 2 != 0) fv.rp = 1;
             h->tuned[key] = fv;
         } else if (!h->tuned.count(key)) {
-            h->tuned[key] = h->opt.autotune ? autotune(h, shape_candidates(nrhs, {4, 2}), launch, [] {})
+            h->tuned[key] = h->opt.autotune ? autotune(h, op_candidates(nrhs, op), launch, [] {})
                                             : StencilVariant{default_map(nrhs), 4};
         }
         t.start(h->stream);
@@ -843,9 +862,10 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
         if (forced_shape(h, nrhs, 4, &fv)) {
             if (fv.gpb != 2) fv.gpb = 4;
             fv.seq = 0;
+            if (!(op == 0 || op == 1) || nrhs % 2 != 0) fv.rp = 1;
             h->tuned[key] = fv;
         } else if (!h->tuned.count(key)) {
-            h->tuned[key] = h->opt.autotune ? autotune(h, shape_candidates(nrhs, {4, 2}), launch, [] {})
+            h->tuned[key] = h->opt.autotune ? autotune(h, op_candidates(nrhs, op), launch, [] {})
                                             : StencilVariant{default_map(nrhs), 4};
         }
         t.start(h->stream);
@@ -959,7 +979,7 @@ ovd_status ovd_get_tuned(ovd_h h, char* buf, int len) {
     std::string out;
     for (const auto& kv : h->tuned)
         out += kv.first + "=map" + std::to_string(kv.second.map) + ",gpb" + std::to_string(kv.second.gpb) +
-               (kv.second.seq ? ",seq;" : ";");
+               (kv.second.seq ? ",seq" : "") + (kv.second.rp == 2 ? ",rp2;" : ";");
     std::strncpy(buf, out.c_str(), (size_t)len - 1);
     buf[len - 1] = 0;
     return OVD_OK;

@@ -417,12 +417,72 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_kernel(Geom g, const 
     store12(out + roff, s, Vp, acc);
 }
 
+// H or Dw on two right-hand sides per thread (OP 0 or 1): the link of every
+// hop is loaded once for both, through the paired hops of the Lanczos stencil
+// (pair r holds right-hand sides 2 r and 2 r + 1, each with its own mu).
+template <typename T, int DIR, bool PLANE>
+__device__ __forceinline__ void pair_hops(cpx<T> (&accA)[12], cpx<T> (&accB)[12], const cpx<T>* Af,
+                                          const cpx<T>* Bf, const cpx<T>* Wf, const cpx<T>* W2f, const Nbr& N, int s,
+                                          int Vp, T cfA, T cbA, T cfB, T cbB, T xfAB, T xbAB, T xfBA, T xbBA, int bc,
+                                          bool vside);
+
+template <typename T, int OP, int GPB>
+__global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_pair_kernel(Geom g, const double* __restrict__ emu,
+                                                            const cpx<T>* __restrict__ U, T mdiag,
+                                                            const cpx<T>* __restrict__ in,
+                                                            cpx<T>* __restrict__ out, int ngroups, int npairs,
+                                                            int map) {
+    static_assert(OP == 0 || OP == 1, "paired form: H or Dw");
+    const Work w = xcd_work(blockIdx.x, gridDim.x / npairs, npairs, map);
+    const int r0 = 2 * w.rhs;
+    const int grp = w.grp * GPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int s = grp * 64 + (threadIdx.x & 63);
+    if (grp >= ngroups || s >= g.V) return;
+    const int Vp = g.Vp;
+    const cpx<T>* A = in + (size_t)r0 * 12 * Vp;
+    const cpx<T>* B = A + (size_t)12 * Vp;
+    const T epA = T(emu[2 * r0]), emA = T(emu[2 * r0 + 1]);
+    const T epB = T(emu[2 * r0 + 2]), emB = T(emu[2 * r0 + 3]);
+    const Nbr N = neighbours(g, s);
+    cpx<T> accA[12], accB[12];
+    load12(A, s, Vp, accA);
+    load12(B, s, Vp, accB);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        accA[c] = mdiag * accA[c];
+        accB[c] = mdiag * accB[c];
+    }
+    const T z = T(0);
+    pair_hops<T, 0, false>(accA, accB, A, B, U, U, N, s, Vp, epA, emA, epB, emB, z, z, z, z, g.bc_t, true);
+    if (OP == 0) {
+#pragma unroll
+        for (int c = 6; c < 12; ++c) {   // gamma5
+            accA[c] = -accA[c];
+            accB[c] = -accB[c];
+        }
+    }
+    store12(out + (size_t)r0 * 12 * Vp, s, Vp, accA);
+    store12(out + (size_t)(r0 + 1) * 12 * Vp, s, Vp, accB);
+}
+
 template <typename T, int OP>
 static void launch_apply_op_v(const Geom& g, int nrhs, const double* d_emu, const cpx<T>* U, const cpx<T>* dU, T md,
                               const cpx<T>* in, cpx<T>* out, StencilVariant v, hipStream_t s) {
     const int ngroups = (g.V + 63) / 64;
     const int gpb = v.gpb == 2 ? 2 : 4;
     const int nq = ((ngroups + gpb - 1) / gpb + 7) / 8 * 8;   // blocks of gpb site groups, padded to 8
+    if constexpr (OP == 0 || OP == 1) {
+        if (v.rp == 2 && nrhs % 2 == 0) {
+            const int np = nrhs / 2;
+            const int map = (v.map == 0 && np % 8 != 0) ? 1 : v.map;
+            dim3 grid(nq * np), block(64 * gpb);
+            if (gpb == 2)
+                apply_op_pair_kernel<T, OP, 2><<<grid, block, 0, s>>>(g, d_emu, U, md, in, out, ngroups, np, map);
+            else
+                apply_op_pair_kernel<T, OP, 4><<<grid, block, 0, s>>>(g, d_emu, U, md, in, out, ngroups, np, map);
+            return;
+        }
+    }
     dim3 grid(nq * nrhs), block(64 * gpb);
     if (gpb == 2)
         apply_op_kernel<T, OP, 2><<<grid, block, 0, s>>>(g, d_emu, U, dU, md, in, out, ngroups, nrhs, v.map);
@@ -637,7 +697,7 @@ __device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12],
     }
 }
 
-template <typename T, int DIR, bool PLANE = false>
+template <typename T, int DIR, bool PLANE>
 __device__ __forceinline__ void pair_hops(cpx<T> (&accA)[12], cpx<T> (&accB)[12], const cpx<T>* Af,
                                           const cpx<T>* Bf, const cpx<T>* Wf, const cpx<T>* W2f, const Nbr& N, int s,
                                           int Vp, T cfA, T cbA, T cfB, T cbB, T xfAB, T xbAB, T xfBA, T xbBA, int bc,

@@ -141,6 +141,7 @@ struct StencilVariant {
     int map = -1;
     int gpb = 0;
     int seq = 0;   // 1: the two outputs of a pair one after the other (DIR 0/1, not the plane shape)
+    int rp = 1;    // Dw.v (H, Dw): right-hand sides per thread, 1 or 2 (2 needs an even count)
 };
 inline int default_map(int nrhs) { return (nrhs >= 16 && nrhs % 8 == 0) ? 0 : 1; }
 

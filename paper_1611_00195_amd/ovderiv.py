@@ -50,7 +50,7 @@ class _Options(ctypes.Structure):
                 ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
                 ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int), ("shape_seq", ctypes.c_int),
-                ("vjp_recompute", ctypes.c_int)]
+                ("shape_rp", ctypes.c_int), ("vjp_recompute", ctypes.c_int)]
 
 
 class _EigStats(ctypes.Structure):
@@ -175,6 +175,7 @@ class Lattice:
                        int(bool(autotune)), -1 if shape is None else int(shape[0]),
                        0 if shape is None else int(shape[1]),
                        -1 if shape is None or len(shape) < 3 else int(shape[2]),
+                       0 if shape is None or len(shape) < 4 else int(shape[3]),
                        -1 if vjp_recompute is None else int(bool(vjp_recompute)))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)

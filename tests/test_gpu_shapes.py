@@ -1,6 +1,6 @@
 """Every launch shape of the stencils (XCD work order x site groups per block x
-paired or sequential form), forced through the options, against the oracle;
-and the autotuner's choice."""
+paired or sequential form x one or two right-hand sides per thread of Dw.v),
+forced through the options, against the oracle; and the autotuner's choice."""
 import pytest
 
 import synth
@@ -11,7 +11,8 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.mark.parametrize("shape", [(0, 1), (0, 2), (1, 1), (1, 2), (0, 4), (1, 4), (0, 8), (1, 8),
-                                   (0, 1, 1), (0, 2, 1), (1, 1, 1), (1, 2, 1), (0, 4, 1), (1, 4, 1), (1, 8, 1)])
+                                   (0, 1, 1), (0, 2, 1), (1, 1, 1), (1, 2, 1), (0, 4, 1), (1, 4, 1), (1, 8, 1),
+                                   (0, 4, 0, 2), (1, 2, 0, 2)])
 def test_forced_shapes_deriv_and_sign(shape):
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, host, ops, print_case, rel
@@ -93,3 +94,27 @@ def test_sequential_and_paired_forms_against_oracle(prec):
             assert rel(ys[r], sref) < t_sign
             assert rel(dy[r], dref) < t_der
             assert abs(complex(s[r]) - sref_x) <= t_der * np.linalg.norm(xh[r]) * np.linalg.norm(dref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nrhs", [6, 5])
+def test_dwv_two_rhs_per_thread(prec, nrhs):
+    """Dw.v with two right-hand sides per thread (forced) against the oracle's
+    H and Dw, on a ragged lattice: 6 sources (3 pairs, the contiguous XCD order)
+    and 5 (odd: one per thread).  FP64 to 1e-14, FP32 to 1e-6."""
+    from paper_1611_00195_amd import ovderiv
+    from oracle import dirac
+    from gpu_helpers import dev, host, print_case, rel
+    dims, mu = (5, 3, 4, 3), 0.35
+    print_case(test="dwv_rp2", prec=prec, nrhs=nrhs, dims=dims)
+    U = synth.make_links(dims, 0.5, 911)
+    b = synth.make_sources(dims, nrhs, 912)
+    lat = ovderiv.Lattice(dims, precision=ovderiv.FP64 if prec == "fp64" else ovderiv.MIXED, shape=(0, 4, 0, 2))
+    lat.set_links(dev(U))
+    tol = 1e-14 if prec == "fp64" else 1e-6
+    for op, ref in ((ovderiv.OP_H, dirac.apply_h), (ovderiv.OP_DW, dirac.apply_dw)):
+        out = host(lat.apply_op(op, mu, dev(b)))
+        for r in range(nrhs):
+            assert rel(out[r], dirac.flat(ref(U, b[r].ravel(), dims, mu))) < tol, (op, r)
+    assert ("rp2" in lat.tuned_shapes()) == (nrhs % 2 == 0)
+    lat.close()
