@@ -7,7 +7,6 @@
 //                 single-shift (Wilkinson) QR iteration with Givens rotations
 //                 to complex Schur form T = Z^dag A Z, then back substitution
 //                 on T (Golub & Van Loan, Matrix Computations, ch. 7);
-//   cholesky_upper, inv_upper   G = R^dag R and R^{-1} (Cholesky QR);
 //   inverse       Gauss-Jordan with partial pivoting.
 // Host only; no device code.
 #pragma once
@@ -186,38 +185,6 @@ inline bool eig_general(int n, Mat A, std::vector<cd>& w, Mat& V) {
             for (int i = 0; i < n; ++i) V[(size_t)i * n + j] /= nrm;
     }
     return true;
-}
-
-// Hermitian positive definite G = R^dag R, R upper triangular.  false if not PD.
-inline bool cholesky_upper(int n, const Mat& G, Mat& R) {
-    R.assign((size_t)n * n, cd(0));
-    for (int j = 0; j < n; ++j) {
-        double d = G[(size_t)j * n + j].real();
-        for (int k = 0; k < j; ++k) d -= cabs2(R[(size_t)k * n + j]);
-        if (!(d > 0)) return false;
-        const double rjj = std::sqrt(d);
-        R[(size_t)j * n + j] = rjj;
-        for (int i = j + 1; i < n; ++i) {
-            cd t = G[(size_t)j * n + i];
-            for (int k = 0; k < j; ++k) t -= std::conj(R[(size_t)k * n + j]) * R[(size_t)k * n + i];
-            R[(size_t)j * n + i] = t / rjj;
-        }
-    }
-    return true;
-}
-
-// inverse of an upper triangular matrix
-inline Mat inv_upper(int n, const Mat& R) {
-    Mat X((size_t)n * n, cd(0));
-    for (int j = 0; j < n; ++j) {
-        X[(size_t)j * n + j] = 1.0 / R[(size_t)j * n + j];
-        for (int i = j - 1; i >= 0; --i) {
-            cd t = 0.0;
-            for (int k = i + 1; k <= j; ++k) t += R[(size_t)i * n + k] * X[(size_t)k * n + j];
-            X[(size_t)i * n + j] = -t / R[(size_t)i * n + i];
-        }
-    }
-    return X;
 }
 
 // general inverse (Gauss-Jordan, partial pivoting); false if singular
