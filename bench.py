@@ -281,12 +281,12 @@ def time_vjp(args, U, V, prec=0, recompute=False):
     from paper_1611_00195_amd import ovderiv
 
     dims = tuple(args.dims)
-    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, vjp_recompute=recompute)
+    lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, basis_recompute=recompute)
     lat.set_links(U)
     b = torch.from_numpy(synth.make_sources(dims, 1, 4000)).cuda()
     x = torch.from_numpy(synth.make_sources(dims, 1, 5000)).cuda()
     lat.sign_apply_vjp(x, b, args.mu, args.k, force=True, wirtinger=True)
-    assert lat.last_stats.vjp_recomputed == int(recompute)
+    assert lat.last_stats.basis_recomputed == int(recompute)
     torch.cuda.synchronize()
     reps = 2
     t0 = time.perf_counter()

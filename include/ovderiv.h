@@ -94,12 +94,15 @@ typedef struct {
     int shape_rp;           /* ovd_apply_op with OVD_OP_H or OVD_OP_DW on an even number of
                                right-hand sides: 2 forces two per thread (each link loaded
                                once for both), 1 one per thread; 0 (default): tuned */
-    int vjp_recompute;      /* ovd_sign_apply_vjp: 0 keeps both Krylov bases and Z (3 k FP64
-                               fields); 1 keeps only the left basis, turned into Z in place,
-                               and regenerates the right basis with a second, identical
-                               Lanczos run, C = min(k, 32) vectors at a time (k + 2C fields,
-                               twice the Lanczos time); -1 (default): recompute only when the
-                               stored form does not fit in the free device memory */
+    int basis_recompute;    /* calls that need a Krylov basis (vector outputs of
+                               ovd_sign_apply and ovd_sign_apply_deriv, the gradient of
+                               ovd_sign_apply_vjp): 0 stores it; 1 regenerates it with a
+                               second, identical Lanczos run, C = min(k, 32) vectors at a time
+                               through a ring of 2C fields, at twice the Lanczos time (vector
+                               outputs: no basis stored; gradient: only the left basis,
+                               turned into Z in place, k + 2C fields instead of 3k); -1
+                               (default): recompute only when the stored form does not fit in
+                               the free device memory */
 } ovd_options;
 
 typedef struct {
@@ -119,7 +122,7 @@ typedef struct {
     double ms_total;        /* device time of the whole call */
     double ms_stencil;      /* summed device time of the k stencil launches (HIP events) */
     double ms_update;       /* summed device time of the k - 1 three-term update launches */
-    int vjp_recomputed;     /* ovd_sign_apply_vjp: 1 if the right basis was regenerated */
+    int basis_recomputed;   /* 1 if the call regenerated its Krylov basis (see basis_recompute) */
 } ovd_stats;
 
 /* Create a handle for one lattice.  Sec. 4 lattices are Lt x Ls^3 (e.g. 14 x 14^3).

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <map>
 #include <type_traits>
 #include <string>
@@ -199,6 +200,27 @@ std::vector<StencilVariant> op_candidates(int nrhs, int op) {
         }
     }
     return c;
+}
+
+// Whether a call keeps its Krylov basis (need bytes) or regenerates it:
+// basis_recompute > 0 always regenerates, 0 never, < 0 when the stored basis
+// does not fit in the free device memory plus what the named workspaces
+// already hold.
+bool recompute_basis(ovd_h h, size_t need, std::initializer_list<const char*> held_names, ovd_status* st) {
+    if (h->opt.basis_recompute > 0) return true;
+    if (h->opt.basis_recompute == 0) return false;
+    size_t held = 0;
+    for (const char* n : held_names) {
+        auto it = h->ws.find(n);
+        if (it != h->ws.end()) held += it->second.second;
+    }
+    size_t fr = 0, tot = 0;
+    const hipError_t e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) {
+        *st = fail(h, OVD_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        return false;
+    }
+    return need > held + fr / 10 * 9;
 }
 
 // fill per-rhs coefficient vector coef[r][j] = delta[r][0] * c[r][j] / delta[r][j]
@@ -510,6 +532,38 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     return OVD_OK;
 }
 
+// The vector outputs without a stored basis: the Lanczos run again (same
+// kernels, launch shape and inputs, so the same right vectors) with the right
+// vectors in a ring of 2C per right-hand side; after every C steps the C
+// finished vectors are added into out0 (half 0) and out1 (half 1, nullable)
+// with the coefficients cf [nrhs][k].
+template <typename T>
+ovd_status reconstruct_two_pass(ovd_h h, int nrhs, int k, int dir, const double* mu, const cpx<T>* srcv,
+                                const cpx<T>* srcw, const cpx<T>* xp, const c64* cf, long long fsz, void* out0,
+                                void* out1) {
+    ovd_status wst = OVD_OK;
+    const Geom& g = h->g;
+    const int C = std::min(k, 32);
+    WS(ring, cpx<T>, "recon_ring", (size_t)nrhs * 2 * C * fsz);
+    WS(c2, c64, "ritz_c_pass2", (size_t)nrhs * k);
+    int done = 0;   // right vectors already added
+    const std::function<void(int, hipStream_t)> hook = [&](int j, hipStream_t stream) {
+        const int avail = j + 1;   // right vectors 1 .. j + 1 are final
+        if (avail - done < C && avail < k) return;
+        const int n = avail - done;
+        const cpx<T>* base = ring + (size_t)(done % (2 * C)) * fsz;   // done is a multiple of C: no wrap
+        if (out0) launch_reconstruct<T>(g, nrhs, n, base, (long long)2 * C * fsz, fsz, 0, cf + done, k, out0, stream,
+                                        done > 0);
+        if (out1) launch_reconstruct<T>(g, nrhs, n, base, (long long)2 * C * fsz, fsz, 1, cf + done, k, out1, stream,
+                                        done > 0);
+        done = avail;
+    };
+    ovd_status s = run_tsl<T>(h, nrhs, k, dir, mu, srcv, srcw, xp, ring, c2, nullptr, nullptr, 2 * C, &hook);
+    if (s != OVD_OK) return s;
+    if (done != k) return fail(h, OVD_EHIP, "the regenerated basis did not reach step k");
+    return OVD_OK;
+}
+
 template <typename T>
 ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const void* b, void* y, ovd_stats* stats) {
     ovd_status wst = OVD_OK;
@@ -520,7 +574,13 @@ ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const voi
     for (const auto& rn : runs)
         if (rn.set && rn.set->m > mmax) mmax = rn.set->m;
     WS(b64, c64, "stage_b", (size_t)nrhs * fsz);
-    WS(basis, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
+    const bool recompute = recompute_basis(h, sizeof(cpx<T>) * (size_t)nrhs * k * fsz, {"basis_v"}, &wst);
+    if (wst != OVD_OK) return wst;
+    cpx<T>* basis = nullptr;
+    if (!recompute) {
+        WS(bb, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
+        basis = bb;
+    }
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     WS(cf, c64, "ritz_coef", (size_t)nrhs * k);
     Timer tt;
@@ -558,7 +618,13 @@ ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const voi
     if (s != OVD_OK) return s;
     dim3 grid((k + 127) / 128, nrhs);
     make_coef_kernel<<<grid, 128, 0, h->stream>>>(k, h->last_co, c, cf);
-    launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, y, h->stream);
+    if (basis) {
+        launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, y, h->stream);
+    } else {
+        s = reconstruct_two_pass<T>(h, nrhs, k, 0, mu, src, src, nullptr, cf, fsz, y, nullptr);
+        if (s != OVD_OK) return s;
+        if (stats) stats->basis_recomputed = 1;
+    }
     if (mmax > 0) {
         HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * fsz, h->stream));
         for (const auto& rn : runs) {
@@ -599,9 +665,14 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
         xp = xb;
     }
     cpx<T>* basis = nullptr;
+    bool recompute = false;
     if (need_vec) {
-        WS(bb, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
-        basis = bb;
+        recompute = recompute_basis(h, sizeof(cpx<T>) * (size_t)nrhs * k * fsz, {"basis_v"}, &wst);
+        if (wst != OVD_OK) return wst;
+        if (!recompute) {
+            WS(bb, cpx<T>, "basis_v", (size_t)nrhs * k * fsz);
+            basis = bb;
+        }
     }
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     Timer tt;
@@ -651,8 +722,14 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
         WS(cf, c64, "ritz_coef", (size_t)nrhs * k);
         dim3 grid((k + 127) / 128, nrhs);
         make_coef_kernel<<<grid, 128, 0, h->stream>>>(k, h->last_co, c, cf);
-        if (dy) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, dy, h->stream);
-        if (y) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 1, cf, k, y, h->stream);
+        if (basis) {
+            if (dy) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 0, cf, k, dy, h->stream);
+            if (y) launch_reconstruct<T>(g, nrhs, k, basis, (long long)k * fsz, fsz, 1, cf, k, y, h->stream);
+        } else {
+            s = reconstruct_two_pass<T>(h, nrhs, k, dirk, mu, srcv, srcw, xp, cf, fsz, dy, y);
+            if (s != OVD_OK) return s;
+            if (stats) stats->basis_recomputed = 1;
+        }
         if (lmax > 0) {
             // exact part: top R (s d) + dR (s c), bottom R (s c)
             HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * half, h->stream));
@@ -753,7 +830,7 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.shape_gpb = 0;
     h->opt.shape_seq = -1;
     h->opt.shape_rp = 0;
-    h->opt.vjp_recompute = -1;
+    h->opt.basis_recompute = -1;
     if (opt) {
         h->opt = *opt;
         if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
@@ -1219,20 +1296,15 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     // stored form: both bases and Z (3 k FP64 fields, plus the two FP32 bases
     // in mixed precision); recompute form: the left basis only (turned into Z
     // in place), the right basis regenerated by a second, identical run
-    bool recompute = grad && h->opt.vjp_recompute > 0;
-    if (grad && h->opt.vjp_recompute < 0) {
+    bool recompute = false;
+    if (grad) {
         const size_t f64 = sizeof(c64) * fsz, f32 = sizeof(c32) * fsz;
         const size_t need = (size_t)3 * k * f64 + (mixed ? (size_t)2 * k * f32 : 0);
-        size_t held = 0;
-        for (const char* n : {"vjp_basis_v", "vjp_basis_w", "vjp_Z", "vjp_basis_v32", "vjp_basis_w32"}) {
-            auto it = h->ws.find(n);
-            if (it != h->ws.end()) held += it->second.second;
-        }
-        size_t fr = 0, tot = 0;
-        HIPCHK(hipMemGetInfo(&fr, &tot));
-        recompute = need > held + fr / 10 * 9;
+        recompute = recompute_basis(h, need, {"vjp_basis_v", "vjp_basis_w", "vjp_Z", "vjp_basis_v32", "vjp_basis_w32"},
+                                    &wst);
+        if (wst != OVD_OK) return wst;
     }
-    if (st) st->vjp_recomputed = recompute ? 1 : 0;
+    if (st) st->basis_recomputed = recompute ? 1 : 0;
     // bilinear two-sided Lanczos: right start b, left start x (FP64, or FP32
     // vectors for OVD_MIXED, widened to FP64 for the gradient)
     WS(bw, c64, "vjp_basis_w", (size_t)k * fsz);

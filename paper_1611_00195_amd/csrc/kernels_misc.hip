@@ -73,7 +73,7 @@ template void launch_unpack_spinor<float>(const Geom&, int, const c32*, long lon
 template <typename T>
 __global__ void reconstruct_kernel(Geom g, int k, const cpx<T>* __restrict__ basis, long long s_rhs,
                                    long long s_j, int half, const c64* __restrict__ coef, int coef_ld,
-                                   c64* __restrict__ out) {
+                                   c64* __restrict__ out, int accumulate) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (s >= g.V) return;
@@ -90,20 +90,21 @@ __global__ void reconstruct_kernel(Geom g, int k, const cpx<T>* __restrict__ bas
     }
     c64* dst = out + ((size_t)r * g.V + s) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[c] = acc[c];
+    for (int c = 0; c < 12; ++c) dst[c] = accumulate ? dst[c] + acc[c] : acc[c];
 }
 
 template <typename T>
 void launch_reconstruct(const Geom& g, int nrhs, int k, const cpx<T>* basis, long long s_rhs,
                         long long s_j, int half, const c64* coef, int coef_ld, void* out_aos,
-                        hipStream_t s) {
+                        hipStream_t s, bool accumulate) {
     dim3 grid((g.V + 255) / 256, nrhs);
-    reconstruct_kernel<T><<<grid, 256, 0, s>>>(g, k, basis, s_rhs, s_j, half, coef, coef_ld, (c64*)out_aos);
+    reconstruct_kernel<T><<<grid, 256, 0, s>>>(g, k, basis, s_rhs, s_j, half, coef, coef_ld, (c64*)out_aos,
+                                               accumulate ? 1 : 0);
 }
 template void launch_reconstruct<double>(const Geom&, int, int, const c64*, long long, long long, int,
-                                         const c64*, int, void*, hipStream_t);
+                                         const c64*, int, void*, hipStream_t, bool);
 template void launch_reconstruct<float>(const Geom&, int, int, const c32*, long long, long long, int,
-                                        const c64*, int, void*, hipStream_t);
+                                        const c64*, int, void*, hipStream_t, bool);
 
 // out[rhs] = scale[rhs] * sum_j c[rhs][j] proj[rhs][j], one block per rhs,
 // fixed summation order

@@ -176,11 +176,12 @@ void launch_small_frechet(int k, TslCoeffs co, double quad_step, c64* scratch, c
                           hipStream_t s);
 size_t small_frechet_scratch_elems(int k);
 
-// y = sum_j coef[rhs][j] * basis[rhs][j]  (top/bottom halves selected by half_off)
+// y = sum_j coef[rhs][j] * basis[rhs][j]  (top/bottom halves selected by half_off);
+// with accumulate, y += the sum (the basis taken a chunk of vectors at a time)
 template <typename T>
 void launch_reconstruct(const Geom& g, int nrhs, int k, const cpx<T>* basis, long long s_rhs,
                         long long s_j, int half, const c64* coef, int coef_ld, void* out_aos,
-                        hipStream_t s);
+                        hipStream_t s, bool accumulate = false);
 
 // scalar result: out[rhs] = scale[rhs] * sum_j c[rhs][j] * proj[rhs][j]
 void launch_scalar_dot(int nrhs, int k, const c64* c, const c64* proj, int ld,

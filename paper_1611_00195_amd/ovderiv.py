@@ -50,7 +50,7 @@ class _Options(ctypes.Structure):
                 ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
                 ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int), ("shape_seq", ctypes.c_int),
-                ("shape_rp", ctypes.c_int), ("vjp_recompute", ctypes.c_int)]
+                ("shape_rp", ctypes.c_int), ("basis_recompute", ctypes.c_int)]
 
 
 class _EigStats(ctypes.Structure):
@@ -68,7 +68,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("breakdown_step", ctypes.c_int), ("min_margin", ctypes.c_double),
                 ("sign_check", ctypes.c_double), ("ms_lanczos", ctypes.c_double),
                 ("ms_small_sign", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("ms_stencil", ctypes.c_double), ("ms_update", ctypes.c_double), ("vjp_recomputed", ctypes.c_int)]
+                ("ms_stencil", ctypes.c_double), ("ms_update", ctypes.c_double), ("basis_recomputed", ctypes.c_int)]
 
 
 class _Job(ctypes.Structure):
@@ -89,7 +89,7 @@ class Stats:
     ms_total: float
     ms_stencil: float
     ms_update: float
-    vjp_recomputed: int = 0
+    basis_recomputed: int = 0
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -161,7 +161,7 @@ class Lattice:
 
     def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
                  breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True,
-                 autotune=True, shape=None, vjp_recompute=None):
+                 autotune=True, shape=None, basis_recompute=None):
         self.dims = tuple(int(d) for d in dims)
         self.V = 1
         for d in self.dims:
@@ -176,7 +176,7 @@ class Lattice:
                        0 if shape is None else int(shape[1]),
                        -1 if shape is None or len(shape) < 3 else int(shape[2]),
                        0 if shape is None or len(shape) < 4 else int(shape[3]),
-                       -1 if vjp_recompute is None else int(bool(vjp_recompute)))
+                       -1 if basis_recompute is None else int(bool(basis_recompute)))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
@@ -211,7 +211,7 @@ class Lattice:
     @staticmethod
     def _stats(s):
         return Stats(s.k, s.breakdown_step, s.min_margin, s.sign_check, s.ms_lanczos, s.ms_small_sign, s.ms_total,
-                     s.ms_stencil, s.ms_update, s.vjp_recomputed)
+                     s.ms_stencil, s.ms_update, s.basis_recomputed)
 
     def _dir(self, direction, dU):
         if direction in (None, "mu", DIR_MU):
@@ -305,9 +305,9 @@ class Lattice:
         Returns (s, ds_dmu, F, dsdU, dsdUc); F = per-link force [4, V, 3, 3]
         (ds/dt = tr(F X) for U -> e^{tX} U) when force, and the Wirtinger
         derivatives ds/dU, ds/dconj(U) when wirtinger.  With grad=False only s
-        is computed (ds_dmu is None).  The handle's vjp_recompute chooses
+        is computed (ds_dmu is None).  The handle's basis_recompute chooses
         between keeping both Krylov bases and regenerating the right one
-        (last_stats.vjp_recomputed tells which ran)."""
+        (last_stats.basis_recomputed tells which ran)."""
         _check_field(x, (1, self.V, 4, 3), "x")
         _check_field(b, (1, self.V, 4, 3), "b")
         sc = (ctypes.c_double * 2)()

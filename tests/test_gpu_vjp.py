@@ -189,10 +189,10 @@ def test_vjp_recomputed_basis_matches_stored(prec, k):
     b = synth.make_source(dims, 543)
     out = {}
     for rc in (0, 1):
-        lat = ovderiv.Lattice(dims, precision=prec, vjp_recompute=bool(rc))
+        lat = ovderiv.Lattice(dims, precision=prec, basis_recompute=bool(rc))
         lat.set_links(dev(U))
         out[rc] = lat.sign_apply_vjp(dev(x[None]), dev(b[None]), MU, k, force=True, wirtinger=True)
-        assert lat.last_stats.vjp_recomputed == rc
+        assert lat.last_stats.basis_recomputed == rc
         lat.close()
     (s0, d0, F0, U0, C0), (s1, d1, F1, U1, C1) = out[0], out[1]
     assert abs(s1 - s0) <= 1e-13 * abs(s0)
@@ -214,4 +214,4 @@ def test_vjp_auto_mode_stores_when_memory_allows():
     lat = _lat(dims, U)
     x = synth.make_source(dims, 552)
     lat.sign_apply_vjp(dev(x[None]), dev(x[None]), MU, 16)
-    assert lat.last_stats.vjp_recomputed == 0
+    assert lat.last_stats.basis_recomputed == 0
