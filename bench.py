@@ -377,8 +377,10 @@ def counters_run(args):
 def run_cpu_baseline(args, nsteps):
     """The oracle, as it stands, on a bounded sample: `nsteps` of the k block
     Lanczos steps at the full lattice size plus one k x k Schur sign, scaled
-    to evaluations per second."""
+    to evaluations per second, with the BLAS/LAPACK thread pools held to one
+    thread (numpy's own loops are single-threaded), so one host core."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import synth
     from oracle import dirac, matfun, tsl
@@ -397,15 +399,16 @@ def run_cpu_baseline(args, nsteps):
     psi = np.concatenate([np.zeros(n, complex), b])
     phi = tsl.block_left_start(psi, n)
     xx = np.concatenate([x, np.zeros(n, complex)])
-    t0 = time.perf_counter()
-    tsl.lanczos(op, op_h, psi, phi, nsteps, keep_basis=False, proj=xx)
-    t_step = (time.perf_counter() - t0) / nsteps
     rng = np.random.default_rng(0)
     T = np.diag(rng.choice([-1, 1], args.k) * rng.uniform(0.5, 4, args.k) + 0.1j * rng.standard_normal(args.k))
     T = T + np.diag(0.3 * rng.standard_normal(args.k - 1), 1) + np.diag(0.3 * rng.standard_normal(args.k - 1), -1)
-    t1 = time.perf_counter()
-    matfun.sign_schur(T)
-    t_sign = time.perf_counter() - t1
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        tsl.lanczos(op, op_h, psi, phi, nsteps, keep_basis=False, proj=xx)
+        t_step = (time.perf_counter() - t0) / nsteps
+        t1 = time.perf_counter()
+        matfun.sign_schur(T)
+        t_sign = time.perf_counter() - t1
     t_eval = args.k * t_step + t_sign
     return {
         "value": 1.0 / t_eval,
@@ -413,7 +416,7 @@ def run_cpu_baseline(args, nsteps):
         "cores": 1,
         "kind": "oracle",
         "sample": f"{nsteps} of {args.k} block Lanczos steps at {'x'.join(map(str, dims))} "
-                  f"({t_step:.2f} s/step, single-threaded numpy) + one {args.k}x{args.k} Schur sign "
+                  f"({t_step:.2f} s/step, numpy and BLAS on one thread) + one {args.k}x{args.k} Schur sign "
                   f"({t_sign:.2f} s), scaled to one evaluation",
     }
 
@@ -435,7 +438,7 @@ def main():
                     help="eigenpairs of smallest |lambda| deflated (0: none); computed on the GPU before timing")
     ap.add_argument("--defl-l", type=int, default=6,
                     help="of those, the pairs whose derivatives enter the deflated derivative")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-forms", action="store_true")
     ap.add_argument("--counters-run", action="store_true",
