@@ -248,6 +248,20 @@ def run_gpu(args):
         progress("gradient forms done")
         out["uneven"] = time_uneven(args)
         progress("uneven batch done")
+    # achievable streaming bandwidth on this machine, for context beside the 8 TB/s
+    # spec: a 1 GiB device-to-device copy (1 GiB read + 1 GiB written)
+    src_c = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst_c = torch.empty_like(src_c)
+    dst_c.copy_(src_c)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst_c.copy_(src_c)
+    ev1.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = round(5 * 2 * (1 << 30) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+    del src_c, dst_c
     # Dw.v bandwidth: nrhs fields per launch so that the traffic exceeds the 256 MB MALL
     nd = args.dwv_nrhs
     src = torch.from_numpy(synth.make_sources(dims, 1, 6000)).cuda().repeat(nd, 1, 1, 1).contiguous()
@@ -489,6 +503,7 @@ def main():
             "ms_lanczos_per_step": round(g["ms_lanczos_per_step"], 3),
             "ms_small_sign_per_step": round(g["ms_small_sign_per_step"], 3),
             "update_kernel": g["update_kernel"],
+            "copy_1gib_gbs": g.get("copy_gbs"),
             "forms": g["forms"],
             "dw_v": g["dw_v"],
             "vjp": g.get("vjp"),
