@@ -131,6 +131,42 @@ def time_form(args, U, prec, n, steps, warmup, V, step_timing=False, lat=None):
     return res
 
 
+def mixed_accuracy(args, U, n, dset=None):
+    """Per-result error of the mixed-precision derivative against FP64 on the
+    benchmark's sources and links: sgn(H)b and d/dmu sgn(H)b as vectors
+    (relative 2-norm) and <x|dy> (relative, and relative to |x| |dy|), with
+    the deflation set dset = (lam, R, L, dR, dL) when given."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1611_00195_amd import ovderiv
+
+    dims = tuple(args.dims)
+    b = torch.from_numpy(synth.make_sources(dims, n, 4000)).cuda()
+    x = torch.from_numpy(synth.make_sources(dims, n, 5000)).cuda()
+    res = {}
+    for prec in (ovderiv.FP64, ovderiv.MIXED):
+        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec)
+        lat.set_links(U)
+        if dset is not None:
+            lam, R, L, dR, dL = dset
+            lat.set_deflation(args.mu, lam, R, L, 0 if dR is None else dR.shape[0], dR, dL)
+        y, dy, s = lat.sign_apply_deriv(b, [args.mu] * n, args.k, x=x)
+        lat.close()
+        res[prec] = (y.reshape(n, -1), dy.reshape(n, -1), np.array(s))
+    nrm = lambda a: torch.linalg.vector_norm(a, dim=-1).cpu().numpy()
+    (y6, dy6, s6), (y3, dy3, s3) = res[ovderiv.FP64], res[ovderiv.MIXED]
+    ey = nrm(y3 - y6) / nrm(y6)
+    ed = nrm(dy3 - dy6) / nrm(dy6)
+    es = np.abs(s3 - s6) / np.abs(s6)
+    en = np.abs(s3 - s6) / (nrm(x.reshape(n, -1)) * nrm(dy6))
+    return {"y_rel_max": float(ey.max()), "dy_rel_max": float(ed.max()),
+            "dy_rel_median": float(np.median(ed)), "xdy_rel_max": float(es.max()),
+            "xdy_err_over_x_dy_max": float(en.max()),
+            "dy_rel_per_source": [float("%.2e" % v) for v in ed]}
+
+
 def run_gpu(args):
     import numpy as np
     import torch
@@ -173,6 +209,7 @@ def run_gpu(args):
     main = und
     if lat_d is not None:
         main = time_form(args, U, prec, n, args.steps, args.warmup, V, lat=lat_d)
+        dset = lat_d.get_deflation(args.mu) if not args.skip_forms else None
         lat_d.close()
         progress(f"deflated form: {main['evals_per_s']:.2f} evals/s")
         defl["undeflated_evals_per_s"] = round(und["evals_per_s"], 3)
@@ -227,6 +264,14 @@ def run_gpu(args):
             "mixed_vs_fp64_max_rel_err_xdy": err,
         }
     out["forms"] = forms
+    if not args.skip_forms:
+        # vector-level accuracy of the mixed form, undeflated and with the set
+        acc = {"undeflated": mixed_accuracy(args, U, n)}
+        if lat_d is not None:
+            acc["deflated"] = mixed_accuracy(args, U, n, dset)
+            del dset
+        out["mixed_accuracy"] = acc
+        progress("mixed accuracy done")
     if not args.skip_forms:
         out["vjp"] = time_vjp(args, U, V)
         vm = time_vjp(args, U, V, prec=ovderiv.MIXED)
@@ -505,6 +550,7 @@ def main():
             "update_kernel": g["update_kernel"],
             "copy_1gib_gbs": g.get("copy_gbs"),
             "forms": g["forms"],
+            "mixed_vs_fp64": g.get("mixed_accuracy"),
             "dw_v": g["dw_v"],
             "vjp": g.get("vjp"),
             "vjp_mixed": g.get("vjp_mixed"),

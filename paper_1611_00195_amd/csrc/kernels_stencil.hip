@@ -542,6 +542,10 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* [16
 // with X = A vhat_j, Y = vhat_j, Z = vhat_{j-1} (all unnormalised; the
 // coefficients fold in the normalisations, see the stencil kernel below).
 // blockIdx.z = side (0: v, 1: w); NT = number of terms (2 on the first update).
+// The arithmetic is FP64 for either storage type, with the single rounding at
+// the store: FP32 vectors then follow the FP64 recurrence coefficients of T_k
+// up to that one rounding, instead of coefficients rounded to FP32 and three
+// FP32 products and sums.  The kernel is HBM-bound; FP64 costs nothing here.
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n_elem,
@@ -550,18 +554,18 @@ __global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n
     const TslState* S = st + rhs;
     if (S->flag) return;
     const bool vside = blockIdx.z == 0;
-    const cpx<T> a = cast<T>(vside ? S->av : S->aw);
-    const cpx<T> b = cast<T>(vside ? S->bv : S->bw);
-    const cpx<T> c = cast<T>(vside ? S->cv : S->cw);
+    const c64 a = vside ? S->av : S->aw;
+    const c64 b = vside ? S->bv : S->bw;
+    const c64 c = vside ? S->cv : S->cw;
     const cpx<T>* X = vside ? (const cpx<T>*)p.Xv + rhs * p.sXv : (const cpx<T>*)p.Xw + rhs * p.sXw;
     const cpx<T>* Y = vside ? (const cpx<T>*)p.Yv + rhs * p.sYv : (const cpx<T>*)p.Yw + rhs * p.sYw;
     const cpx<T>* Z = vside ? (const cpx<T>*)p.Zv + rhs * p.sZv : (const cpx<T>*)p.Zw + rhs * p.sZw;
     cpx<T>* O = vside ? (cpx<T>*)p.outV + rhs * p.sV : (cpx<T>*)p.outW + rhs * p.sW;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
-        cpx<T> r = a * X[e] + b * Y[e];
-        if constexpr (NT == 3) r += c * Z[e];
-        O[e] = r;
+        c64 r = a * cast<double>(X[e]) + b * cast<double>(Y[e]);
+        if constexpr (NT == 3) r += c * cast<double>(Z[e]);
+        O[e] = cast<T>(r);
     }
 }
 
