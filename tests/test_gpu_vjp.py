@@ -2,8 +2,9 @@
 
 Same-k parity against the oracle's Krylov VJP (same two-sided Lanczos, Frechet
 derivative of sgn(T_k) by the Schur-Sylvester block method), convergence to
-the dense gradient at large k, and the autograd wrapper against central
-finite differences of the oracle's dense <x|sgn(H)|b>.
+the dense gradient at large k, the autograd wrapper against central
+finite differences of the oracle's dense <x|sgn(H)|b>, and
+torch.autograd.gradcheck of the wrapper at a converged k.
 """
 import numpy as np
 import pytest
@@ -125,6 +126,36 @@ def test_autograd_against_oracle_and_finite_differences():
     eb = cn(*b.shape)
     check(np.sum(np.conj(host(bt.grad)) * eb).real, (c * np.vdot(Sx, eb.ravel())).real,
           (L(U, MU, x, b + h * eb) - L(U, MU, x, b - h * eb)) / (2 * h))
+
+
+def test_autograd_gradcheck():
+    """torch.autograd.gradcheck of sign_bilinear on 2^4 (complex output: real
+    and imaginary parts checked separately), over U, mu, x and b together.
+    At k = 160 the Krylov value has converged (1e-12 against the dense sign),
+    so central differences of the forward are the exact gradient, which the
+    library's VJP reproduces to ~1e-7 (test_vjp_converges_to_dense).  Fast
+    mode: random projections u, v of the Jacobian, v^T J u numerically and
+    analytically."""
+    from paper_1611_00195_amd import ovderiv
+    from paper_1611_00195_amd.functional import sign_bilinear
+    from gpu_helpers import dev, print_case
+    dims, k = (2, 2, 2, 2), 160
+    print_case(test="vjp_gradcheck", dims=dims, k=k)
+    torch.manual_seed(524)
+    U = synth.make_links(dims, 0.5, 521)
+    x = synth.make_source(dims, 522)
+    b = synth.make_source(dims, 523)
+    lat = ovderiv.Lattice(dims)
+    inputs = (dev(U).requires_grad_(), torch.tensor(MU, dtype=torch.float64, requires_grad=True),
+              dev(x).requires_grad_(), dev(b).requires_grad_())
+
+    def fn(U_, mu_, x_, b_):
+        return sign_bilinear(lat, U_, mu_, x_, b_, k)
+
+    # eps = 1e-5 keeps the rounding noise of the converged forward (~1e-12)
+    # below 1e-7 in the difference quotients
+    assert torch.autograd.gradcheck(fn, inputs, eps=1e-5, atol=1e-5, rtol=1e-3, fast_mode=True)
+    lat.close()
 
 
 def test_vjp_dsdmu_agrees_with_block_derivative():
