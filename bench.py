@@ -254,12 +254,14 @@ def run_gpu(args):
     if not args.skip_forms:
         other = ovderiv.FP64 if prec == ovderiv.MIXED else ovderiv.MIXED
         single = time_form(args, U, ovderiv.FP64, 1, max(1, args.steps // 2), 1, V)
+        msingle = time_form(args, U, ovderiv.MIXED, 1, max(1, args.steps // 2), 1, V)
         oth = time_form(args, U, other, n, max(1, args.steps // 2), 1, V)
         ref = main["vals"] if prec == ovderiv.FP64 else oth["vals"]
         mix = oth["vals"] if prec == ovderiv.FP64 else main["vals"]
         err = max(abs(a - b) / abs(b) for a, b in zip(mix, ref))
         forms = {
             "fp64_single_evals_per_s": round(single["evals_per_s"], 3),
+            "mixed_single_evals_per_s": round(msingle["evals_per_s"], 3),
             ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}_evals_per_s": round(oth["evals_per_s"], 3),
             "mixed_vs_fp64_max_rel_err_xdy": err,
         }
