@@ -63,8 +63,9 @@ enum { OVD_OP_H = 0, OVD_OP_DW = 1, OVD_OP_DH_DMU = 2, OVD_OP_DH_DLINK = 3 };
 
 typedef struct {
     int precision;          /* OVD_FP64 (default) or OVD_MIXED: FP32 vectors, links and
-                               stencil arithmetic; FP64 inner products, Lanczos scalars,
-                               T_k, sgn(T_k) and deflation */
+                               stencil arithmetic; the three-term update in FP64 with one
+                               rounding at the FP32 store; FP64 inner products, Lanczos
+                               scalars, T_k, sgn(T_k) and deflation */
     int left_start;         /* left start of the block system, see ovd_sign_apply_deriv */
     double breakdown_tol;   /* tau, default 1e-14 */
     double quad_step;       /* first refined step of the trapezoidal rule in log(y) used for
