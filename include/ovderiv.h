@@ -47,7 +47,9 @@ typedef struct ovd_lattice* ovd_h;
 
 typedef enum {
     OVD_OK = 0,
-    OVD_EINVAL = -1,      /* bad argument (sizes, null pointers, unsupported r, ...) */
+    OVD_EINVAL = -1,      /* bad argument (sizes, null pointers, unsupported r, ...); every
+                             batched call needs nrhs >= 1 and k >= 1, and an empty batch is
+                             rejected before any device work */
     OVD_ENOMEM = -2,      /* device allocation failed */
     OVD_EHIP = -3,        /* a HIP runtime call failed */
     OVD_EBREAKDOWN = -4,  /* serious Lanczos breakdown: |w^dag v| <= tau |w| |v| */

@@ -156,6 +156,30 @@ def test_zero_source_is_an_error():
         lat.sign_apply(dev(b), 0.3, 8)
 
 
+def test_empty_batch_and_zero_k_are_errors():
+    """An empty batch (nrhs = 0) and k = 0 are rejected (OVD_EINVAL) before
+    any device work, for the sign and the derivative; the handle stays usable."""
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims = (2, 2, 2, 2)
+    print_case(test="empty_batch", dims=dims)
+    U, lat = _setup(dims, 0.5, 219)
+    empty = torch.zeros((0, 16, 4, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(ovderiv.OvdError) as e:
+        lat.sign_apply(empty, 0.3, 8)
+    assert e.value.status == -1
+    with pytest.raises(ovderiv.OvdError) as e:
+        lat.sign_apply_deriv(empty, 0.3, 8)
+    assert e.value.status == -1
+    b = synth.make_sources(dims, 1, 220)
+    with pytest.raises(ovderiv.OvdError) as e:
+        lat.sign_apply(dev(b), 0.3, 0)
+    assert e.value.status == -1
+    h, hd, _, _ = ops(U, dims, 0.3)
+    ref, _ = tsl.krylov_sign(h, hd, b[0].ravel(), b[0].ravel(), 8)
+    assert rel(host(lat.sign_apply(dev(b), 0.3, 8))[0], ref) < 1e-10
+
+
 def test_left_same_breaks_down_or_diverges():
     """Left start psi for the block system: an error or a useless derivative, never a hang."""
     from paper_1611_00195_amd import ovderiv
