@@ -78,6 +78,24 @@ __global__ void lincomb_kernel(long long n_elem, c64 a, const c64* __restrict__ 
     }
 }
 
+// out = X + f Y with f = sgn num / den from device scalars, so that a CG step
+// needs no host round trip (f = 0 when den = 0); X and out may be the same
+__global__ void axpy_ratio_kernel(long long n_elem, const c64* X, double sgn, const c64* __restrict__ num,
+                                  const c64* __restrict__ den, const c64* __restrict__ Y, c64* out) {
+    const c64 a = *num, b = *den;
+    const double bb = b.re * b.re + b.im * b.im;
+    const c64 f = bb > 0 ? c64{sgn * (a.re * b.re + a.im * b.im) / bb, sgn * (a.im * b.re - a.re * b.im) / bb}
+                         : c64{0.0, 0.0};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+        const c64 y = Y[e];
+        c64 r = X[e];
+        r.re += f.re * y.re - f.im * y.im;
+        r.im += f.re * y.im + f.im * y.re;
+        out[e] = r;
+    }
+}
+
 namespace {
 
 // progress lines on stderr when OVDERIV_VERBOSE is set (long setup runs)
@@ -102,9 +120,16 @@ struct Ctx {
     size_t scr_elems = 0;
     c64* small = nullptr;    // device staging of small matrices
     size_t small_elems = 0;
-    double* emu = nullptr;   // device (e^{m}, e^{-m}) per field, 2 x max fields
-    int emu_n = 0;
-    double emu_mu = 1e300;
+    // device tables (e^{mu}, e^{-mu}) per field for the two values of mu used
+    // last: a solve alternates H(mu) and H(-mu) = H(mu)^dag, which then costs
+    // no upload and no wait inside its iterations
+    struct MuTable {
+        double mu = 1e300;
+        int n = 0;
+        double* d = nullptr;
+    };
+    MuTable mu_tab[2];
+    int mu_next = 0;
 
     ~Ctx() {
         for (void* p : owned) (void)hipFree(p);
@@ -149,31 +174,35 @@ struct Ctx {
         small_elems = n;
         return true;
     }
-    // (e^{mu}, e^{-mu}) for n fields
-    bool set_mu(double mu, int n) {
-        if (mu == emu_mu && n <= emu_n) return true;
-        const int cap = std::max(n, emu_n);
-        if (cap > emu_n) {
+    // the table of mu for n fields (built on first use; one of two slots)
+    const double* mu_table(double mu, int n) {
+        for (const MuTable& t : mu_tab)
+            if (t.d && t.mu == mu && n <= t.n) return t.d;
+        MuTable& t = mu_tab[mu_next];
+        mu_next ^= 1;
+        if (n > t.n) {
             void* p = nullptr;
-            if (!ok(hipMalloc(&p, sizeof(double) * 2 * cap), "hipMalloc")) return false;
+            if (!ok(hipMalloc(&p, sizeof(double) * 2 * n), "hipMalloc")) return nullptr;
             owned.push_back(p);
-            emu = (double*)p;
-            emu_n = cap;
+            t.d = (double*)p;
+            t.n = n;
         }
-        std::vector<double> h(2 * (size_t)emu_n);
-        for (int i = 0; i < emu_n; ++i) {
+        std::vector<double> h(2 * (size_t)t.n);
+        for (int i = 0; i < t.n; ++i) {
             h[2 * i] = std::exp(mu);
             h[2 * i + 1] = std::exp(-mu);
         }
-        if (!ok(hipMemcpyAsync(emu, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s), "copy"))
-            return false;
-        if (!ok(hipStreamSynchronize(s), "sync")) return false;
-        emu_mu = mu;
-        return true;
+        // stream-ordered after every launch that read the slot's previous table
+        if (!ok(hipMemcpyAsync(t.d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s), "copy"))
+            return nullptr;
+        if (!ok(hipStreamSynchronize(s), "sync")) return nullptr;   // h is released on return
+        t.mu = mu;
+        return t.d;
     }
     // out = op(mu) in, n fields (op: 0 H, 2 dH/dmu, 3 dH/dlink)
     bool apply(int op, double mu, const c64* in, c64* out, int n) {
-        if (!set_mu(mu, n)) return false;
+        const double* emu = mu_table(mu, n);
+        if (!emu) return false;
         launch_apply_op<double>(g, op, n, emu, U, dU, md, in, out, s);
         return ok(hipGetLastError(), "apply_op");
     }
@@ -199,6 +228,36 @@ struct Ctx {
         lincomb_kernel<<<(unsigned)nb, 256, 0, s>>>(n_elem, c64{a.real(), a.imag()}, X, c64{b.real(), b.imag()}, Y,
                                                    c64{c.real(), c.imag()}, Z, out);
         return ok(hipGetLastError(), "lincomb");
+    }
+    // dst (device, one complex) = x^dag y, left on the device
+    bool dot_dev(const c64* x, const c64* y, c64* dst) {
+        if (!ensure_scratch(1, 1)) return false;
+        launch_defl_proj(x, nf, 1, y, nf, 1, nf, dst, scr, s);
+        return ok(hipGetLastError(), "defl_proj");
+    }
+    bool axpy_ratio(const c64* X, double sgn, const c64* num, const c64* den, const c64* Y, c64* out) {
+        long long nb = (nf + 255) / 256;
+        if (nb > 8192) nb = 8192;
+        axpy_ratio_kernel<<<(unsigned)nb, 256, 0, s>>>(nf, X, sgn, num, den, Y, out);
+        return ok(hipGetLastError(), "axpy_ratio");
+    }
+    // host copy of a device scalar (waits for the stream)
+    bool read_scalar(const c64* src, cd& out) {
+        c64 v{};
+        if (!ok(hipMemcpyAsync(&v, src, sizeof(c64), hipMemcpyDeviceToHost, s), "copy")) return false;
+        if (!ok(hipStreamSynchronize(s), "sync")) return false;
+        out = cd(v.re, v.im);
+        return true;
+    }
+    // three device scalars for the CG recurrence
+    c64* cg_sc = nullptr;
+    c64* cg_scalars() {
+        if (cg_sc) return cg_sc;
+        void* p = nullptr;
+        if (!ok(hipMalloc(&p, 3 * sizeof(c64)), "hipMalloc")) return nullptr;
+        owned.push_back(p);
+        cg_sc = (c64*)p;
+        return cg_sc;
     }
     bool copy(c64* dst, const c64* src, int n) {
         return ok(hipMemcpyAsync(dst, src, sizeof(c64) * (size_t)n * nf, hipMemcpyDeviceToDevice, s), "copy");
@@ -232,37 +291,36 @@ void sort_by_modulus_desc(int p, std::vector<cd>& w, std::vector<cd>& S) {
 }
 
 // z = H(mu)^{-1} v by conjugate gradients on the normal equations
-// H^dag H z = H^dag v (H^dag = H(-mu)); r, d, q, t: work fields
+// H^dag H z = H^dag v (H^dag = H(-mu)); r, d, q, t: work fields.  The CG
+// scalars stay on the device; the residual is read every kCgCheck iterations,
+// so a solve may run up to kCgCheck - 1 iterations past the tolerance.
+constexpr int kCgCheck = 8;
 bool solve_h(Ctx& c, double mu, const c64* v, c64* z, c64* r, c64* d, c64* q, c64* t, double tol, int max_it,
              long long& iters) {
-    auto dot = [&](const c64* x, const c64* y, cd& out) -> bool {
-        std::vector<cd> o;
-        if (!c.proj(x, 1, y, 1, o)) return false;
-        out = o[0];
-        return true;
-    };
+    c64* sc = c.cg_scalars();
+    if (!sc) return false;
+    c64 *rr = sc, *qq = sc + 1, *rn = sc + 2;
     if (!c.ok(hipMemsetAsync(z, 0, sizeof(c64) * c.nf, c.s), "memset")) return false;
     if (!c.apply(0, -mu, v, r, 1)) return false;   // r = H^dag v (z = 0)
     if (!c.copy(d, r, 1)) return false;
-    cd rr;
-    if (!dot(r, r, rr)) return false;
-    const double r0 = std::sqrt(rr.real());
+    cd h;
+    if (!c.dot_dev(r, r, rr) || !c.read_scalar(rr, h)) return false;
+    const double r0 = std::sqrt(h.real());
     if (!(r0 > 0)) return true;
     for (int it = 0; it < max_it; ++it) {
         if (!c.apply(0, mu, d, q, 1) || !c.apply(0, -mu, q, t, 1)) return false;   // t = H^dag H d
-        cd qq;
-        if (!dot(q, q, qq)) return false;
-        const cd alpha = rr / qq;
-        if (!c.lincomb(c.nf, 1.0, z, alpha, d, 0.0, nullptr, z)) return false;
-        if (!c.lincomb(c.nf, 1.0, r, -alpha, t, 0.0, nullptr, r)) return false;
-        cd rn;
-        if (!dot(r, r, rn)) return false;
+        if (!c.dot_dev(q, q, qq)) return false;
+        if (!c.axpy_ratio(z, 1.0, rr, qq, d, z) || !c.axpy_ratio(r, -1.0, rr, qq, t, r)) return false;
+        if (!c.dot_dev(r, r, rn)) return false;
         ++iters;
-        if (std::sqrt(rn.real()) <= tol * r0) break;
-        if (!c.lincomb(c.nf, 1.0, r, rn / rr, d, 0.0, nullptr, d)) return false;
-        rr = rn;
+        if ((it + 1) % kCgCheck == 0 || it + 1 == max_it) {
+            if (!c.read_scalar(rn, h)) return false;
+            if (std::sqrt(std::max(0.0, h.real())) <= tol * r0) break;
+        }
+        if (!c.axpy_ratio(r, 1.0, rn, rr, d, d)) return false;
+        std::swap(rr, rn);   // stream order: the next dot overwrites the old rr after this step's reads
     }
-    return true;
+    return c.ok(hipStreamSynchronize(c.s), "sync");
 }
 
 // One side (mu, or -mu for the left vectors): the m eigenpairs of H(mu) of
