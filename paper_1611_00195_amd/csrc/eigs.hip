@@ -486,71 +486,107 @@ bool arnoldi_side(Ctx& c, double mu, int m, int n, double tol, int max_cycles, u
     return true;
 }
 
-// (shift - A) z = rhs on the range of 1 - P (P = sum R_i L_i^dag; adjoint
-// side: A^dag = H(-mu), P^dag = sum L_i R_i^dag), solved as op z = rhs with
-// op = shift (1 - P) - A (1 - P) + P by CGLS: conjugate gradients on the
-// normal equations op^dag op z = op^dag rhs with the residual rhs - op z kept
-// explicitly.  The shift sits inside the spectrum of A (an interior
-// eigenvalue), so op is indefinite with a small gap; CGLS converges
-// monotonically there, where restarted GMRES stalls.  z in Z.
-bool cgls_shifted(Ctx& c, double mu, bool adjoint, cd shift, const c64* Rv, const c64* Lv, int m, const c64* rhs,
-                  c64* Z, double tol, int max_it, int& iters, double& relres) {
+// (shift_j - A) z_j = rhs_j, j < nr, on the range of 1 - P (P = sum R_i L_i^dag;
+// adjoint side: A^dag = H(-mu), P^dag = sum L_i R_i^dag), each solved as
+// op_j z = rhs_j with op_j = shift_j (1 - P) - A (1 - P) + P by CGLS: conjugate
+// gradients on the normal equations op_j^dag op_j z = op_j^dag rhs_j with the
+// residual rhs_j - op_j z kept explicitly.  The shift sits inside the spectrum
+// of A (an interior eigenvalue), so op_j is indefinite with a small gap; CGLS
+// converges monotonically there, where restarted GMRES stalls.  The nr systems
+// run side by side, each with its own CGLS scalars, so that one pass over the m
+// projector vectors serves all of them; a converged system is left as it is.
+// rhs, Z: nr fields; iters, relres: per system.
+bool cgls_shifted(Ctx& c, double mu, bool adjoint, const std::vector<cd>& shift, const c64* Rv, const c64* Lv, int m,
+                  const c64* rhs, c64* Z, double tol, int max_it, std::vector<int>& iters,
+                  std::vector<double>& relres) {
+    const int nr = (int)shift.size();
     const c64* Pa = adjoint ? Rv : Lv;   // P z = Pb (Pa^dag z), P^dag y = Pa (Pb^dag y)
     const c64* Pb = adjoint ? Lv : Rv;
     const double amu = adjoint ? -mu : mu;
-    c64* W = c.reuse(6);
+    c64* W = c.reuse(6 * nr);
     if (!W) return false;
-    c64 *r = W, *s = W + c.nf, *p = W + 2 * c.nf, *q = W + 3 * c.nf, *u = W + 4 * c.nf, *t = W + 5 * c.nf;
-    // out = op(zin): u = (1 - P) zin, out = shift u - A u + (zin - u)
+    const long long blk = (long long)nr * c.nf;
+    c64 *r = W, *s = W + blk, *p = W + 2 * blk, *q = W + 3 * blk, *u = W + 4 * blk, *t = W + 5 * blk;
+    auto col = [&](c64* x, int j) { return x + (size_t)j * c.nf; };
+    auto ccol = [&](const c64* x, int j) { return x + (size_t)j * c.nf; };
+    // squared 2-norms of the nr columns of x
+    auto norms2 = [&](const c64* x, std::vector<double>& n2) -> bool {
+        std::vector<cd> G;
+        if (!c.proj(x, nr, x, nr, G)) return false;
+        n2.resize(nr);
+        for (int j = 0; j < nr; ++j) n2[j] = std::max(0.0, G[(size_t)j * nr + j].real());
+        return true;
+    };
+    // out = op(zin): u = (1 - P) zin, out_j = shift_j u_j - A u_j + (zin_j - u_j)
     auto op = [&](const c64* zin, c64* out) -> bool {
         std::vector<cd> pc;
-        if (!c.proj(Pa, m, zin, 1, pc)) return false;
-        if (!c.copy(u, zin, 1)) return false;
+        if (!c.proj(Pa, m, zin, nr, pc)) return false;
+        if (!c.copy(u, zin, nr)) return false;
         for (auto& v : pc) v = -v;
-        if (!c.comb(Pb, m, pc, 1, u)) return false;
-        if (!c.apply(0, amu, u, out, 1)) return false;
-        return c.lincomb(c.nf, shift - 1.0, u, -1.0, out, 1.0, zin, out);
+        if (!c.comb(Pb, m, pc, nr, u)) return false;
+        if (!c.apply(0, amu, u, out, nr)) return false;
+        for (int j = 0; j < nr; ++j)
+            if (!c.lincomb(c.nf, shift[j] - 1.0, ccol(u, j), -1.0, ccol(out, j), 1.0, ccol(zin, j), col(out, j)))
+                return false;
+        return true;
     };
-    // out = op^dag(y) = (1 - P^dag)(conj(shift) y - A^dag y) + P^dag y = t + Pa (Pb^dag (y - t))
+    // out = op_j^dag(y) = (1 - P^dag)(conj(shift_j) y - A^dag y) + P^dag y = t + Pa (Pb^dag (y - t))
     auto opd = [&](const c64* y, c64* out) -> bool {
-        if (!c.apply(0, -amu, y, t, 1)) return false;
-        if (!c.lincomb(c.nf, std::conj(shift), y, -1.0, t, 0.0, nullptr, t)) return false;
-        if (!c.lincomb(c.nf, 1.0, y, -1.0, t, 0.0, nullptr, u)) return false;
+        if (!c.apply(0, -amu, y, t, nr)) return false;
+        for (int j = 0; j < nr; ++j)
+            if (!c.lincomb(c.nf, std::conj(shift[j]), ccol(y, j), -1.0, ccol(t, j), 0.0, nullptr, col(t, j)))
+                return false;
+        if (!c.lincomb(blk, 1.0, y, -1.0, t, 0.0, nullptr, u)) return false;
         std::vector<cd> pc;
-        if (!c.proj(Pb, m, u, 1, pc)) return false;
-        if (!c.copy(out, t, 1)) return false;
-        return c.comb(Pa, m, pc, 1, out);
+        if (!c.proj(Pb, m, u, nr, pc)) return false;
+        if (!c.copy(out, t, nr)) return false;
+        return c.comb(Pa, m, pc, nr, out);
     };
-    iters = 0;
-    relres = 0.0;
-    if (!c.ok(hipMemsetAsync(Z, 0, sizeof(c64) * c.nf, c.s), "memset")) return false;
-    const double bn = c.norm(rhs);
-    if (!(bn > 0)) return true;
-    if (!c.copy(r, rhs, 1) || !opd(r, s) || !c.copy(p, s, 1)) return false;
-    double gam = c.norm(s);
-    gam *= gam;
-    relres = 1.0;
-    while (iters < max_it) {
-        if (!op(p, q)) return false;
-        double qq = c.norm(q);
-        qq *= qq;
-        if (!(qq > 0)) break;
-        const double alpha = gam / qq;
-        if (!c.lincomb(c.nf, 1.0, Z, alpha, p, 0.0, nullptr, Z)) return false;
-        if (!c.lincomb(c.nf, 1.0, r, -alpha, q, 0.0, nullptr, r)) return false;
-        ++iters;
-        relres = c.norm(r) / bn;
-        if (relres <= tol) break;
-        if (!opd(r, s)) return false;
-        double gn = c.norm(s);
-        gn *= gn;
-        if (!c.lincomb(c.nf, 1.0, s, gn / gam, p, 0.0, nullptr, p)) return false;
-        gam = gn;
+    iters.assign(nr, 0);
+    relres.assign(nr, 0.0);
+    if (!c.ok(hipMemsetAsync(Z, 0, sizeof(c64) * blk, c.s), "memset")) return false;
+    std::vector<double> bn, gam, qq, rn, gn;
+    if (!norms2(rhs, bn)) return false;
+    std::vector<char> active(nr, 0);
+    for (int j = 0; j < nr; ++j) {
+        bn[j] = std::sqrt(bn[j]);
+        active[j] = bn[j] > 0;
+        relres[j] = active[j] ? 1.0 : 0.0;
     }
-    // true residual of the final iterate
+    if (!c.copy(r, rhs, nr) || !opd(r, s) || !c.copy(p, s, nr) || !norms2(s, gam)) return false;
+    for (int it = 0; it < max_it; ++it) {
+        if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
+        if (!op(p, q) || !norms2(q, qq)) return false;
+        for (int j = 0; j < nr; ++j) {
+            if (!active[j]) continue;
+            if (!(qq[j] > 0)) {
+                active[j] = 0;
+                continue;
+            }
+            const double alpha = gam[j] / qq[j];
+            if (!c.lincomb(c.nf, 1.0, col(Z, j), alpha, col(p, j), 0.0, nullptr, col(Z, j))) return false;
+            if (!c.lincomb(c.nf, 1.0, col(r, j), -alpha, col(q, j), 0.0, nullptr, col(r, j))) return false;
+            ++iters[j];
+        }
+        if (!norms2(r, rn)) return false;
+        for (int j = 0; j < nr; ++j) {
+            if (!active[j]) continue;
+            relres[j] = std::sqrt(rn[j]) / bn[j];
+            if (relres[j] <= tol) active[j] = 0;
+        }
+        if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
+        if (!opd(r, s) || !norms2(s, gn)) return false;
+        for (int j = 0; j < nr; ++j) {
+            if (!active[j]) continue;
+            if (!c.lincomb(c.nf, 1.0, col(s, j), gn[j] / gam[j], col(p, j), 0.0, nullptr, col(p, j))) return false;
+            gam[j] = gn[j];
+        }
+    }
+    // true residuals of the final iterates
     if (!op(Z, q)) return false;
-    if (!c.lincomb(c.nf, 1.0, rhs, -1.0, q, 0.0, nullptr, r)) return false;
-    relres = c.norm(r) / bn;
+    if (!c.lincomb(blk, 1.0, rhs, -1.0, q, 0.0, nullptr, r)) return false;
+    if (!norms2(r, rn)) return false;
+    for (int j = 0; j < nr; ++j) relres[j] = bn[j] > 0 ? std::sqrt(rn[j]) / bn[j] : 0.0;
     return true;
 }
 
@@ -630,8 +666,8 @@ int eigs_compute(const EigParams& P, EigResult& out) {
         c64* DL = c.fields(l);      // dA^dag L_j
         c64* dR = c.fields(l);
         c64* dL = c.fields(l);
-        c64* rhs = c.fields(1);
-        c64* z = c.fields(1);
+        c64* rhs = c.fields(l);
+        c64* z = c.fields(l);
         if (!D || !DL || !dR || !dL || !rhs || !z) return fail(-2);
         if (!c.apply(dop, P.mu, Rv, D, m)) return fail(-3);
         // (d/dmu H)^dag = -(d/dmu H)(-mu); for a link direction dH^dag = dH(-mu)
@@ -641,54 +677,57 @@ int eigs_compute(const EigParams& P, EigResult& out) {
         if (!c.proj(Lv, m, D, m, C)) return fail(-3);
         std::vector<cd> lam(m);
         for (int i = 0; i < m; ++i) lam[i] = right.theta[i];
-        for (int j = 0; j < l; ++j) {
+        for (int j = 0; j < l; ++j)
             for (int i = 0; i < m; ++i)
                 if (i != j && std::abs(lam[j] - lam[i]) < 1e-9 * (1.0 + std::abs(lam[j]))) {
                     c.err = "degenerate eigenvalues among the derivative pairs";
                     return fail(-7);
                 }
-            // right: rhs = (1 - P) dA R_j
-            if (!c.copy(rhs, D + (size_t)j * c.nf, 1)) return fail(-3);
-            std::vector<cd> cj(m);
-            for (int i = 0; i < m; ++i) cj[i] = -C[(size_t)i * m + j];
-            if (!c.comb(Rv, m, cj, 1, rhs)) return fail(-3);
-            int it = 0;
-            double rr = 0.0;
-            if (!cgls_shifted(c, P.mu, false, lam[j], Rv, Lv, m, rhs, z, P.shift_tol, P.shift_max, it, rr))
-                return fail(-3);
-            if (verbose()) {
-                std::fprintf(stderr, "eigs dR_%d: %d CGLS iterations, residual %.2e\n", j, it, rr);
-                std::fflush(stderr);
+        std::vector<int> its;
+        std::vector<double> res;
+        auto record = [&](const char* side) {
+            for (int j = 0; j < l; ++j) {
+                if (verbose()) {
+                    std::fprintf(stderr, "eigs %s_%d: %d CGLS iterations, residual %.2e\n", side, j, its[j], res[j]);
+                    std::fflush(stderr);
+                }
+                out.shift_iters += its[j];
+                out.shift_res = std::max(out.shift_res, res[j]);
             }
-            out.shift_iters += it;
-            out.shift_res = std::max(out.shift_res, rr);
-            c64* dRj = dR + (size_t)j * c.nf;
-            if (!c.copy(dRj, z, 1)) return fail(-3);
-            std::vector<cd> sr(m, cd(0));
+        };
+        // right, all l at once: rhs_j = (1 - P) dA R_j, then dR_j = z_j + sum_{i != j} R_i C_ij / (lam_j - lam_i)
+        {
+            if (!c.copy(rhs, D, l)) return fail(-3);
+            std::vector<cd> cm((size_t)m * l), sr((size_t)m * l, cd(0));
             for (int i = 0; i < m; ++i)
-                if (i != j) sr[i] = C[(size_t)i * m + j] / (lam[j] - lam[i]);
-            if (!c.comb(Rv, m, sr, 1, dRj)) return fail(-3);
-            // left: rhs = (1 - P)^dag dA^dag L_j = e - L (R^dag e)
-            const c64* e = DL + (size_t)j * c.nf;
+                for (int j = 0; j < l; ++j) {
+                    cm[(size_t)i * l + j] = -C[(size_t)i * m + j];
+                    if (i != j) sr[(size_t)i * l + j] = C[(size_t)i * m + j] / (lam[j] - lam[i]);
+                }
+            if (!c.comb(Rv, m, cm, l, rhs)) return fail(-3);
+            if (!cgls_shifted(c, P.mu, false, std::vector<cd>(lam.begin(), lam.begin() + l), Rv, Lv, m, rhs, z,
+                              P.shift_tol, P.shift_max, its, res))
+                return fail(-3);
+            record("dR");
+            if (!c.copy(dR, z, l) || !c.comb(Rv, m, sr, l, dR)) return fail(-3);
+        }
+        // left: rhs_j = (1 - P)^dag dA^dag L_j = e_j - L (R^dag e_j), then
+        // dL_j = z_j + sum_{i != j} L_i conj(C_ji / (lam_j - lam_i))
+        {
             std::vector<cd> pr;
-            if (!c.proj(Rv, m, e, 1, pr)) return fail(-3);
-            if (!c.copy(rhs, e, 1)) return fail(-3);
+            if (!c.proj(Rv, m, DL, l, pr)) return fail(-3);
+            if (!c.copy(rhs, DL, l)) return fail(-3);
             for (auto& v : pr) v = -v;
-            if (!c.comb(Lv, m, pr, 1, rhs)) return fail(-3);
-            if (!cgls_shifted(c, P.mu, true, std::conj(lam[j]), Rv, Lv, m, rhs, z, P.shift_tol, P.shift_max, it, rr))
-                return fail(-3);
-            if (verbose()) {
-                std::fprintf(stderr, "eigs dL_%d: %d CGLS iterations, residual %.2e\n", j, it, rr);
-                std::fflush(stderr);
-            }
-            out.shift_iters += it;
-            out.shift_res = std::max(out.shift_res, rr);
-            c64* dLj = dL + (size_t)j * c.nf;
-            if (!c.copy(dLj, z, 1)) return fail(-3);
-            std::vector<cd> sl(m, cd(0));
+            if (!c.comb(Lv, m, pr, l, rhs)) return fail(-3);
+            std::vector<cd> shl(l), sl((size_t)m * l, cd(0));
+            for (int j = 0; j < l; ++j) shl[j] = std::conj(lam[j]);
             for (int i = 0; i < m; ++i)
-                if (i != j) sl[i] = std::conj(C[(size_t)j * m + i] / (lam[j] - lam[i]));
-            if (!c.comb(Lv, m, sl, 1, dLj)) return fail(-3);
+                for (int j = 0; j < l; ++j)
+                    if (i != j) sl[(size_t)i * l + j] = std::conj(C[(size_t)j * m + i] / (lam[j] - lam[i]));
+            if (!cgls_shifted(c, P.mu, true, shl, Rv, Lv, m, rhs, z, P.shift_tol, P.shift_max, its, res))
+                return fail(-3);
+            record("dL");
+            if (!c.copy(dL, z, l) || !c.comb(Lv, m, sl, l, dL)) return fail(-3);
         }
         if (out.shift_res > 1e3 * P.shift_tol) {
             c.err = "shifted solves for the eigenvector derivatives did not converge (residual " +
