@@ -78,6 +78,53 @@ __global__ void lincomb_kernel(long long n_elem, c64 a, const c64* __restrict__ 
     }
 }
 
+// x^dag y of two fields in two launches with a fixed summation order: each of
+// kDotBlocks blocks sums a strided share of the elements (wave shuffles, then
+// the block's waves in order), and one block adds the partials in order.
+constexpr int kDotBlocks = 512;
+__device__ __forceinline__ void block_sum2(double& re, double& im, double* lds) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        re += __shfl_xor(re, m, 64);
+        im += __shfl_xor(im, m, 64);
+    }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        lds[2 * w] = re;
+        lds[2 * w + 1] = im;
+    }
+    __syncthreads();
+    re = 0.0;
+    im = 0.0;
+    for (int q = 0; q < nw; ++q) {
+        re += lds[2 * q];
+        im += lds[2 * q + 1];
+    }
+}
+__global__ __launch_bounds__(256) void dot_partial_kernel(long long n_elem, const c64* __restrict__ x,
+                                                          const c64* __restrict__ y, c64* __restrict__ part) {
+    __shared__ double lds[8];
+    double re = 0.0, im = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+        const c64 a = x[e], b = y[e];
+        re += a.re * b.re + a.im * b.im;
+        im += a.re * b.im - a.im * b.re;
+    }
+    block_sum2(re, im, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = c64{re, im};
+}
+__global__ __launch_bounds__(256) void dot_final_kernel(int nb, const c64* __restrict__ part, c64* __restrict__ out) {
+    __shared__ double lds[8];
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        re += part[i].re;
+        im += part[i].im;
+    }
+    block_sum2(re, im, lds);
+    if (threadIdx.x == 0) *out = c64{re, im};
+}
+
 // out = X + f Y with f = sgn num / den from device scalars, so that a CG step
 // needs no host round trip (f = 0 when den = 0); X and out may be the same
 __global__ void axpy_ratio_kernel(long long n_elem, const c64* X, double sgn, const c64* __restrict__ num,
@@ -230,10 +277,17 @@ struct Ctx {
         return ok(hipGetLastError(), "lincomb");
     }
     // dst (device, one complex) = x^dag y, left on the device
+    c64* dot_part = nullptr;
     bool dot_dev(const c64* x, const c64* y, c64* dst) {
-        if (!ensure_scratch(1, 1)) return false;
-        launch_defl_proj(x, nf, 1, y, nf, 1, nf, dst, scr, s);
-        return ok(hipGetLastError(), "defl_proj");
+        if (!dot_part) {
+            void* p = nullptr;
+            if (!ok(hipMalloc(&p, kDotBlocks * sizeof(c64)), "hipMalloc")) return false;
+            owned.push_back(p);
+            dot_part = (c64*)p;
+        }
+        dot_partial_kernel<<<kDotBlocks, 256, 0, s>>>(nf, x, y, dot_part);
+        dot_final_kernel<<<1, 256, 0, s>>>(kDotBlocks, dot_part, dst);
+        return ok(hipGetLastError(), "dot");
     }
     bool axpy_ratio(const c64* X, double sgn, const c64* num, const c64* den, const c64* Y, c64* out) {
         long long nb = (nf + 255) / 256;
@@ -263,9 +317,10 @@ struct Ctx {
         return ok(hipMemcpyAsync(dst, src, sizeof(c64) * (size_t)n * nf, hipMemcpyDeviceToDevice, s), "copy");
     }
     double norm(const c64* x) {
-        std::vector<cd> c;
-        if (!proj(x, 1, x, 1, c)) return -1.0;
-        return std::sqrt(std::max(0.0, c[0].real()));
+        c64* sc = cg_scalars();
+        cd v;
+        if (!sc || !dot_dev(x, x, sc) || !read_scalar(sc, v)) return -1.0;
+        return std::sqrt(std::max(0.0, v.real()));
     }
 };
 
