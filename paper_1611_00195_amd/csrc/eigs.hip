@@ -35,6 +35,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace ovd {
@@ -667,8 +668,42 @@ int eigs_compute(const EigParams& P, EigResult& out) {
     c64* Lraw = c.fields(m);
     if (!Rv || !Lraw) return fail(-2);
     SideResult right, left;
-    if (!arnoldi_side(c, P.mu, m, p, P.tol, P.max_outer, P.seed, Rv, right)) return fail(-3);
-    if (!arnoldi_side(c, -P.mu, m, p, P.tol, P.max_outer, P.seed + 1, Lraw, left)) return fail(-3);
+    {
+        // The two sides are independent.  The left one runs from a second host
+        // thread on a second stream with workspaces of its own, so that the
+        // small launches of the two sides (one field each) overlap on the GPU.
+        hipStream_t s2 = nullptr;
+        hipEvent_t ready = nullptr;
+        if (!c.ok(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "hipStreamCreate")) return fail(-3);
+        bool ok1 = c.ok(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "hipEventCreate") &&
+                   c.ok(hipEventRecord(ready, c.s), "hipEventRecord") &&
+                   c.ok(hipStreamWaitEvent(s2, ready, 0), "hipStreamWaitEvent");   // links and Lraw are ready
+        bool ok2 = ok1;
+        std::string err2;
+        if (ok1) {
+            Ctx c2;
+            c2.g = c.g;
+            c2.U = c.U;
+            c2.dU = c.dU;
+            c2.md = c.md;
+            c2.s = s2;
+            c2.nf = c.nf;
+            std::thread left_side([&] {
+                ok2 = arnoldi_side(c2, -P.mu, m, p, P.tol, P.max_outer, P.seed + 1, Lraw, left);
+            });
+            ok1 = arnoldi_side(c, P.mu, m, p, P.tol, P.max_outer, P.seed, Rv, right);
+            left_side.join();
+            ok2 = c2.ok(hipStreamSynchronize(s2), "sync") && ok2;   // before c2's workspaces are freed
+            err2 = c2.err;
+        }
+        if (ready) (void)hipEventDestroy(ready);
+        (void)hipStreamDestroy(s2);
+        if (!ok1) return fail(-3);
+        if (!ok2) {
+            if (c.err.empty()) c.err = err2;
+            return fail(-3);
+        }
+    }
     out.outer_right = right.outer;
     out.outer_left = left.outer;
     out.res_right = right.max_res;
