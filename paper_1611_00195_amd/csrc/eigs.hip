@@ -773,9 +773,7 @@ int eigs_compute(const EigParams& P, EigResult& out) {
                     c.err = "degenerate eigenvalues among the derivative pairs";
                     return fail(-7);
                 }
-        std::vector<int> its;
-        std::vector<double> res;
-        auto record = [&](const char* side) {
+        auto record = [&](const char* side, const std::vector<int>& its, const std::vector<double>& res) {
             for (int j = 0; j < l; ++j) {
                 if (verbose()) {
                     std::fprintf(stderr, "eigs %s_%d: %d CGLS iterations, residual %.2e\n", side, j, its[j], res[j]);
@@ -786,38 +784,76 @@ int eigs_compute(const EigParams& P, EigResult& out) {
             }
         };
         // right, all l at once: rhs_j = (1 - P) dA R_j, then dR_j = z_j + sum_{i != j} R_i C_ij / (lam_j - lam_i)
-        {
-            if (!c.copy(rhs, D, l)) return fail(-3);
+        auto right_side = [&](Ctx& cx, c64* rb, c64* zb, std::vector<int>& its, std::vector<double>& res) -> bool {
+            if (!cx.copy(rb, D, l)) return false;
             std::vector<cd> cm((size_t)m * l), sr((size_t)m * l, cd(0));
             for (int i = 0; i < m; ++i)
                 for (int j = 0; j < l; ++j) {
                     cm[(size_t)i * l + j] = -C[(size_t)i * m + j];
                     if (i != j) sr[(size_t)i * l + j] = C[(size_t)i * m + j] / (lam[j] - lam[i]);
                 }
-            if (!c.comb(Rv, m, cm, l, rhs)) return fail(-3);
-            if (!cgls_shifted(c, P.mu, false, std::vector<cd>(lam.begin(), lam.begin() + l), Rv, Lv, m, rhs, z,
+            if (!cx.comb(Rv, m, cm, l, rb)) return false;
+            if (!cgls_shifted(cx, P.mu, false, std::vector<cd>(lam.begin(), lam.begin() + l), Rv, Lv, m, rb, zb,
                               P.shift_tol, P.shift_max, its, res))
-                return fail(-3);
-            record("dR");
-            if (!c.copy(dR, z, l) || !c.comb(Rv, m, sr, l, dR)) return fail(-3);
-        }
+                return false;
+            return cx.copy(dR, zb, l) && cx.comb(Rv, m, sr, l, dR);
+        };
         // left: rhs_j = (1 - P)^dag dA^dag L_j = e_j - L (R^dag e_j), then
         // dL_j = z_j + sum_{i != j} L_i conj(C_ji / (lam_j - lam_i))
-        {
+        auto left_side = [&](Ctx& cx, c64* rb, c64* zb, std::vector<int>& its, std::vector<double>& res) -> bool {
             std::vector<cd> pr;
-            if (!c.proj(Rv, m, DL, l, pr)) return fail(-3);
-            if (!c.copy(rhs, DL, l)) return fail(-3);
+            if (!cx.proj(Rv, m, DL, l, pr)) return false;
+            if (!cx.copy(rb, DL, l)) return false;
             for (auto& v : pr) v = -v;
-            if (!c.comb(Lv, m, pr, l, rhs)) return fail(-3);
+            if (!cx.comb(Lv, m, pr, l, rb)) return false;
             std::vector<cd> shl(l), sl((size_t)m * l, cd(0));
             for (int j = 0; j < l; ++j) shl[j] = std::conj(lam[j]);
             for (int i = 0; i < m; ++i)
                 for (int j = 0; j < l; ++j)
                     if (i != j) sl[(size_t)i * l + j] = std::conj(C[(size_t)j * m + i] / (lam[j] - lam[i]));
-            if (!cgls_shifted(c, P.mu, true, shl, Rv, Lv, m, rhs, z, P.shift_tol, P.shift_max, its, res))
+            if (!cgls_shifted(cx, P.mu, true, shl, Rv, Lv, m, rb, zb, P.shift_tol, P.shift_max, its, res))
+                return false;
+            return cx.copy(dL, zb, l) && cx.comb(Lv, m, sl, l, dL);
+        };
+        // the two sets of systems are independent: the left one runs from a
+        // second host thread on a second stream with workspaces of its own
+        {
+            c64* rhs2 = c.fields(l);
+            c64* z2 = c.fields(l);
+            if (!rhs2 || !z2) return fail(-2);
+            std::vector<int> its_r, its_l;
+            std::vector<double> res_r, res_l;
+            hipStream_t s2 = nullptr;
+            hipEvent_t ready = nullptr;
+            if (!c.ok(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "hipStreamCreate")) return fail(-3);
+            bool ok1 = c.ok(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "hipEventCreate") &&
+                       c.ok(hipEventRecord(ready, c.s), "hipEventRecord") &&
+                       c.ok(hipStreamWaitEvent(s2, ready, 0), "hipStreamWaitEvent");   // D, DL, R, L are ready
+            bool ok2 = ok1;
+            std::string err2;
+            if (ok1) {
+                Ctx c2;
+                c2.g = c.g;
+                c2.U = c.U;
+                c2.dU = c.dU;
+                c2.md = c.md;
+                c2.s = s2;
+                c2.nf = c.nf;
+                std::thread left_thread([&] { ok2 = left_side(c2, rhs2, z2, its_l, res_l); });
+                ok1 = right_side(c, rhs, z, its_r, res_r);
+                left_thread.join();
+                ok2 = c2.ok(hipStreamSynchronize(s2), "sync") && ok2;   // before c2's workspaces are freed
+                err2 = c2.err;
+            }
+            if (ready) (void)hipEventDestroy(ready);
+            (void)hipStreamDestroy(s2);
+            if (!ok1) return fail(-3);
+            if (!ok2) {
+                if (c.err.empty()) c.err = err2;
                 return fail(-3);
-            record("dL");
-            if (!c.copy(dL, z, l) || !c.comb(Lv, m, sl, l, dL)) return fail(-3);
+            }
+            record("dR", its_r, res_r);
+            record("dL", its_l, res_l);
         }
         if (out.shift_res > 1e3 * P.shift_tol) {
             c.err = "shifted solves for the eigenvector derivatives did not converge (residual " +
