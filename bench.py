@@ -508,7 +508,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU form "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+              "(independent solves would shard one group per GPU); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.counters_run:
         counters_run(args)
