@@ -55,13 +55,15 @@ typedef enum {
     OVD_EBREAKDOWN = -4,  /* serious Lanczos breakdown: |w^dag v| <= tau |w| |v| */
     OVD_ENODEFL = -5,     /* deflation requested for a mu with no deflation set */
     OVD_ENAN = -6,        /* non-finite value detected in the recurrence */
-    OVD_ENOCONV = -7      /* an iterative solver (eigenpairs, shifted solves) did not converge */
+    OVD_ENOCONV = -7      /* an iterative solver did not converge: eigenpairs, shifted solves,
+                             or the sgn(T_k) e_1 quadrature (see quad_max_levels) */
 } ovd_status;
 
 enum { OVD_FP64 = 0, OVD_MIXED = 1 };        /* precision of Krylov vectors and stencil */
 enum { OVD_LEFT_SUM = 0, OVD_LEFT_SAME = 1 };  /* left start of the block system */
 enum { OVD_DIR_MU = 0, OVD_DIR_LINK = 1 };     /* derivative direction t */
 enum { OVD_OP_H = 0, OVD_OP_DW = 1, OVD_OP_DH_DMU = 2, OVD_OP_DH_DLINK = 3 };
+enum { OVD_SIGN_QUAD = 0, OVD_SIGN_NESTED = 1 };   /* method for sgn(T_k) e_1 */
 
 typedef struct {
     int precision;          /* OVD_FP64 (default) or OVD_MIXED: FP32 vectors, links and
@@ -106,6 +108,19 @@ typedef struct {
                                turned into Z in place, k + 2C fields instead of 3k); -1
                                (default): recompute only when the stored form does not fit in
                                the free device memory */
+    int quad_max_levels;    /* refinement levels of the sgn(T_k) e_1 quadrature before the call
+                               fails with OVD_ENOCONV (two successive levels must agree to
+                               1e-10); 0: 9; at most 20 */
+    int sign_method;        /* OVD_SIGN_QUAD (default): sgn(T_k) e_1 by the quadrature above;
+                               OVD_SIGN_NESTED: by a nested two-sided Lanczos run (Sec. 4: one
+                               level of nesting, inner Krylov size nested_inner) on
+                               (T_k + T_k^{-1})/2, whose kp x kp Ritz matrix is signed by the
+                               quadrature; an inner breakdown returns OVD_EBREAKDOWN */
+    int nested_inner;       /* inner Krylov size of OVD_SIGN_NESTED; 0: 100 (the paper's);
+                               values above k are clamped to k */
+    long long mem_budget;   /* > 0: with basis_recompute = -1, the bytes a stored Krylov basis may
+                               take; a larger one is regenerated instead (as when it does not
+                               fit in free device memory); 0 (default): no budget */
 } ovd_options;
 
 typedef struct {
@@ -119,7 +134,8 @@ typedef struct {
     int breakdown_step;     /* first step with a serious breakdown, -1 if none */
     double min_margin;      /* min over steps and right-hand sides of |w^dag v|/(|w||v|) */
     double sign_check;      /* error estimate of sgn(T_k) e_1: max difference between the last two
-                               refinement levels of the quadrature (see quad_step) */
+                               refinement levels of the quadrature (see quad_step); set also
+                               when the call fails with OVD_ENOCONV */
     double ms_lanczos;      /* device time of the Lanczos steps (HIP events) */
     double ms_small_sign;   /* device time of the sgn(T_k) e_1 solve */
     double ms_total;        /* device time of the whole call */
@@ -143,7 +159,9 @@ ovd_status ovd_set_stream(ovd_h h, void* stream);
 
 /* Upload a gauge configuration (Sec. 4: the derivative is taken on SU(3)
  * configurations).  U: device complex128 [4][V][3][3].  The handle keeps an
- * FP64 copy and, for OVD_MIXED, an FP32 copy in its own layout. */
+ * FP64 copy and, for OVD_MIXED, an FP32 copy in its own layout.  Every
+ * deflation set of the handle is removed: its eigenvectors belong to the
+ * previous links. */
 ovd_status ovd_set_links(ovd_h h, const void* U);
 
 /* Apply one operator to nrhs spinor fields (used for stencil checks and the
@@ -167,7 +185,12 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
  *   dR, dL   device complex128 [l][V][4][3], t-derivatives of the first l
  *            R_i, L_i along dir, gauge L_i^dag dR_i = 0 = dL_i^dag R_i; may be
  *            NULL when l = 0
- *   dir      the direction dR, dL belong to (nullable when l = 0) */
+ *   dir      the direction dR, dL belong to (nullable when l = 0); for
+ *            OVD_DIR_LINK with l > 0, dir->dU must be that direction: the set
+ *            keeps a copy, and ovd_sign_apply_deriv along any other direction
+ *            (mu, or a different dU) fails with OVD_EINVAL instead of using
+ *            derivatives that belong elsewhere.
+ * The set lives until it is replaced, cleared, or the links change. */
 ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam,
                              const void* R, const void* L, int l,
                              const void* dR, const void* dL, const ovd_dir* dir);
@@ -237,6 +260,28 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
                                 int k, const void* b, void* y, void* dy,
                                 const void* x, double* xdy, ovd_stats* st);
 
+/* sgn(B) applied to a general block vector psi = (t; b) by the same method
+ * (eq. 7 with a full source): k steps of two-sided Lanczos on
+ * B = [[H, dH], [0, H]], left start (t + b; b), deflated by eq. 11 with the
+ * first l pairs of the set for mu (the projections c = L^dag b,
+ * d = dL^dag b + L^dag t).  With t = NULL this is ovd_sign_apply_deriv
+ * (yt = dy, yb = y).  The second application of the Sec. 4 error estimate of
+ * the derivative needs it.
+ *   t         device complex128 [nrhs][V][4][3] or NULL (zero top half)
+ *   b         device complex128 [nrhs][V][4][3]
+ *   yt, yb    device complex128 [nrhs][V][4][3] or NULL (not both): top and
+ *             bottom halves of sgn(B) psi */
+ovd_status ovd_block_sign_apply(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* t,
+                                const void* b, void* yt, void* yb, ovd_stats* st);
+
+/* Error estimate of Sec. 4 for the derivative: with psi = (0; phi),
+ *   eps_B = |sgn(B)(sgn(B) psi) - psi| / (2 |psi|),
+ * both applications of sgn(B) by ovd_block_sign_apply (k steps each, the
+ * handle's precision, deflated when a set for mu exists).  eps: host
+ * double[nrhs]; phi: device complex128 [nrhs][V][4][3]. */
+ovd_status ovd_deriv_error_estimate(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* phi,
+                                    double* eps, ovd_stats* st);
+
 /* The overlap operator of eq. 1 (lattice spacing a = 1) and its derivative:
  *   Db  = D_ov b = b + gamma5 sgn(H(mu)) b,     dDb = d/dt D_ov b = gamma5 d/dt sgn(H) b,
  * with sgn(H) b and its derivative from ovd_sign_apply / ovd_sign_apply_deriv
@@ -291,19 +336,42 @@ ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs);
  *   dsdU, dsdUc  device complex128 [4][V][3][3] or NULL: Wirtinger derivatives
  *             ds/dU_nu(y)[a][b] and ds/dconj(U_nu(y)[a][b]) with the links taken
  *             as unconstrained complex matrices (for automatic differentiation)
+ *   dsdtheta  device complex128 [4][V] or NULL: ds/dTheta_nu(y) = i tr F_nu(y),
+ *             the derivatives along an external U(1) field, U_nu(y) ->
+ *             e^{i Theta_nu(y)} U_nu(y) (Sec. 4 takes its derivatives along such a
+ *             field; Sec. 5 builds the conserved axial current from them)
  * The Krylov bases V_k, W_k are stored (2 k 12 V complex128 of workspace).
  * With OVD_MIXED the Lanczos run keeps FP32 vectors (FP64 scalars, as in
  * ovd_sign_apply) and its bases are widened to FP64 for M_k, Z and the force
  * (2 k 12 V complex64 more workspace). */
 ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b,
                               double* s, double* ds_dmu, void* F, void* dsdU, void* dsdUc,
-                              ovd_stats* st);
+                              void* dsdtheta, ovd_stats* st);
 
 /* Launch shapes in use so far (chosen by the autotuner, or forced through the
  * options), as text
  * "kernel:precision:dir-or-op:nrhs=map<m>,gpb<g>[,seq];..." into buf (host, len
  * bytes, truncated and NUL-terminated). */
 ovd_status ovd_get_tuned(ovd_h h, char* buf, int len);
+
+/* sgn(T) e_1 for nt complex tridiagonal k x k matrices given on the host: the
+ * small dense step of every Krylov-Ritz approximation (Sec. 2, closing part:
+ * f(A) psi ~ |psi| V_k f(T_k) e_1), on its own, with the method, quadrature
+ * step, level limit, inner size and breakdown tolerance of opt (nullable:
+ * defaults).  The sign is discontinuous on the imaginary axis (Sec. 3), so the
+ * quadrature needs more levels for eigenvalues close to it.
+ *   alpha, beta, delta  host complex128 [nt][k] in the convention of
+ *             ovd_get_tridiag: diagonal alpha[0..k-1], T[i][i+1] = beta[i+1],
+ *             T[i+1][i] = delta[i+1] (entries 0 of beta and delta unused)
+ *   c         host complex128 [nt][k], receives sgn(T) e_1
+ *   check     host double or NULL: the quadrature's last level difference
+ *   stream    hipStream_t (NULL: null stream)
+ * Errors: OVD_EINVAL (nt < 1, k < 1, null pointers), OVD_ENOCONV (levels
+ * exhausted; c then holds the last level), OVD_EBREAKDOWN (inner breakdown of
+ * OVD_SIGN_NESTED), OVD_ENOMEM, OVD_EHIP.  Device memory is allocated and
+ * freed inside the call. */
+ovd_status ovd_tridiag_sign(int nt, int k, const double* alpha, const double* beta, const double* delta,
+                            const ovd_options* opt, double* c, double* check, void* stream);
 
 /* Lanczos coefficients of the last Lanczos run (for parity checks), right-hand
  * side rhs: host complex128 arrays alpha[k], beta[k], delta[k].  T_k has

@@ -166,6 +166,22 @@ def deflate_gen(h, h_dag, dh, dh_dag, b, k, lam, R, L, dR, dL,
     return y[:n] + exact_top, y[n:] + exact_bot, info
 
 
+def deflate_gen_block(h, h_dag, dh, dh_dag, psi, k, lam, R, L, dR, dL,
+                      sign=matfun.sign_schur, rule="sum", tau=1e-14):
+    """Eq. 11 for a general block source psi = (p_t; p_b): sgn(B) psi as one
+    2n vector, l deflated Jordan blocks."""
+    psi = np.asarray(psi, dtype=np.complex128).ravel()
+    n = psi.size // 2
+    proj, c_t, c_b = block_projector_apply(psi, R, L, dR, dL)
+    psi_p = psi - proj
+    op, op_h = tsl.block_ops(h, h_dag, dh, dh_dag, n)
+    phi = tsl.block_left_start(psi_p, n, rule)
+    y, info = tsl.krylov_sign(op, op_h, psi_p, phi, k, sign, tau)
+    s = matfun.sgn_scalar(lam)
+    exact = np.concatenate([R @ (s * c_t) + dR @ (s * c_b), R @ (s * c_b)])
+    return y + exact, info
+
+
 def deflate_gen_scalar(h, h_dag, dh, dh_dag, b, x, k, lam, R, L, dR, dL,
                        sign=matfun.sign_schur, rule="sum", tau=1e-14):
     """<x| d sgn(A) b> in the storage-free scalar mode, with generalised deflation."""

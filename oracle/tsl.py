@@ -25,7 +25,8 @@ Readings of points the paper leaves open (each recorded in the design notes):
   * the normalisation split delta = sqrt|omega| (a convention);
   * breakdown tolerance tau = 1e-14, no look-ahead;
   * sgn(T_k) e_1 by the Schur method (matfun.sign_schur) -- robust when the
-    Ritz values pair up, as they do for the non-diagonalisable block matrix;
+    Ritz values pair up, as they do for the non-diagonalisable block matrix --
+    or by the paper's nested two-sided Lanczos (``NestedSign``, Sec. 4);
   * left start vector: phi = psi for the kernel itself; for the block system
     (source (p_t; p_b)) phi = (p_t + p_b; p_b).  phi = psi cannot work there:
     B^dag (0; v) = (0; A^dag v), so every left vector would keep a zero top
@@ -105,8 +106,47 @@ def lanczos(op, op_h, psi, phi, k, tau=1e-14, keep_basis=True, proj=None):
 
 
 def ritz_coeffs(T, sign=matfun.sign_schur):
-    """c = sgn(T_k) e_1."""
+    """c = sgn(T_k) e_1.  ``sign`` maps a square matrix to its sign; a
+    ``NestedSign`` instance returns the first column directly."""
+    if isinstance(sign, NestedSign):
+        return sign(T)
     return sign(T)[:, 0]
+
+
+class NestedSign:
+    """sgn(T) e_1 by one level of nesting (Sec. 4: the paper's outer Ritz
+    matrix is signed by a nested two-sided Lanczos run, inner Krylov size 100;
+    the construction follows the cited nested Krylov-Ritz method).
+
+    The inner run cannot use T itself: its Krylov space from e_1 is spanned by
+    e_1 .. e_kp and would only reproduce the outer run truncated at kp steps.
+    It uses Tt = (T + T^{-1}) / 2, which has the same sign function as T
+    (Re(z + 1/z) = Re z (1 + 1/|z|^2)), with right and left start e_1:
+
+        sgn(T) e_1 ~ V' sgn(T') e_1,   T' the kp x kp inner Ritz matrix,
+
+    and sgn(T') by the dense ``inner`` method.  Tt is formed densely here; at
+    kp = k the inner space is all of C^k and the result is exact.
+
+    Pinned by (tests/test_oracle_nested.py): sgn(Tt) = sgn(T) on dense
+    matrices, exactness at kp = k against the Schur sign, and convergence in kp
+    towards sgn(T) e_1 for the Ritz matrix of a lattice operator.
+    """
+
+    def __init__(self, kp, inner=matfun.sign_schur, tau=1e-14):
+        self.kp = int(kp)
+        self.inner = inner
+        self.tau = tau
+
+    def __call__(self, T):
+        T = np.asarray(T, dtype=np.complex128)
+        k = T.shape[0]
+        Tt = 0.5 * (T + np.linalg.inv(T))
+        Tth = Tt.conj().T
+        e1 = np.zeros(k, dtype=np.complex128)
+        e1[0] = 1.0
+        L = lanczos(lambda v: Tt @ v, lambda w: Tth @ w, e1, e1, min(self.kp, k), self.tau)
+        return L["norm"] * (L["V"] @ self.inner(L["T"])[:, 0])
 
 
 def krylov_sign(op, op_h, psi, phi, k, sign=matfun.sign_schur, tau=1e-14):
@@ -143,6 +183,15 @@ def block_left_start(psi, n, rule="sum"):
     if rule == "same":
         return psi.copy()
     return np.concatenate([psi[:n] + psi[n:], psi[n:]])
+
+
+def krylov_block_sign(h, h_dag, dh, dh_dag, psi, k, sign=matfun.sign_schur, rule="sum", tau=1e-14):
+    """sgn(B) psi for a general block vector psi = (p_t; p_b) of length 2n
+    (eq. 7 with a full source), left start by ``rule``; returns (y, lanczos info)."""
+    psi = np.asarray(psi, dtype=np.complex128).ravel()
+    n = psi.size // 2
+    op, op_h = block_ops(h, h_dag, dh, dh_dag, n)
+    return krylov_sign(op, op_h, psi, block_left_start(psi, n, rule), k, sign, tau)
 
 
 def krylov_sign_deriv(h, h_dag, dh, dh_dag, b, k, sign=matfun.sign_schur, rule="sum", tau=1e-14):

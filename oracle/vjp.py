@@ -24,7 +24,9 @@ derivative is ds/dt = tr(F_nu(y) X) with
 
 c_f = e^{mu}, c_b = e^{-mu} for nu = t (else 1), s_f, s_b the time-boundary
 signs of the two hops.  The su(3) component along i lambda_a/2 is
-tr(F i lambda_a/2); a U(1) phase exp(i theta) on the link gives i tr F.
+tr(F i lambda_a/2); a U(1) phase exp(i theta) on the link gives i tr F
+(``u1_derivative``), the derivative along the external U(1) field that Sec. 4
+differentiates along.
 
 Pinned by (tests/test_oracle_vjp.py): central finite differences of s computed
 with the dense sign, for mu and for random link directions; the Krylov form
@@ -132,11 +134,9 @@ def force_from_pairs(Vb, Z, U, dims, mu, r=1.0, bc_t=-1.0):
     return F
 
 
-def su3_components(F):
-    """tr(F i lambda_a / 2) for the eight Gell-Mann generators, shape [4][V][8]."""
-    import synth
-    lam = synth.gell_mann()
-    return np.einsum("nvab,kba->nvk", F, 0.5j * lam)
+def u1_derivative(F):
+    """ds/dTheta_nu(y) = i tr F_nu(y) for the U(1) phases U_nu(y) -> e^{i Theta} U_nu(y), shape [4][V]."""
+    return 1j * np.einsum("nvaa->nv", F)
 
 
 def directional(F, X):

@@ -37,6 +37,7 @@ struct DeflSet {
     c64* L = nullptr;
     c64* dR = nullptr;  // [l][12][Vp]
     c64* dL = nullptr;
+    c64* dir_ref = nullptr;  // link direction of dR, dL (FP64 internal layout); null for mu
     double* sgn = nullptr;   // device [m]: sgn(Re lambda_i)
     double* ones = nullptr;  // device [m]: 1
 };
@@ -209,6 +210,7 @@ std::vector<StencilVariant> op_candidates(int nrhs, int op) {
 bool recompute_basis(ovd_h h, size_t need, std::initializer_list<const char*> held_names, ovd_status* st) {
     if (h->opt.basis_recompute > 0) return true;
     if (h->opt.basis_recompute == 0) return false;
+    if (h->opt.mem_budget > 0 && need > (size_t)h->opt.mem_budget) return true;
     size_t held = 0;
     for (const char* n : held_names) {
         auto it = h->ws.find(n);
@@ -295,6 +297,42 @@ ovd_status check_handle(ovd_h h) {
     if (!h) return OVD_EINVAL;
     if (!h->links_set) return fail(h, OVD_EINVAL, "links not set (call ovd_set_links first)");
     return OVD_OK;
+}
+
+SmallSignCfg sign_cfg(const ovd_options& o) {
+    SmallSignCfg c;
+    c.quad_step = o.quad_step;
+    c.max_levels = o.quad_max_levels > 0 ? o.quad_max_levels : kDefaultMaxLevels;
+    c.chunk = kDefaultChunkSolves;
+    return c;
+}
+
+// map a return code of the small dense solvers to a status
+ovd_status small_status(ovd_h h, int rc, const char* what, double chk, int bstep) {
+    if (rc == 0) return OVD_OK;
+    if (rc == 1)
+        return fail(h, OVD_ENOCONV, std::string(what) + ": two successive quadrature levels still differ by " +
+                                        std::to_string(chk) + " (> 1e-10) after the last allowed level");
+    if (rc == 2)
+        return fail(h, OVD_EBREAKDOWN, std::string(what) + ": breakdown of the inner Lanczos run at step " +
+                                           std::to_string(bstep));
+    return fail(h, OVD_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)(-rc)));
+}
+
+// sgn(T_k) e_1 for the nrhs Ritz matrices in co, by the handle's method
+ovd_status small_sign(ovd_h h, int nrhs, int k, TslCoeffs co, c64* c_out, double* chk, int* bstep) {
+    ovd_status wst = OVD_OK;
+    const SmallSignCfg cfg = sign_cfg(h->opt);
+    if (h->opt.sign_method == OVD_SIGN_NESTED) {
+        const int kp = std::min(k, h->opt.nested_inner > 0 ? h->opt.nested_inner : 100);
+        WS(scr, c64, "small_scratch", nested_sign_scratch_elems(nrhs, k, kp, cfg.chunk));
+        const int rc = launch_nested_sign(nrhs, k, co, kp, h->opt.breakdown_tol, cfg, scr, c_out, chk, bstep,
+                                          h->stream);
+        return small_status(h, rc, "sgn(T_k) e_1 (nested)", *chk, *bstep);
+    }
+    WS(scr, c64, "small_scratch", small_sign_scratch_elems(nrhs, k, cfg.chunk));
+    const int rc = launch_small_sign(nrhs, k, co, cfg, scr, c_out, chk, h->stream);
+    return small_status(h, rc, "sgn(T_k) e_1", *chk, -1);
 }
 
 // Core two-sided Lanczos run on nrhs systems.
@@ -518,18 +556,17 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     if (bad == 2) return fail(h, OVD_ENAN, "non-finite value in the Lanczos recurrence at step " + std::to_string(bstep));
 
     // sgn(T_k) e_1
-    const size_t ne = small_sign_scratch_elems(nrhs, k, h->opt.quad_step);
-    WS(scr, c64, "small_scratch", ne);
     ts.start(h->stream);
     double chk = 0.0;
-    launch_small_sign(nrhs, k, co, h->opt.quad_step, scr, ne, c_out, &chk, h->stream);
-    HIPCHK(hipGetLastError());
+    int bst = -1;
+    const ovd_status ss = small_sign(h, nrhs, k, co, c_out, &chk, &bst);
     ts.stop(h->stream);
     if (stats) {
         stats->ms_small_sign = ts.ms();
         stats->sign_check = chk;
+        if (ss == OVD_EBREAKDOWN) stats->breakdown_step = bst;
     }
-    return OVD_OK;
+    return ss;
 }
 
 // The vector outputs without a stored basis: the Lanczos run again (same
@@ -640,9 +677,18 @@ ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const voi
     return OVD_OK;
 }
 
+// a[i] += b[i] for n complex
+__global__ void cadd_kernel(int n, c64* __restrict__ a, const c64* __restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += b[i];
+}
+
+// The block method (eq. 6-7) on the source psi = (t; b) (t = 0 when null):
+// dy, y = top and bottom halves of sgn(B) psi, deflated by eq. 11 when a set
+// for mu exists; with x, the storage-free <x|dy>.
 template <typename T>
 ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, const void* b, void* y, void* dy,
-                      const void* x, double* xdy, ovd_stats* stats) {
+                      const void* x, double* xdy, ovd_stats* stats, const void* t = nullptr) {
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const long long half = (long long)12 * g.Vp;
@@ -655,6 +701,22 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
     for (const auto& rn : runs)
         if (rn.set && rn.set->l > 0 && rn.set->dir_kind != (dirk == 2 ? OVD_DIR_LINK : OVD_DIR_MU))
             return fail(h, OVD_EINVAL, "deflation set derivatives belong to another direction");
+    if (dirk == 2) {   // a set built along one link direction must not serve another
+        WS(flag, unsigned, "dir_flag", 1);
+        bool any = false;
+        HIPCHK(hipMemsetAsync(flag, 0, sizeof(unsigned), h->stream));
+        for (const auto& rn : runs)
+            if (rn.set && rn.set->l > 0) {
+                launch_field_differs((long long)link_elems<double>(g.Vp), h->dU64, rn.set->dir_ref, flag, h->stream);
+                any = true;
+            }
+        if (any) {
+            unsigned hf = 0;
+            HIPCHK(hipMemcpyAsync(&hf, flag, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            if (hf) return fail(h, OVD_EINVAL, "the deflation set's derivatives belong to another link direction");
+        }
+    }
     WS(b64, c64, "stage_b", (size_t)nrhs * half);
     WS(t64, c64, "stage_t", (size_t)nrhs * half);
     WS(srcv, cpx<T>, "src_v", (size_t)nrhs * fsz);
@@ -677,11 +739,12 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     Timer tt;
     tt.start(h->stream);
-    // psi = (0; b), deflated by eq. 11: psi' = psi - P_{2l} psi = (-(R d + dR c); b - R c)
-    // with c = L^dag b, d = dL^dag b over the first l pairs
+    // psi = (t; b), deflated by eq. 11: psi' = psi - P_{2l} psi = (t - (R d + dR c); b - R c)
+    // with c = L^dag b, d = dL^dag b + L^dag t over the first l pairs
     HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * half, h->stream));
     HIPCHK(hipMemsetAsync(t64, 0, sizeof(c64) * nrhs * half, h->stream));
     launch_pack_spinor<double>(g, nrhs, b, b64, half, h->stream);
+    if (t) launch_pack_spinor<double>(g, nrhs, t, t64, half, h->stream);
     c64 *sC = nullptr, *sD = nullptr;
     if (lmax > 0) {
         WS(Cm, c64, "defl_C", (size_t)lmax * nrhs);
@@ -700,6 +763,10 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
             c64* tb = t64 + (size_t)rn.r0 * half;
             launch_defl_proj(d.L, half, l, bb, half, rn.n, half, Cm, scr, h->stream);
             launch_defl_proj(d.dL, half, l, bb, half, rn.n, half, Dm, scr, h->stream);
+            if (t) {   // d += L^dag t
+                launch_defl_proj(d.L, half, l, tb, half, rn.n, half, tmp, scr, h->stream);
+                cadd_kernel<<<(l * rn.n + 255) / 256, 256, 0, h->stream>>>(l * rn.n, Dm, tmp);
+            }
             launch_defl_scale(l, rn.n, d.ones, Cm, tmp, -1.0, h->stream);
             launch_defl_comb(d.dR, half, l, tmp, rn.n, tb, half, half, h->stream);   // t -= dR c
             launch_defl_comb(d.R, half, l, tmp, rn.n, bb, half, half, h->stream);    // b -= R c
@@ -800,6 +867,12 @@ ovd_status upload_dir(ovd_h h, const ovd_dir* dir, int* dirk) {
 
 }  // namespace
 
+bool options_ok(const ovd_options& o) {
+    return (o.precision == OVD_FP64 || o.precision == OVD_MIXED) && o.quad_max_levels >= 0 &&
+           o.quad_max_levels <= kMaxLevelsLimit && (o.sign_method == OVD_SIGN_QUAD || o.sign_method == OVD_SIGN_NESTED) &&
+           o.nested_inner >= 0 && o.mem_budget >= 0;
+}
+
 extern "C" {
 
 ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, const ovd_options* opt,
@@ -831,14 +904,18 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.shape_seq = -1;
     h->opt.shape_rp = 0;
     h->opt.basis_recompute = -1;
+    h->opt.quad_max_levels = 0;
+    h->opt.sign_method = OVD_SIGN_QUAD;
+    h->opt.nested_inner = 0;
+    h->opt.mem_budget = 0;
     if (opt) {
-        h->opt = *opt;
-        if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
-        if (h->opt.quad_step <= 0) h->opt.quad_step = 0.1;
-        if (h->opt.precision != OVD_FP64 && h->opt.precision != OVD_MIXED) {
+        if (!options_ok(*opt)) {
             delete h;
             return OVD_EINVAL;
         }
+        h->opt = *opt;
+        if (h->opt.breakdown_tol <= 0) h->opt.breakdown_tol = 1e-14;
+        if (h->opt.quad_step <= 0) h->opt.quad_step = 0.1;
     }
     h->stream = (hipStream_t)stream;
     *out = h;
@@ -875,6 +952,8 @@ ovd_status ovd_set_links(ovd_h h, const void* U) {
     if (!U) return fail(h, OVD_EINVAL, "null link pointer");
     if (!h->U64) HIPCHK(hipMalloc(&h->U64, link_elems<double>(h->g.Vp) * sizeof(c64)));
     if (h->opt.precision == OVD_MIXED && !h->U32) HIPCHK(hipMalloc(&h->U32, link_elems<float>(h->g.Vp) * sizeof(c32)));
+    // the eigenvectors of any deflation set belong to the old links
+    if (!h->defl.empty()) ovd_clear_deflation(h);
     launch_pack_links(h->g, U, h->U64, h->U32, h->stream);
     HIPCHK(hipGetLastError());
     h->links_set = true;
@@ -979,6 +1058,43 @@ ovd_status ovd_sign_apply_deriv(ovd_h h, int nrhs, const double* mu, const ovd_d
     return deriv_impl<double>(h, nrhs, mu, dirk, k, b, y, dy, x, xdy, st);
 }
 
+ovd_status ovd_block_sign_apply(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* t,
+                                const void* b, void* yt, void* yb, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !b || (!yt && !yb)) return fail(h, OVD_EINVAL, "bad ovd_block_sign_apply arguments");
+    if (st) std::memset(st, 0, sizeof(*st));
+    int dirk = 1;
+    s = upload_dir(h, dir, &dirk);
+    if (s != OVD_OK) return s;
+    if (h->opt.precision == OVD_MIXED)
+        return deriv_impl<float>(h, nrhs, mu, dirk, k, b, yb, yt, nullptr, nullptr, st, t);
+    return deriv_impl<double>(h, nrhs, mu, dirk, k, b, yb, yt, nullptr, nullptr, st, t);
+}
+
+ovd_status ovd_deriv_error_estimate(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* phi,
+                                    double* eps, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !phi || !eps) return fail(h, OVD_EINVAL, "bad ovd_deriv_error_estimate arguments");
+    ovd_status wst = OVD_OK;
+    const long long ns = (long long)nrhs * h->g.V;
+    WS(t1, c64, "eps_t1", (size_t)ns * 12);
+    WS(b1, c64, "eps_b1", (size_t)ns * 12);
+    WS(t2, c64, "eps_t2", (size_t)ns * 12);
+    WS(b2, c64, "eps_b2", (size_t)ns * 12);
+    WS(e, double, "eps_out", nrhs);
+    // sgn(B) (0; phi), then sgn(B) applied to that full block vector
+    s = ovd_block_sign_apply(h, nrhs, mu, dir, k, nullptr, phi, t1, b1, st);
+    if (s != OVD_OK) return s;
+    s = ovd_block_sign_apply(h, nrhs, mu, dir, k, t1, b1, t2, b2, nullptr);
+    if (s != OVD_OK) return s;
+    launch_half_rel_diff(nrhs, (long long)h->g.V * 12, b2, phi, e, h->stream, t2);
+    HIPCHK(hipMemcpyAsync(eps, e, sizeof(double) * nrhs, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return OVD_OK;
+}
+
 ovd_status ovd_overlap_apply(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k, const void* b,
                              void* Db, void* dDb, ovd_stats* st) {
     ovd_status s = check_handle(h);
@@ -1076,6 +1192,20 @@ ovd_status ovd_get_tridiag(ovd_h h, int rhs, int k, double* alpha, double* beta,
 
 }  // extern "C"
 
+void free_defl(DeflSet& d) {
+    for (void* q : {(void*)d.R, (void*)d.L, (void*)d.dR, (void*)d.dL, (void*)d.dir_ref, (void*)d.sgn, (void*)d.ones})
+        if (q) (void)hipFree(q);
+    d = DeflSet{};
+}
+
+// a device copy of the packed link direction that dR, dL belong to
+ovd_status tag_direction(ovd_h h, DeflSet& d, const c64* packed) {
+    const size_t n = link_elems<double>(h->g.Vp);
+    if (hipMalloc(&d.dir_ref, sizeof(c64) * n) != hipSuccess) return fail(h, OVD_ENOMEM, "deflation direction copy");
+    HIPCHK(hipMemcpyAsync(d.dir_ref, packed, sizeof(c64) * n, hipMemcpyDeviceToDevice, h->stream));
+    return OVD_OK;
+}
+
 // finish a deflation set whose vectors are on the device: upload sgn(lambda),
 // check L^dag R = 1, replace any set of the same mu
 template <typename Release>
@@ -1113,12 +1243,7 @@ ovd_status install_defl(ovd_h h, DeflSet& d, const std::vector<double>& sg, cons
     }
     for (auto it = h->defl.begin(); it != h->defl.end(); ++it) {
         if (std::fabs(it->mu - mu) <= 1e-12) {
-            (void)hipFree(it->R);
-            (void)hipFree(it->L);
-            if (it->dR) (void)hipFree(it->dR);
-            if (it->dL) (void)hipFree(it->dL);
-            (void)hipFree(it->sgn);
-            (void)hipFree(it->ones);
+            free_defl(*it);
             h->defl.erase(it);
             break;
         }
@@ -1135,6 +1260,8 @@ ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const
     if (!h) return OVD_EINVAL;
     if (m < 1 || !lam || !R || !L || l < 0 || l > m || (l > 0 && (!dR || !dL)))
         return fail(h, OVD_EINVAL, "bad ovd_set_deflation arguments");
+    if (l > 0 && dir && dir->kind == OVD_DIR_LINK && !dir->dU)
+        return fail(h, OVD_EINVAL, "deflation derivatives along a link direction need that direction (dir->dU)");
     ovd_status wst = OVD_OK;
     const Geom& g = h->g;
     const long long nf = (long long)12 * g.Vp;
@@ -1154,14 +1281,7 @@ ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const
         if (e == hipSuccess) e = hipMemsetAsync(*p, 0, sizeof(c64) * (size_t)n * nf, h->stream);
         return e;
     };
-    auto release = [&]() {
-        if (d.R) (void)hipFree(d.R);
-        if (d.L) (void)hipFree(d.L);
-        if (d.dR) (void)hipFree(d.dR);
-        if (d.dL) (void)hipFree(d.dL);
-        if (d.sgn) (void)hipFree(d.sgn);
-        if (d.ones) (void)hipFree(d.ones);
-    };
+    auto release = [&]() { free_defl(d); };
     if (alloc(&d.R, m) != hipSuccess || alloc(&d.L, m) != hipSuccess ||
         (l > 0 && (alloc(&d.dR, l) != hipSuccess || alloc(&d.dL, l) != hipSuccess)) ||
         hipMalloc(&d.sgn, sizeof(double) * m) != hipSuccess || hipMalloc(&d.ones, sizeof(double) * m) != hipSuccess) {
@@ -1173,6 +1293,15 @@ ovd_status ovd_set_deflation(ovd_h h, double mu, int m, const double* lam, const
     if (l > 0) {
         launch_pack_spinor<double>(g, l, dR, d.dR, nf, h->stream);
         launch_pack_spinor<double>(g, l, dL, d.dL, nf, h->stream);
+    }
+    if (l > 0 && d.dir_kind == OVD_DIR_LINK) {
+        int dk = 0;
+        ovd_status s2 = upload_dir(h, dir, &dk);
+        if (s2 == OVD_OK) s2 = tag_direction(h, d, h->dU64);
+        if (s2 != OVD_OK) {
+            release();
+            return s2;
+        }
     }
     return install_defl(h, d, sg, on, release);
 }
@@ -1235,13 +1364,17 @@ ovd_status ovd_compute_deflation(ovd_h h, double mu, int m, int l, const ovd_dir
             lam[2 * i + 1] = R.lam[i].im;
         }
     }
-    auto release = [&]() {
-        for (void* q : {(void*)d.R, (void*)d.L, (void*)d.dR, (void*)d.dL, (void*)d.sgn, (void*)d.ones})
-            if (q) (void)hipFree(q);
-    };
+    auto release = [&]() { free_defl(d); };
     if (hipMalloc(&d.sgn, sizeof(double) * m) != hipSuccess || hipMalloc(&d.ones, sizeof(double) * m) != hipSuccess) {
         release();
         return fail(h, OVD_ENOMEM, "device allocation of the deflation set failed");
+    }
+    if (l > 0 && d.dir_kind == OVD_DIR_LINK) {
+        const ovd_status s2 = tag_direction(h, d, h->dU64);
+        if (s2 != OVD_OK) {
+            release();
+            return s2;
+        }
     }
     return install_defl(h, d, sg, on, release);
 }
@@ -1270,20 +1403,13 @@ ovd_status ovd_get_deflation(ovd_h h, double mu, int* m, int* l, double* lam, vo
 ovd_status ovd_clear_deflation(ovd_h h) {
     if (!h) return OVD_EINVAL;
     (void)hipStreamSynchronize(h->stream);
-    for (auto& d : h->defl) {
-        (void)hipFree(d.R);
-        (void)hipFree(d.L);
-        if (d.dR) (void)hipFree(d.dR);
-        if (d.dL) (void)hipFree(d.dL);
-        (void)hipFree(d.sgn);
-        (void)hipFree(d.ones);
-    }
+    for (auto& d : h->defl) free_defl(d);
     h->defl.clear();
     return OVD_OK;
 }
 
 ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b, double* s_out,
-                              double* ds_dmu, void* F, void* dsdU, void* dsdUc, ovd_stats* st) {
+                              double* ds_dmu, void* F, void* dsdU, void* dsdUc, void* dsdtheta, ovd_stats* st) {
     ovd_status s = check_handle(h);
     if (s != OVD_OK) return s;
     if (k < 1 || !x || !b) return fail(h, OVD_EINVAL, "bad ovd_sign_apply_vjp arguments");
@@ -1292,7 +1418,7 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     const Geom& g = h->g;
     const long long fsz = (long long)12 * g.Vp;
     const bool mixed = h->opt.precision == OVD_MIXED;
-    const bool grad = ds_dmu || F || dsdU || dsdUc;
+    const bool grad = ds_dmu || F || dsdU || dsdUc || dsdtheta;
     // stored form: both bases and Z (3 k FP64 fields, plus the two FP32 bases
     // in mixed precision); recompute form: the left basis only (turned into Z
     // in place), the right basis regenerated by a second, identical run
@@ -1372,12 +1498,15 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         WS(trF, c64, "vjp_trF", g.V);
         WS(dsum, c64, "vjp_dsum", 1);
         double chk = 0.0;
-        launch_small_frechet(k, co, h->opt.quad_step, scr, M, &chk, h->stream);
+        const int frc = launch_small_frechet(k, co, sign_cfg(h->opt), scr, M, &chk, h->stream);
+        if (st) st->sign_check = std::max(st->sign_check, chk);
+        s = small_status(h, frc, "L_sgn(T_k, e_1 e_1^T)", chk, -1);
+        if (s != OVD_OK) return s;
         launch_vjp_scale_m(k, co, M, Mp, h->stream);
         if (!recompute) {
             WS(Z, c64, "vjp_Z", (size_t)k * fsz);
             launch_zgemm_wmh(bw, fsz, k, Mp, Z, fsz, fsz, h->stream);
-            launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
+            launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF, (c64*)dsdtheta,
                              h->stream);
         } else {
             // Z over W in place, a slab of field elements at a time through a
@@ -1417,7 +1546,7 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
                 const c64* vch = ring64 ? ring64 + slot0 * fsz : chunk64;
                 if (ring32) launch_widen_field(g, n, ring32 + slot0 * fsz, fsz, chunk64, fsz, stream);
                 launch_vjp_force(g, n, vch, fsz, bw + (size_t)done * fsz, fsz, h->U64, emu, (c64*)F, (c64*)dsdU,
-                                 (c64*)dsdUc, trF, stream, Kacc, done == 0, avail == k);
+                                 (c64*)dsdUc, trF, (c64*)dsdtheta, stream, Kacc, done == 0, avail == k);
                 done = avail;
             };
             ovd_stats st2{};
@@ -1441,6 +1570,55 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     tt.stop(h->stream);
     if (st) st->ms_total = tt.ms();
     return OVD_OK;
+}
+
+ovd_status ovd_tridiag_sign(int nt, int k, const double* alpha, const double* beta, const double* delta,
+                            const ovd_options* opt, double* c, double* check, void* stream) {
+    if (nt < 1 || k < 1 || !alpha || !beta || !delta || !c) return OVD_EINVAL;
+    ovd_options o{};
+    o.breakdown_tol = 1e-14;
+    o.quad_step = 0.1;
+    if (opt) {
+        if (!options_ok(*opt)) return OVD_EINVAL;
+        o = *opt;
+        if (o.breakdown_tol <= 0) o.breakdown_tol = 1e-14;
+        if (o.quad_step <= 0) o.quad_step = 0.1;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const SmallSignCfg cfg = sign_cfg(o);
+    const int kp = std::min(k, o.nested_inner > 0 ? o.nested_inner : 100);
+    const bool nested = o.sign_method == OVD_SIGN_NESTED;
+    const size_t nscr = nested ? nested_sign_scratch_elems(nt, k, kp, cfg.chunk) : small_sign_scratch_elems(nt, k, cfg.chunk);
+    const size_t ncoef = (size_t)4 * nt * k;
+    c64* d = nullptr;
+    if (hipMalloc(&d, sizeof(c64) * (ncoef + (size_t)nt * k + nscr)) != hipSuccess) return OVD_ENOMEM;
+    TslCoeffs co{d, d + (size_t)nt * k, d + (size_t)2 * nt * k, d + (size_t)3 * nt * k, k};
+    c64* cd = d + ncoef;
+    c64* scr = cd + (size_t)nt * k;
+    ovd_status st = OVD_OK;
+    double chk = 0.0;
+    int bstep = -1;
+    if (hipMemcpyAsync(co.alpha, alpha, sizeof(c64) * nt * k, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(co.beta, beta, sizeof(c64) * nt * k, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(co.delta, delta, sizeof(c64) * nt * k, hipMemcpyHostToDevice, s) != hipSuccess) {
+        st = OVD_EHIP;
+    } else {
+        const int rc = nested ? launch_nested_sign(nt, k, co, kp, o.breakdown_tol, cfg, scr, cd, &chk, &bstep, s)
+                              : launch_small_sign(nt, k, co, cfg, scr, cd, &chk, s);
+        if (rc < 0) st = OVD_EHIP;
+        else if (rc == 2) st = OVD_EBREAKDOWN;
+        else {
+            if (hipMemcpyAsync(c, cd, sizeof(c64) * nt * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                st = OVD_EHIP;
+            else if (rc == 1)
+                st = OVD_ENOCONV;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (check) *check = chk;
+    return st;
 }
 
 }  // extern "C"

@@ -151,9 +151,10 @@ void launch_gamma5_axpy(long long n_sites, double cb, const void* b, double cy, 
                                                                    (c64*)out);
 }
 
-// per field: out[r] = |a[r] - b[r]| / (2 |b[r]|)  (AoS complex128, m elements each); one block per field
-__global__ void half_rel_diff_kernel(long long m, const c64* __restrict__ a, const c64* __restrict__ b,
-                                     double* __restrict__ out) {
+// per field: out[r] = sqrt(|top[r]|^2 + |a[r] - b[r]|^2) / (2 |b[r]|)  (AoS complex128, m
+// elements each, top nullable: the block vector (top; a) against (0; b)); one block per field
+__global__ void half_rel_diff_kernel(long long m, const c64* __restrict__ top, const c64* __restrict__ a,
+                                     const c64* __restrict__ b, double* __restrict__ out) {
     __shared__ double sd[256], sb[256];
     const c64* A = a + (size_t)blockIdx.x * m;
     const c64* B = b + (size_t)blockIdx.x * m;
@@ -161,6 +162,10 @@ __global__ void half_rel_diff_kernel(long long m, const c64* __restrict__ a, con
     for (long long i = threadIdx.x; i < m; i += blockDim.x) {
         d += norm2(A[i] - B[i]);
         n += norm2(B[i]);
+    }
+    if (top) {
+        const c64* Tp = top + (size_t)blockIdx.x * m;
+        for (long long i = threadIdx.x; i < m; i += blockDim.x) d += norm2(Tp[i]);
     }
     sd[threadIdx.x] = d;
     sb[threadIdx.x] = n;
@@ -175,8 +180,27 @@ __global__ void half_rel_diff_kernel(long long m, const c64* __restrict__ a, con
     if (threadIdx.x == 0) out[blockIdx.x] = sqrt(sd[0]) / (2.0 * sqrt(sb[0]));
 }
 
-void launch_half_rel_diff(int n, long long m, const void* a, const void* b, double* out, hipStream_t s) {
-    half_rel_diff_kernel<<<n, 256, 0, s>>>(m, (const c64*)a, (const c64*)b, out);
+void launch_half_rel_diff(int n, long long m, const void* a, const void* b, double* out, hipStream_t s,
+                          const void* top) {
+    half_rel_diff_kernel<<<n, 256, 0, s>>>(m, (const c64*)top, (const c64*)a, (const c64*)b, out);
+}
+
+// flag |= 1 when two arrays of n complex differ anywhere (bit for bit)
+__global__ void field_differs_kernel(long long n, const c64* __restrict__ a, const c64* __restrict__ b,
+                                     unsigned* __restrict__ flag) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    bool diff = false;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const c64 x = a[i], y = b[i];
+        diff |= (x.re != y.re) || (x.im != y.im);
+    }
+    if (__any(diff) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+void launch_field_differs(long long n, const c64* a, const c64* b, unsigned* flag, hipStream_t s) {
+    long long nb = (n + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    field_differs_kernel<<<(unsigned)nb, 256, 0, s>>>(n, a, b, flag);
 }
 
 }  // namespace ovd

@@ -40,13 +40,11 @@ namespace ovd {
 
 static constexpr double kLowSpan = 54.0;
 static constexpr double kHighSpan = 11.5;
-static constexpr int kMaxLevels = 9;
-static constexpr int kChunkSolves = 16384;   // solves per launch over all rhs (bounds the scratch)
+static constexpr double kSignTol = 1e-10;   // agreement of two refinement levels
 
-size_t small_sign_scratch_elems(int nrhs, int k, double quad_step) {
-    (void)quad_step;
-    (void)nrhs;
-    return 4 * (size_t)k * kChunkSolves + (size_t)4 * nrhs * k + 2 * (size_t)nrhs;
+size_t small_sign_scratch_elems(int nrhs, int k, int chunk) {
+    if (chunk < 1) chunk = kDefaultChunkSolves;
+    return 4 * (size_t)k * chunk + (size_t)4 * nrhs * k + 2 * (size_t)nrhs;
 }
 
 __device__ __forceinline__ c64 tdiag(const TslCoeffs& co, int r, int i) { return co.alpha[(size_t)r * co.kmax + i]; }
@@ -141,8 +139,8 @@ __global__ void small_sign_accum_kernel(int nrhs, int k, int nq, const c64* __re
 
 // c = (h/pi) acc + tail(h); diff[r] = max_i |c - c_prev| (one block per rhs); c_prev <- c
 __global__ void small_sign_finalize_kernel(int k, TslCoeffs co, const double* __restrict__ smin, double h,
-                                           int qlast, const c64* __restrict__ acc, c64* __restrict__ c_out,
-                                           c64* __restrict__ c_prev, double* __restrict__ diff) {
+                                           long long qlast, const c64* __restrict__ acc, c64* __restrict__ c_out,
+                                           c64* __restrict__ c_prev, double* __restrict__ diff, int transpose) {
     __shared__ double red[256];
     __shared__ c64 tail[4];
     const int r = blockIdx.x;
@@ -155,6 +153,11 @@ __global__ void small_sign_finalize_kernel(int k, TslCoeffs co, const double* __
         c64 v1[4] = {}, v2[4] = {}, v3[4] = {};
         auto T = [&](int a, int b) -> c64 {
             if (a >= k || b >= k) return c64{0.0, 0.0};
+            if (transpose) {
+                const int t = a;
+                a = b;
+                b = t;
+            }
             if (a == b) return tdiag(co, r, a);
             if (b == a + 1) return tsup(co, r, a);
             if (a == b + 1) return tsub(co, r, b);
@@ -188,50 +191,61 @@ __global__ void small_sign_finalize_kernel(int k, TslCoeffs co, const double* __
 }
 
 // Host driver: level 0 with step h0 = 2 quad_step, then midpoint refinements
-// until max_r diff_r <= tol (at least one refinement, at most kMaxLevels).
-// Returns the last difference (an error estimate of the previous level, an
-// upper bound of the final error in the geometric regime) in *check.
-void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scratch, size_t scratch_elems,
-                       c64* c_out, double* check, hipStream_t s) {
-    (void)scratch_elems;
+// until max_r diff_r <= kSignTol (at least one refinement, at most
+// cfg.max_levels).  The last difference (an error estimate of the previous
+// level, an upper bound of the final error in the geometric regime) goes to
+// *check.  Returns 0 when converged, 1 when the levels ran out first, or the
+// HIP error of the first failing runtime call (negated).
+int launch_small_sign(int nrhs, int k, TslCoeffs co, const SmallSignCfg& cfg, c64* scratch, c64* c_out,
+                      double* check, hipStream_t s, int transpose) {
+    const int chunk_solves = cfg.chunk > 0 ? cfg.chunk : kDefaultChunkSolves;
+    const int max_levels = cfg.max_levels > 0 ? cfg.max_levels : kDefaultMaxLevels;
     c64* scr = scratch;
-    c64* acc = scratch + 4 * (size_t)k * kChunkSolves;
+    c64* acc = scratch + 4 * (size_t)k * chunk_solves;
     c64* cprev = acc + (size_t)nrhs * k;
     double* smin = (double*)(cprev + (size_t)nrhs * k);
     double* diff = smin + nrhs;
-    (void)hipMemsetAsync(acc, 0, sizeof(c64) * 2 * nrhs * k, s);
+    hipError_t e = hipMemsetAsync(acc, 0, sizeof(c64) * 2 * nrhs * k, s);
+    if (e != hipSuccess) return -(int)e;
     small_sign_setup_kernel<<<(nrhs + 63) / 64, 64, 0, s>>>(nrhs, k, co, smin);
-    const double h0 = 2.0 * quad_step;
+    const double h0 = 2.0 * cfg.quad_step;
     const int Q0 = (int)ceil((kLowSpan + kHighSpan) / h0) + 1;
-    const int chunk = kChunkSolves / (2 * nrhs) > 0 ? kChunkSolves / (2 * nrhs) : 1;
-    const double tol = 1e-10;
+    const int chunk = chunk_solves / (2 * nrhs) > 0 ? chunk_solves / (2 * nrhs) : 1;
     std::vector<double> hd(nrhs);
     double last = 0.0;
-    for (int lev = 0; lev <= kMaxLevels; ++lev) {
+    int rc = 1;
+    for (int lev = 0; lev <= max_levels; ++lev) {
         // nodes of this level: level 0 all Q0 nodes at spacing h0; level l >= 1
         // the (Q0 - 1) 2^{l-1} midpoints at spacing h0 / 2^{l-1}
-        const double sp = lev == 0 ? h0 : h0 / (double)(1 << (lev - 1));
+        const double sp = lev == 0 ? h0 : h0 / (double)(1LL << (lev - 1));
         const double off = lev == 0 ? 0.0 : 0.5;
-        const int nq = lev == 0 ? Q0 : (Q0 - 1) * (1 << (lev - 1));
+        const long long nql = lev == 0 ? Q0 : (long long)(Q0 - 1) * (1LL << (lev - 1));
+        const int nq = (int)nql;
         for (int q0 = 0; q0 < nq; q0 += chunk) {
             const int n = (nq - q0) < chunk ? (nq - q0) : chunk;
             const int nsol = nrhs * 2 * n;
-            small_sign_solve_kernel<<<(nsol + 63) / 64, 64, 0, s>>>(nrhs, k, co, smin, sp, off, q0, n, scr, 0, 1);
+            small_sign_solve_kernel<<<(nsol + 63) / 64, 64, 0, s>>>(nrhs, k, co, smin, sp, off, q0, n, scr, transpose, 1);
             dim3 g((k + 127) / 128, nrhs);
             small_sign_accum_kernel<<<g, 128, 0, s>>>(nrhs, k, n, scr, acc);
         }
-        const double hl = h0 / (double)(1 << lev);
+        const double hl = h0 / (double)(1LL << lev);
         // the last node is s = smin + (Q0 - 1) h0 = smin + qlast * hl
-        const int qlast = (Q0 - 1) * (1 << lev);
-        small_sign_finalize_kernel<<<nrhs, 256, 0, s>>>(k, co, smin, hl, qlast, acc, c_out, cprev, diff);
+        const long long qlast = (long long)(Q0 - 1) * (1LL << lev);
+        small_sign_finalize_kernel<<<nrhs, 256, 0, s>>>(k, co, smin, hl, qlast, acc, c_out, cprev, diff, transpose);
         if (lev == 0) continue;
-        (void)hipMemcpyAsync(hd.data(), diff, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s);
-        (void)hipStreamSynchronize(s);
+        if ((e = hipMemcpyAsync(hd.data(), diff, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return -(int)e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return -(int)e;
         last = 0.0;
-        for (double d : hd) last = d > last ? d : last;
-        if (last <= tol) break;
+        for (double d : hd) last = (d > last || d != d) ? d : last;
+        if (last <= kSignTol) {
+            rc = 0;
+            break;
+        }
     }
     if (check) *check = last;
+    if ((e = hipGetLastError()) != hipSuccess) return -(int)e;
+    return rc;
 }
 
 
@@ -274,7 +288,7 @@ __global__ __launch_bounds__(64) void frechet_accum_kernel(int k, int nsol, cons
 }
 
 // Mout = -(h/pi) Msum + tail; diff = max |Mout - Mprev|; Mprev <- Mout   (one block)
-__global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __restrict__ smin, double h, int qlast,
+__global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __restrict__ smin, double h, long long qlast,
                                         const c64* __restrict__ Msum, c64* __restrict__ Mout,
                                         c64* __restrict__ Mprev, double* __restrict__ diff) {
     __shared__ double red[256];
@@ -329,28 +343,32 @@ __global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __res
 }
 
 size_t small_frechet_scratch_elems(int k) {
-    return 2 * (4 * (size_t)k * kChunkSolves) + 3 * (size_t)k * k + 4;
+    return 2 * (4 * (size_t)k * kDefaultChunkSolves) + 3 * (size_t)k * k + 4;
 }
 
-// M (k x k, row-major) = L_sgn(T, e_1 e_1^T) for one tridiagonal (rhs 0 of co)
-void launch_small_frechet(int k, TslCoeffs co, double quad_step, c64* scratch, c64* M_out, double* check,
-                          hipStream_t s) {
+// M (k x k, row-major) = L_sgn(T, e_1 e_1^T) for one tridiagonal (rhs 0 of co);
+// return codes as launch_small_sign
+int launch_small_frechet(int k, TslCoeffs co, const SmallSignCfg& cfg, c64* scratch, c64* M_out, double* check,
+                         hipStream_t s) {
+    const int max_levels = cfg.max_levels > 0 ? cfg.max_levels : kDefaultMaxLevels;
     c64* scrA = scratch;
-    c64* scrB = scrA + 4 * (size_t)k * kChunkSolves;
-    c64* Msum = scrB + 4 * (size_t)k * kChunkSolves;
+    c64* scrB = scrA + 4 * (size_t)k * kDefaultChunkSolves;
+    c64* Msum = scrB + 4 * (size_t)k * kDefaultChunkSolves;
     c64* Mprev = Msum + (size_t)k * k;
     double* smin = (double*)(Mprev + (size_t)k * k);
     double* diff = smin + 2;
-    (void)hipMemsetAsync(Msum, 0, sizeof(c64) * 2 * k * k, s);
+    hipError_t e = hipMemsetAsync(Msum, 0, sizeof(c64) * 2 * k * k, s);
+    if (e != hipSuccess) return -(int)e;
     small_sign_setup_kernel<<<1, 64, 0, s>>>(1, k, co, smin);
-    const double h0 = 2.0 * quad_step;
+    const double h0 = 2.0 * cfg.quad_step;
     const int Q0 = (int)ceil((kLowSpan + kHighSpan) / h0) + 1;
-    const int chunk = kChunkSolves / 2;
+    const int chunk = kDefaultChunkSolves / 2;
     double hd = 0.0, last = 0.0;
-    for (int lev = 0; lev <= kMaxLevels; ++lev) {
-        const double sp = lev == 0 ? h0 : h0 / (double)(1 << (lev - 1));
+    int rc = 1;
+    for (int lev = 0; lev <= max_levels; ++lev) {
+        const double sp = lev == 0 ? h0 : h0 / (double)(1LL << (lev - 1));
         const double off = lev == 0 ? 0.0 : 0.5;
-        const int nq = lev == 0 ? Q0 : (Q0 - 1) * (1 << (lev - 1));
+        const int nq = lev == 0 ? Q0 : (int)((long long)(Q0 - 1) * (1LL << (lev - 1)));
         for (int q0 = 0; q0 < nq; q0 += chunk) {
             const int n = (nq - q0) < chunk ? (nq - q0) : chunk;
             const int nsol = 2 * n;
@@ -361,16 +379,304 @@ void launch_small_frechet(int k, TslCoeffs co, double quad_step, c64* scratch, c
             frechet_accum_kernel<<<g, 64, 0, s>>>(k, nsol, scrA + (size_t)3 * k * nsol, scrB + (size_t)3 * k * nsol,
                                                   Msum);
         }
-        const double hl = h0 / (double)(1 << lev);
-        const int qlast = (Q0 - 1) * (1 << lev);
+        const double hl = h0 / (double)(1LL << lev);
+        const long long qlast = (long long)(Q0 - 1) * (1LL << lev);
         frechet_finalize_kernel<<<1, 256, 0, s>>>(k, co, smin, hl, qlast, Msum, M_out, Mprev, diff);
         if (lev == 0) continue;
-        (void)hipMemcpyAsync(&hd, diff, sizeof(double), hipMemcpyDeviceToHost, s);
-        (void)hipStreamSynchronize(s);
+        if ((e = hipMemcpyAsync(&hd, diff, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return -(int)e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return -(int)e;
         last = hd;
-        if (last <= 1e-10) break;
+        if (last <= kSignTol) {
+            rc = 0;
+            break;
+        }
     }
     if (check) *check = last;
+    if ((e = hipGetLastError()) != hipSuccess) return -(int)e;
+    return rc;
+}
+
+// ===========================================================================
+// Nested two-sided Lanczos for sgn(T_k) e_1 (the paper computes the sign of its
+// outer Ritz matrix with one level of nesting and an inner Krylov size of 100,
+// Sec. 4; the construction is that of the cited nested Krylov-Ritz method).
+//
+// A Krylov space of the tridiagonal T_k itself started at e_1 is spanned by
+// e_1 .. e_kp and would only reproduce the outer run truncated at kp steps.
+// The inner run therefore works on Tt = (T_k + T_k^{-1}) / 2, which has the
+// same sign function as T_k (Re(z + 1/z) = Re z (1 + 1/|z|^2)) and whose
+// Krylov space holds rational functions of T_k:
+//   v_1 = w_1 = e_1;  kp steps of the same two-sided recurrence as the outer
+//   run (Tt^dag = (T^dag + T^{-dag}) / 2);  T' the kp x kp Ritz matrix;
+//   sgn(T_k) e_1 ~ V' sgn(T') e_1,
+// with sgn(T') e_1 from the quadrature above.
+//
+// One block of 256 threads per right-hand side.  The two solves of a step
+// (T^{-1} v and T^{-dag} w) are sequential recurrences; they run at the same
+// time on lane 0 of waves 0 and 1, from pivoted LU factors computed once.
+// Everything else (tridiagonal products, three-term updates, inner products
+// with a fixed summation order) is spread over the block.
+// ===========================================================================
+
+// LU factors of a tridiagonal matrix with partial pivoting (rows i and i+1
+// exchanged when the subdiagonal entry is larger in modulus): unit lower
+// factor with multipliers ml[i], upper factor with diagonal d, superdiagonals
+// du, du2; piv[i] = 1 when rows i, i+1 were exchanged.
+struct TriLU {
+    c64 *d, *du, *du2, *ml;
+    int* piv;
+};
+
+// a: diagonal (n), up[i] = A[i][i+1], lo[i] = A[i+1][i] (n - 1 each), into f
+__device__ void tri_factor(int n, const c64* a_diag, const c64* up, const c64* lo, TriLU f) {
+    for (int i = 0; i < n; ++i) {
+        f.d[i] = a_diag[i];
+        f.du[i] = i + 1 < n ? up[i] : c64{0.0, 0.0};
+        f.du2[i] = c64{0.0, 0.0};
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+        const c64 l = lo[i];
+        if (cabs1(f.d[i]) >= cabs1(l)) {
+            f.piv[i] = 0;
+            const c64 m = cabs1(f.d[i]) > 0.0 ? cdiv(l, f.d[i]) : c64{0.0, 0.0};
+            f.ml[i] = m;
+            f.d[i + 1] = f.d[i + 1] - m * f.du[i];
+        } else {
+            // rows i, i+1 exchanged: row i = (l, d[i+1], du[i+1]), then eliminate
+            f.piv[i] = 1;
+            const c64 m = cdiv(f.d[i], l);
+            f.ml[i] = m;
+            const c64 old_du = f.du[i];
+            f.d[i] = l;
+            f.du[i] = f.d[i + 1];
+            f.d[i + 1] = old_du - m * f.du[i];
+            if (i + 2 < n) {
+                f.du2[i] = f.du[i + 1];
+                f.du[i + 1] = -(m * f.du2[i]);
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (cabs1(f.d[i]) == 0.0) f.d[i] = c64{1e-300, 0.0};
+}
+
+// x <- A^{-1} x with the factors of A
+__device__ void tri_solve(int n, TriLU f, c64* x) {
+    for (int i = 0; i + 1 < n; ++i) {
+        if (f.piv[i] == 0) {
+            x[i + 1] = x[i + 1] - f.ml[i] * x[i];
+        } else {
+            const c64 t = x[i];
+            x[i] = x[i + 1];
+            x[i + 1] = t - f.ml[i] * x[i];
+        }
+    }
+    x[n - 1] = cdiv(x[n - 1], f.d[n - 1]);
+    if (n >= 2) x[n - 2] = cdiv(x[n - 2] - f.du[n - 2] * x[n - 1], f.d[n - 2]);
+    for (int i = n - 3; i >= 0; --i) x[i] = cdiv(x[i] - f.du[i] * x[i + 1] - f.du2[i] * x[i + 2], f.d[i]);
+}
+
+// deterministic block sum of NV doubles (256 threads): fixed shuffle tree in
+// each wave, then the four wave sums in order; the result is returned to all
+template <int NV>
+__device__ void nested_block_sum(double (&v)[NV], double* lds /* [4 * NV + NV] */) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+        v[i] = x;
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int i = 0; i < NV; ++i) lds[w * NV + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NV; ++i) lds[4 * NV + i] = ((lds[i] + lds[NV + i]) + lds[2 * NV + i]) + lds[3 * NV + i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = lds[4 * NV + i];
+}
+
+// per-rhs scratch of the inner run (complex elements): 2 x 4k factors, the
+// six k-vectors v, v_prev, w, w_prev, u, z, and the inner basis kp x k
+__host__ __device__ inline size_t nested_rhs_elems(int k, int kp) { return (size_t)8 * k + 6 * (size_t)k + (size_t)kp * k; }
+
+__global__ __launch_bounds__(256) void nested_tsl_kernel(int k, TslCoeffs co, int kp, double tau,
+                                                         c64* __restrict__ scr, int* __restrict__ ipiv,
+                                                         TslCoeffs ico, int* __restrict__ flags) {
+    __shared__ double lds[64];
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    c64* base = scr + (size_t)r * nested_rhs_elems(k, kp);
+    TriLU fa{base, base + k, base + 2 * k, base + 3 * k, ipiv + (size_t)r * 2 * k};
+    TriLU fh{base + 4 * k, base + 5 * k, base + 6 * k, base + 7 * k, ipiv + (size_t)r * 2 * k + k};
+    c64* v = base + 8 * k;
+    c64* vp = v + k;
+    c64* w = vp + k;
+    c64* wp = w + k;
+    c64* u = wp + k;
+    c64* z = u + k;
+    c64* Vb = z + k;      // inner basis, [kp][k]
+    const c64* al = co.alpha + (size_t)r * co.kmax;
+    const c64* be = co.beta + (size_t)r * co.kmax;    // T[i][i+1] = be[i + 1]
+    const c64* de = co.delta + (size_t)r * co.kmax;   // T[i+1][i] = de[i + 1]
+    c64* ia = ico.alpha + (size_t)r * ico.kmax;
+    c64* ib = ico.beta + (size_t)r * ico.kmax;
+    c64* id = ico.delta + (size_t)r * ico.kmax;
+    // factors of T (lane 0 of wave 0) and of T^dag (lane 0 of wave 1); the
+    // diagonals and off-diagonals are staged through u and z
+    for (int i = tid; i < k; i += nt) {
+        u[i] = al[i];                               // diagonal of T
+        v[i] = i + 1 < k ? be[i + 1] : c64{0.0, 0.0};   // T[i][i+1]
+        vp[i] = i + 1 < k ? de[i + 1] : c64{0.0, 0.0};  // T[i+1][i]
+        z[i] = conj(al[i]);                         // diagonal of T^dag
+        w[i] = i + 1 < k ? conj(de[i + 1]) : c64{0.0, 0.0};   // T^dag[i][i+1] = conj(T[i+1][i])
+        wp[i] = i + 1 < k ? conj(be[i + 1]) : c64{0.0, 0.0};  // T^dag[i+1][i] = conj(T[i][i+1])
+    }
+    __syncthreads();
+    if (tid == 0) tri_factor(k, u, v, vp, fa);
+    if (tid == 64) tri_factor(k, z, w, wp, fh);
+    __syncthreads();
+    for (int i = tid; i < k; i += nt) {
+        v[i] = c64{i == 0 ? 1.0 : 0.0, 0.0};
+        w[i] = v[i];
+        vp[i] = c64{0.0, 0.0};
+        wp[i] = c64{0.0, 0.0};
+    }
+    if (tid == 0) {
+        ib[0] = c64{0.0, 0.0};
+        id[0] = c64{1.0, 0.0};
+        flags[r] = -1;
+    }
+    c64 beta{0.0, 0.0};
+    double delta = 0.0;
+    for (int j = 0; j < kp; ++j) {
+        __syncthreads();
+        // the basis vector, and the right-hand sides of the two solves
+        for (int i = tid; i < k; i += nt) {
+            Vb[(size_t)j * k + i] = v[i];
+            u[i] = v[i];
+            z[i] = w[i];
+        }
+        __syncthreads();
+        if (tid == 0) tri_solve(k, fa, u);      // u = T^{-1} v
+        if (tid == 64) tri_solve(k, fh, z);     // z = T^{-dag} w
+        __syncthreads();
+        // u = (T v + T^{-1} v) / 2,  z = (T^dag w + T^{-dag} w) / 2,  alpha = w^dag u
+        double pa[2] = {0.0, 0.0};
+        for (int i = tid; i < k; i += nt) {
+            c64 tv = al[i] * v[i];
+            c64 tw = conj(al[i]) * w[i];
+            if (i > 0) {
+                tv += de[i] * v[i - 1];             // T[i][i-1]
+                tw += conj(be[i]) * w[i - 1];       // conj(T[i-1][i])
+            }
+            if (i + 1 < k) {
+                tv += be[i + 1] * v[i + 1];         // T[i][i+1]
+                tw += conj(de[i + 1]) * w[i + 1];   // conj(T[i+1][i])
+            }
+            const c64 uu = 0.5 * (tv + u[i]);
+            const c64 zz = 0.5 * (tw + z[i]);
+            u[i] = uu;
+            z[i] = zz;
+            const c64 d = cdot(w[i], uu);
+            pa[0] += d.re;
+            pa[1] += d.im;
+        }
+        nested_block_sum<2>(pa, lds);
+        const c64 alpha{pa[0], pa[1]};
+        if (tid == 0) ia[j] = alpha;
+        if (j == kp - 1) break;
+        // three-term update and omega = what^dag vhat
+        double po[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = tid; i < k; i += nt) {
+            const c64 vh = u[i] - alpha * v[i] - beta * vp[i];
+            const c64 wh = z[i] - conj(alpha) * w[i] - c64{delta, 0.0} * wp[i];
+            u[i] = vh;
+            z[i] = wh;
+            const c64 d = cdot(wh, vh);
+            po[0] += d.re;
+            po[1] += d.im;
+            po[2] += norm2(vh);
+            po[3] += norm2(wh);
+        }
+        nested_block_sum<4>(po, lds);
+        const c64 omega{po[0], po[1]};
+        const double aom = sqrt(norm2(omega));
+        const double margin = aom / sqrt(po[2] * po[3]);
+        if (!(margin > tau)) {   // breakdown (or a non-finite value): T' has j + 1 rows
+            if (tid == 0) flags[r] = j + 1;
+            return;
+        }
+        const double dn = sqrt(aom);
+        const c64 bn = (1.0 / dn) * omega;
+        const c64 sw = cdiv(c64{1.0, 0.0}, conj(bn));
+        for (int i = tid; i < k; i += nt) {
+            vp[i] = v[i];
+            wp[i] = w[i];
+            v[i] = (1.0 / dn) * u[i];
+            w[i] = sw * z[i];
+        }
+        if (tid == 0) {
+            ib[j + 1] = bn;
+            id[j + 1] = c64{dn, 0.0};
+        }
+        // the next update subtracts beta_{j+1} v_j and conj(delta_{j+1}) w_j
+        beta = bn;
+        delta = dn;
+    }
+}
+
+// c[r][i] = sum_j Vb[r][j][i] cp[r][j]  (fixed order in j)
+__global__ void nested_combine_kernel(int k, int kp, const c64* __restrict__ scr, const c64* __restrict__ cp,
+                                      c64* __restrict__ c_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= k) return;
+    const c64* Vb = scr + (size_t)r * nested_rhs_elems(k, kp) + (size_t)14 * k;
+    c64 a{0.0, 0.0};
+    for (int j = 0; j < kp; ++j) a += Vb[(size_t)j * k + i] * cp[(size_t)r * kp + j];
+    c_out[(size_t)r * k + i] = a;
+}
+
+size_t nested_sign_scratch_elems(int nrhs, int k, int kp, int chunk) {
+    return (size_t)nrhs * nested_rhs_elems(k, kp)   // factors, vectors, inner bases
+           + (size_t)nrhs * k                      // pivots (2 k ints per rhs)
+           + (size_t)5 * nrhs * kp                 // inner alpha, beta, delta, proj, sgn(T') e_1
+           + (size_t)nrhs                          // flags
+           + small_sign_scratch_elems(nrhs, kp, chunk);
+}
+
+int launch_nested_sign(int nrhs, int k, TslCoeffs co, int kp, double tau, const SmallSignCfg& cfg, c64* scratch,
+                       c64* c_out, double* check, int* bstep, hipStream_t s) {
+    if (kp > k) kp = k;
+    c64* scr = scratch;
+    int* ipiv = (int*)(scr + (size_t)nrhs * nested_rhs_elems(k, kp));
+    c64* ic = scr + (size_t)nrhs * nested_rhs_elems(k, kp) + (size_t)nrhs * k;
+    TslCoeffs ico{ic, ic + (size_t)nrhs * kp, ic + (size_t)2 * nrhs * kp, ic + (size_t)3 * nrhs * kp, kp};
+    c64* cp = ic + (size_t)4 * nrhs * kp;
+    int* flags = (int*)(cp + (size_t)nrhs * kp);
+    c64* sscr = (c64*)(flags) + nrhs;
+    hipError_t e = hipMemsetAsync(ic, 0, sizeof(c64) * 4 * nrhs * kp, s);
+    if (e != hipSuccess) return -(int)e;
+    nested_tsl_kernel<<<nrhs, 256, 0, s>>>(k, co, kp, tau, scr, ipiv, ico, flags);
+    std::vector<int> hf(nrhs);
+    if ((e = hipMemcpyAsync(hf.data(), flags, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return -(int)e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return -(int)e;
+    for (int r = 0; r < nrhs; ++r)
+        if (hf[r] >= 0) {
+            if (bstep) *bstep = hf[r];
+            return 2;
+        }
+    const int rc = launch_small_sign(nrhs, kp, ico, cfg, sscr, cp, check, s, 0);
+    if (rc < 0) return rc;
+    dim3 g((k + 127) / 128, nrhs);
+    nested_combine_kernel<<<g, 128, 0, s>>>(k, kp, scr, cp, c_out);
+    if ((e = hipGetLastError()) != hipSuccess) return -(int)e;
+    return rc;
 }
 
 }  // namespace ovd

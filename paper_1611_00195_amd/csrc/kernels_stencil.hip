@@ -1262,7 +1262,8 @@ OVD_INST(float)
 //   F = -1/2 cf sgn U Kf + 1/2 cb sgn Kb U^dag  (ds/dt = tr(F X) for U -> e^{tX} U),
 // cf = e^{mu}, cb = e^{-mu} on time links (1 in space), sgn the boundary
 // factor of the hop.  One thread per (site, direction), direction fastest.
-// trF[y] = tr F_t(y), summed later into ds/dmu.
+// trF[y] = tr F_t(y), summed later into ds/dmu; dth[nu][y] = i tr F_nu(y), the
+// derivative along a U(1) phase U_nu(y) -> e^{i theta} U_nu(y) (nullable).
 // The sum over p may be split into chunks (the basis regenerated a chunk at a
 // time): Kacc [18][4V] carries Kf, Kb between the launches of one gradient;
 // `first` starts from zero instead of Kacc, `last` turns K into the outputs
@@ -1273,7 +1274,8 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
                                                         const c64* __restrict__ U, double emu,
                                                         c64* __restrict__ F, c64* __restrict__ dU,
                                                         c64* __restrict__ dUc, c64* __restrict__ trF,
-                                                        c64* __restrict__ Kacc, int first, int last) {
+                                                        c64* __restrict__ dth, c64* __restrict__ Kacc, int first,
+                                                        int last) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 4 * g.V) return;
     const size_t n4 = (size_t)4 * g.V;
@@ -1347,13 +1349,14 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
             if (dUc) dUc[o + 3 * a + b] = (-ab) * Kb[3 * a + b];
         }
     if (nu == 3) trF[y] = tr;
+    if (dth) dth[(size_t)nu * g.V + y] = c64{-tr.im, tr.re};   // i tr F: the U(1) phase of this link
 }
 
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
-                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s, c64* Kacc, bool first,
+                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, c64* dth, hipStream_t s, c64* Kacc, bool first,
                       bool last) {
-    vjp_force_kernel<<<(4 * g.V + 255) / 256, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF, Kacc,
-                                                           first ? 1 : 0, last ? 1 : 0);
+    vjp_force_kernel<<<(4 * g.V + 255) / 256, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF, dth,
+                                                           Kacc, first ? 1 : 0, last ? 1 : 0);
 }
 
 // out = sum_y trF[y] (one block, fixed order)

@@ -168,13 +168,36 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
                         unsigned* counters, int j, double tau, hipStream_t s, StencilVariant v = StencilVariant{});
 
 // sgn(T_k) e_1 for nrhs tridiagonal matrices by the resolvent quadrature.
-void launch_small_sign(int nrhs, int k, TslCoeffs co, double quad_step, c64* scratch,
-                       size_t scratch_elems, c64* c_out, double* check, hipStream_t s);
-size_t small_sign_scratch_elems(int nrhs, int k, double quad_step);
+// quad_step: first refined step of the trapezoidal rule in log(y); max_levels:
+// refinement levels before giving up (<= 0: kDefaultMaxLevels); chunk: solves
+// per launch, which sizes the scratch (<= 0: kDefaultChunkSolves).  The result
+// does not depend on chunk (the node sums are accumulated in one fixed order).
+constexpr int kDefaultMaxLevels = 9;
+constexpr int kMaxLevelsLimit = 20;
+constexpr int kDefaultChunkSolves = 16384;
+struct SmallSignCfg {
+    double quad_step = 0.1;
+    int max_levels = kDefaultMaxLevels;
+    int chunk = kDefaultChunkSolves;
+};
+// Return codes of the small dense solvers: 0 converged, 1 not converged within
+// max_levels (the result is the last level's), < 0 the negated HIP error.
+// transpose: sgn(T^T) e_1 (the first row of sgn(T)) instead of sgn(T) e_1.
+int launch_small_sign(int nrhs, int k, TslCoeffs co, const SmallSignCfg& cfg, c64* scratch, c64* c_out,
+                      double* check, hipStream_t s, int transpose = 0);
+size_t small_sign_scratch_elems(int nrhs, int k, int chunk);
 // M = L_sgn(T_k, e_1 e_1^T) (k x k, row-major) for rhs 0 of co
-void launch_small_frechet(int k, TslCoeffs co, double quad_step, c64* scratch, c64* M_out, double* check,
-                          hipStream_t s);
+int launch_small_frechet(int k, TslCoeffs co, const SmallSignCfg& cfg, c64* scratch, c64* M_out, double* check,
+                         hipStream_t s);
 size_t small_frechet_scratch_elems(int k);
+// Nested two-sided Lanczos for sgn(T_k) e_1: an inner Krylov-Ritz run of kp
+// steps on Tt = (T_k + T_k^{-1}) / 2 (same sign as T_k) from e_1, whose kp x kp
+// Ritz matrix is signed by the quadrature above; c = V' sgn(T') e_1.  Return
+// codes: 0, 1 (quadrature of T' not converged), 2 (inner breakdown, step in
+// *bstep), < 0 HIP error.
+size_t nested_sign_scratch_elems(int nrhs, int k, int kp, int chunk);
+int launch_nested_sign(int nrhs, int k, TslCoeffs co, int kp, double tau, const SmallSignCfg& cfg, c64* scratch,
+                       c64* c_out, double* check, int* bstep, hipStream_t s);
 
 // y = sum_j coef[rhs][j] * basis[rhs][j]  (top/bottom halves selected by half_off);
 // with accumulate, y += the sum (the basis taken a chunk of vectors at a time)
@@ -207,8 +230,13 @@ void launch_convert_field(const Geom& g, int n, const c64* in, long long sin, cp
 // AoS complex128 fields: out = cb b + cy gamma5 y (b may be null)
 void launch_gamma5_axpy(long long n_sites, double cb, const void* b, double cy, const void* y, void* out,
                         hipStream_t s);
-// out[r] = |a_r - b_r| / (2 |b_r|) for n AoS complex128 fields of m complex each (device out)
-void launch_half_rel_diff(int n, long long m, const void* a, const void* b, double* out, hipStream_t s);
+// out[r] = |a_r - b_r| / (2 |b_r|) for n AoS complex128 fields of m complex each (device out);
+// with top: sqrt(|top_r|^2 + |a_r - b_r|^2) / (2 |b_r|), the block vector (top; a) against (0; b)
+void launch_half_rel_diff(int n, long long m, const void* a, const void* b, double* out, hipStream_t s,
+                          const void* top = nullptr);
+
+// *flag |= 1 when the n complex of a and b differ anywhere (flag cleared by the caller)
+void launch_field_differs(long long n, const c64* a, const c64* b, unsigned* flag, hipStream_t s);
 
 // FP32 internal fields -> FP64 internal fields (n fields, strides in elements)
 void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64* out, long long sout, hipStream_t s);
@@ -221,7 +249,7 @@ void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t 
 // split over launches that carry Kf, Kb in Kacc ([18][4V], needed unless
 // first && last): first starts from zero, last writes F, dU, dUc, trF
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
-                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, hipStream_t s, c64* Kacc = nullptr,
+                      double emu, c64* F, c64* dU, c64* dUc, c64* trF, c64* dth, hipStream_t s, c64* Kacc = nullptr,
                       bool first = true, bool last = true);
 void launch_sum_c64(int n, const c64* v, c64* out, hipStream_t s);
 

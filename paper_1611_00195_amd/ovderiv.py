@@ -25,13 +25,14 @@ FP64, MIXED = 0, 1
 LEFT_SUM, LEFT_SAME = 0, 1
 DIR_MU, DIR_LINK = 0, 1
 OP_H, OP_DW, OP_DH_DMU, OP_DH_DLINK = 0, 1, 2, 3
+SIGN_QUAD, SIGN_NESTED = 0, 1
 
 EXPORTS = [
     "ovd_create_lattice", "ovd_destroy", "ovd_last_error", "ovd_set_stream", "ovd_set_links",
     "ovd_apply_op", "ovd_set_deflation", "ovd_clear_deflation", "ovd_sign_apply",
     "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag", "ovd_compute_deflation",
     "ovd_get_deflation", "ovd_sign_apply_deriv_batch", "ovd_get_tuned", "ovd_overlap_apply",
-    "ovd_sign_error_estimate",
+    "ovd_sign_error_estimate", "ovd_tridiag_sign", "ovd_block_sign_apply", "ovd_deriv_error_estimate",
 ]
 
 
@@ -50,7 +51,9 @@ class _Options(ctypes.Structure):
                 ("breakdown_tol", ctypes.c_double), ("quad_step", ctypes.c_double),
                 ("step_timing", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int), ("shape_seq", ctypes.c_int),
-                ("shape_rp", ctypes.c_int), ("basis_recompute", ctypes.c_int)]
+                ("shape_rp", ctypes.c_int), ("basis_recompute", ctypes.c_int),
+                ("quad_max_levels", ctypes.c_int), ("sign_method", ctypes.c_int), ("nested_inner", ctypes.c_int),
+                ("mem_budget", ctypes.c_longlong)]
 
 
 class _EigStats(ctypes.Structure):
@@ -115,8 +118,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ovd_compute_deflation": (i, [vp, d, i, i, ctypes.POINTER(_Dir), d, dp, ctypes.POINTER(_EigStats)]),
         "ovd_sign_apply": (i, [vp, i, dp, i, vp, vp, ctypes.POINTER(_Stats)]),
         "ovd_sign_apply_deriv": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, vp, dp, ctypes.POINTER(_Stats)]),
-        "ovd_sign_apply_vjp": (i, [vp, d, i, vp, vp, dp, dp, vp, vp, vp, ctypes.POINTER(_Stats)]),
+        "ovd_sign_apply_vjp": (i, [vp, d, i, vp, vp, dp, dp, vp, vp, vp, vp, ctypes.POINTER(_Stats)]),
         "ovd_get_tridiag": (i, [vp, i, i, dp, dp, dp]),
+        "ovd_tridiag_sign": (i, [i, i, dp, dp, dp, ctypes.POINTER(_Options), dp, dp, vp]),
+        "ovd_block_sign_apply": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, vp, ctypes.POINTER(_Stats)]),
+        "ovd_deriv_error_estimate": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, dp, ctypes.POINTER(_Stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -161,7 +167,8 @@ class Lattice:
 
     def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
                  breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True,
-                 autotune=True, shape=None, basis_recompute=None):
+                 autotune=True, shape=None, basis_recompute=None, quad_max_levels=0, sign_method=SIGN_QUAD,
+                 nested_inner=0, mem_budget=0):
         self.dims = tuple(int(d) for d in dims)
         self.V = 1
         for d in self.dims:
@@ -176,7 +183,8 @@ class Lattice:
                        0 if shape is None else int(shape[1]),
                        -1 if shape is None or len(shape) < 3 else int(shape[2]),
                        0 if shape is None or len(shape) < 4 else int(shape[3]),
-                       -1 if basis_recompute is None else int(bool(basis_recompute)))
+                       -1 if basis_recompute is None else int(bool(basis_recompute)),
+                       int(quad_max_levels), int(sign_method), int(nested_inner), int(mem_budget))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
@@ -298,7 +306,35 @@ class Lattice:
         self._call("ovd_sign_error_estimate", n, _dbl(mus), int(k), _ptr(b), eps, ctypes.byref(st))
         return [eps[i] for i in range(n)]
 
-    def sign_apply_vjp(self, x, b, mu, k, force=True, wirtinger=False, grad=True):
+    def block_sign_apply(self, t, b, mu, k, direction="mu", dU=None):
+        """sgn(B) (t; b) for the block matrix of eq. 6 (t may be None: zero top
+        half).  Returns (yt, yb), the top and bottom halves."""
+        n = b.shape[0]
+        _check_field(b, (n, self.V, 4, 3), "b")
+        if t is not None:
+            _check_field(t, (n, self.V, 4, 3), "t")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        d, keep = self._dir(direction, dU)
+        yt, yb = torch.empty_like(b), torch.empty_like(b)
+        st = _Stats()
+        self._call("ovd_block_sign_apply", n, _dbl(mus), ctypes.byref(d), int(k), _ptr(t), _ptr(b), _ptr(yt),
+                   _ptr(yb), ctypes.byref(st))
+        self.last_stats = self._stats(st)
+        return yt, yb
+
+    def deriv_error_estimate(self, phi, mu, k, direction="mu", dU=None):
+        """Sec. 4 estimate for the derivative: |sgn(B)^2 (0; phi) - (0; phi)| / (2 |phi|) per source."""
+        n = phi.shape[0]
+        _check_field(phi, (n, self.V, 4, 3), "phi")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        d, keep = self._dir(direction, dU)
+        eps = (ctypes.c_double * n)()
+        st = _Stats()
+        self._call("ovd_deriv_error_estimate", n, _dbl(mus), ctypes.byref(d), int(k), _ptr(phi), eps,
+                   ctypes.byref(st))
+        return [eps[i] for i in range(n)]
+
+    def sign_apply_vjp(self, x, b, mu, k, force=True, wirtinger=False, grad=True, u1=False):
         """s = <x|sgn(H(mu))|b>, ds/dmu and the link gradients (FP64 results;
         the Lanczos run in the handle's precision).
 
@@ -307,7 +343,9 @@ class Lattice:
         derivatives ds/dU, ds/dconj(U) when wirtinger.  With grad=False only s
         is computed (ds_dmu is None).  The handle's basis_recompute chooses
         between keeping both Krylov bases and regenerating the right one
-        (last_stats.basis_recomputed tells which ran)."""
+        (last_stats.basis_recomputed tells which ran).  With u1=True the U(1)
+        derivatives ds/dTheta_nu(y) = i tr F_nu(y) ([4, V] complex) are stored
+        in self.last_dsdtheta."""
         _check_field(x, (1, self.V, 4, 3), "x")
         _check_field(b, (1, self.V, 4, 3), "b")
         sc = (ctypes.c_double * 2)()
@@ -316,9 +354,11 @@ class Lattice:
         F = torch.empty((4, self.V, 3, 3), **opts) if grad and force else None
         dU = torch.empty((4, self.V, 3, 3), **opts) if grad and wirtinger else None
         dUc = torch.empty((4, self.V, 3, 3), **opts) if grad and wirtinger else None
+        dth = torch.empty((4, self.V), **opts) if grad and u1 else None
         st = _Stats()
         self._call("ovd_sign_apply_vjp", float(mu), int(k), _ptr(x), _ptr(b), sc, dm, _ptr(F), _ptr(dU), _ptr(dUc),
-                   ctypes.byref(st))
+                   _ptr(dth), ctypes.byref(st))
+        self.last_dsdtheta = dth
         self.last_stats = self._stats(st)
         return complex(sc[0], sc[1]), (complex(dm[0], dm[1]) if grad else None), F, dU, dUc
 
@@ -338,7 +378,10 @@ class Lattice:
         for i, z in enumerate(lam):
             lam_c[2 * i] = float(complex(z).real)
             lam_c[2 * i + 1] = float(complex(z).imag)
-        d = _Dir(DIR_LINK if direction in ("link", DIR_LINK) else DIR_MU, None)
+        link = direction in ("link", DIR_LINK)
+        if link and l > 0 and dU is not None:
+            _check_field(dU, (4, self.V, 3, 3), "dU")
+        d = _Dir(DIR_LINK if link else DIR_MU, ctypes.c_void_p(dU.data_ptr()) if link and dU is not None else None)
         self._call("ovd_set_deflation", float(mu), m, lam_c, _ptr(R), _ptr(L), int(l),
                    _ptr(dR) if l > 0 else None, _ptr(dL) if l > 0 else None, ctypes.byref(d))
 
@@ -423,6 +466,35 @@ def sign_apply_deriv_batch(jobs):
         lat.last_stats = Lattice._stats(st)
         res.append([complex(xdy[2 * j], xdy[2 * j + 1]) for j in range(nr)])
     return res
+
+
+def tridiag_sign(alpha, beta, delta, method=SIGN_QUAD, quad_step=0.1, quad_max_levels=0, nested_inner=0,
+                 breakdown_tol=1e-14):
+    """sgn(T) e_1 for complex tridiagonal matrices given as numpy arrays
+    [nt, k] (ovd_tridiag_sign; the ovd_get_tridiag convention: T[i][i+1] =
+    beta[i+1], T[i+1][i] = delta[i+1]).  Returns (c [nt, k], check); raises
+    OvdError with status OVD_ENOCONV when the quadrature levels run out."""
+    import numpy as np
+    a = np.ascontiguousarray(np.atleast_2d(alpha), dtype=np.complex128)
+    b = np.ascontiguousarray(np.atleast_2d(beta), dtype=np.complex128)
+    d = np.ascontiguousarray(np.atleast_2d(delta), dtype=np.complex128)
+    nt, k = a.shape
+    if b.shape != a.shape or d.shape != a.shape:
+        raise ValueError("alpha, beta, delta must have the same shape [nt, k]")
+    opt = _Options(FP64, LEFT_SUM, breakdown_tol, quad_step, 0, 1, 1, -1, 0, -1, 0, -1, int(quad_max_levels),
+                   int(method), int(nested_inner), 0)
+    c = np.zeros((nt, k), dtype=np.complex128)
+    chk = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib().ovd_tridiag_sign(nt, k, a.ctypes.data_as(dp), b.ctypes.data_as(dp), d.ctypes.data_as(dp),
+                                ctypes.byref(opt), c.ctypes.data_as(dp), ctypes.byref(chk),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != OVD_OK:
+        err = OvdError(st, "ovd_tridiag_sign failed")
+        err.check = chk.value
+        err.c = c
+        raise err
+    return c, chk.value
 
 
 def create_lattice(dims, **kw) -> Lattice:

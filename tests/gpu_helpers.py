@@ -15,9 +15,16 @@ def host(t):
 
 
 def rel(a, b):
+    """Distance of a from the reference b: the larger of the relative 2-norm
+    error and the largest element error relative to the largest element of b,
+    so that a bound on it is a bound element by element as well."""
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    if a.shape != b.shape:
+        raise ValueError(f"shape mismatch {a.shape} vs {b.shape}")
+    norm = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    elem = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300) if b.size else 0.0
+    return max(norm, elem)
 
 
 def ops(U, dims, mu, dU=None):

@@ -55,3 +55,27 @@ def test_invalid_arguments_rejected_without_gpu_work():
     ok = (ctypes.c_int * 4)(4, 4, 4, 4)
     assert lib.ovd_create_lattice(ok, ctypes.c_double(-1.5), ctypes.c_double(0.5), -1, None, None,
                                   ctypes.byref(h)) == -1
+
+
+def test_bad_options_and_small_sign_arguments_rejected():
+    """Option ranges and the arguments of ovd_tridiag_sign are checked before
+    any device call."""
+    _ensure_built()
+    from paper_1611_00195_amd import ovderiv
+    lib = ctypes.CDLL(LIB)
+    lib.ovd_create_lattice.restype = ctypes.c_int
+    h = ctypes.c_void_p()
+    ok = (ctypes.c_int * 4)(4, 4, 4, 4)
+    base = dict(precision=0, left_start=0, breakdown_tol=1e-14, quad_step=0.1, step_timing=0, use_graph=1,
+                autotune=1, shape_map=-1, shape_gpb=0, shape_seq=-1, shape_rp=0, basis_recompute=-1,
+                quad_max_levels=0, sign_method=0, nested_inner=0, mem_budget=0)
+    for bad in (dict(quad_max_levels=21), dict(sign_method=2), dict(nested_inner=-1), dict(mem_budget=-5),
+                dict(precision=3)):
+        opt = ovderiv._Options(**{**base, **bad})
+        assert lib.ovd_create_lattice(ok, ctypes.c_double(-1.5), ctypes.c_double(1.0), -1, ctypes.byref(opt), None,
+                                      ctypes.byref(h)) == -1, bad
+    lib.ovd_tridiag_sign.restype = ctypes.c_int
+    a = (ctypes.c_double * 8)()
+    assert lib.ovd_tridiag_sign(0, 4, a, a, a, None, a, None, None) == -1
+    assert lib.ovd_tridiag_sign(1, 0, a, a, a, None, a, None, None) == -1
+    assert lib.ovd_tridiag_sign(1, 4, None, a, a, None, a, None, None) == -1

@@ -94,7 +94,8 @@ def test_generalised_deflation_link_parity(eig):
     print_case(test="defl_gen_link", dims=DIMS, m=m, l=l, k=k)
     lam, R, L, dlam, dR, dL = deflation.eig_derivs_dense(H, dHl, m)
     lat = _lat(U)
-    lat.set_deflation(MU, lam, dev(_f(R)), dev(_f(L)), l, dev(_f(dR[:, :l])), dev(_f(dL[:, :l])), direction="link")
+    lat.set_deflation(MU, lam, dev(_f(R)), dev(_f(L)), l, dev(_f(dR[:, :l])), dev(_f(dL[:, :l])), direction="link",
+                      dU=dev(dU))
     b = synth.make_sources(DIMS, 1, 306)
     y, dy, _ = lat.sign_apply_deriv(dev(b), MU, k, direction="link", dU=dev(dU))
     h, hd, dh, dhd = ops(U, DIMS, MU, dU)
@@ -147,7 +148,7 @@ def test_deflation_mixed_precision(eig):
     e = rel(host(dy)[0], dref)
     print(f"mixed precision deflated derivative error {e:.2e}")
     # FP32 Krylov vectors on this rough field (eps = 1.0): measured 1.1e-3
-    assert e < 5e-3
+    assert e < 3e-3
 
 
 def test_non_biorthonormal_set_rejected(eig):

@@ -246,3 +246,43 @@ def test_vjp_auto_mode_stores_when_memory_allows():
     x = synth.make_source(dims, 552)
     lat.sign_apply_vjp(dev(x[None]), dev(x[None]), MU, 16)
     assert lat.last_stats.basis_recomputed == 0
+
+
+def test_u1_current_against_finite_differences_and_oracle():
+    """ds/dTheta_nu(y) = i tr F_nu(y), the derivative along the external U(1)
+    field of Sec. 4 (dsdtheta output of ovd_sign_apply_vjp): on 2^4 at k = 160
+    (converged) against central differences of the oracle's dense
+    <x|sgn(H)|b> for the phase of every link; on 4^4 at k = 96 against the
+    oracle's Krylov gradient at the same k."""
+    from gpu_helpers import dev, host, print_case, rel
+    dims = (2, 2, 2, 2)
+    print_case(test="vjp_u1", dims=dims, k=160)
+    U = synth.make_links(dims, 0.5, 41)
+    x = synth.make_source(dims, 42)
+    b = synth.make_source(dims, 43)
+    lat = _lat(dims, U)
+    lat.sign_apply_vjp(dev(x[None]), dev(b[None]), MU, 160, force=False, u1=True)
+    D = host(lat.last_dsdtheta)
+    lat.close()
+    h = 1e-5
+
+    def s_of(Uv):
+        return np.vdot(x.ravel(), matfun.sign_schur(dirac.dense_h(Uv, dims, MU)) @ b.ravel())
+
+    for nu in range(4):
+        for site in range(U.shape[1]):
+            Up, Um = U.copy(), U.copy()
+            Up[nu, site] = np.exp(1j * h) * Up[nu, site]
+            Um[nu, site] = np.exp(-1j * h) * Um[nu, site]
+            fd = (s_of(Up) - s_of(Um)) / (2 * h)
+            assert abs(fd - D[nu, site]) < 1e-8, (nu, site)
+    dims, k = (4, 4, 4, 4), 96
+    print_case(test="vjp_u1", dims=dims, k=k)
+    U = synth.make_links(dims, 0.4, 501)
+    x = synth.make_source(dims, 502)
+    b = synth.make_source(dims, 503)
+    _, _, F_r, _ = vjp.krylov_vjp(U, dims, MU, x, b, k)
+    lat = _lat(dims, U)
+    lat.sign_apply_vjp(dev(x[None]), dev(b[None]), MU, k, force=False, u1=True)
+    assert rel(host(lat.last_dsdtheta), vjp.u1_derivative(F_r)) < 1e-10
+    lat.close()

@@ -59,6 +59,21 @@ def test_u1_phase_derivative(setup):
     assert abs(fd - 1j * np.trace(F[nu, site])) < 1e-8
 
 
+def test_u1_derivative_every_link(setup):
+    """u1_derivative (i tr F) against central differences of the dense s for
+    the U(1) phase of every link of the 2^4 lattice."""
+    U, x, b, s, dsdmu, F = setup
+    h = 1e-5
+    D = vjp.u1_derivative(F)
+    for nu in range(4):
+        for site in range(U.shape[1]):
+            Up, Um = U.copy(), U.copy()
+            Up[nu, site] = np.exp(1j * h) * Up[nu, site]
+            Um[nu, site] = np.exp(-1j * h) * Um[nu, site]
+            fd = (_s(Up, MU, x, b) - _s(Um, MU, x, b)) / (2 * h)
+            assert abs(fd - D[nu, site]) < 1e-8, (nu, site)
+
+
 def test_krylov_vjp_converges_to_dense(setup):
     U, x, b, s, dsdmu, F = setup
     out = [vjp.krylov_vjp(U, DIMS, MU, x, b, k) for k in (40, 160)]
