@@ -295,6 +295,7 @@ std::vector<Run> defl_runs(ovd_h h, int nrhs, const double* mu) {
 
 ovd_status check_handle(ovd_h h) {
     if (!h) return OVD_EINVAL;
+    (void)hipGetLastError();   // a failed runtime call of an earlier, finished call is not this call's error
     if (!h->links_set) return fail(h, OVD_EINVAL, "links not set (call ovd_set_links first)");
     return OVD_OK;
 }
@@ -949,6 +950,7 @@ ovd_status ovd_set_stream(ovd_h h, void* stream) {
 
 ovd_status ovd_set_links(ovd_h h, const void* U) {
     if (!h) return OVD_EINVAL;
+    (void)hipGetLastError();
     if (!U) return fail(h, OVD_EINVAL, "null link pointer");
     if (!h->U64) HIPCHK(hipMalloc(&h->U64, link_elems<double>(h->g.Vp) * sizeof(c64)));
     if (h->opt.precision == OVD_MIXED && !h->U32) HIPCHK(hipMalloc(&h->U32, link_elems<float>(h->g.Vp) * sizeof(c32)));

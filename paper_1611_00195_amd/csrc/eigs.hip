@@ -327,6 +327,7 @@ struct Ctx {
 
 struct SideResult {
     std::vector<cd> theta;   // m eigenvalues of H, increasing |theta|
+    cd next{0.0, 0.0};       // the (m+1)-th Ritz value of H at convergence (0 when the basis has no more)
     int outer = 0;
     double max_res = 0.0;
     long long solves = 0, cg_iters = 0;
@@ -458,6 +459,7 @@ bool arnoldi_side(Ctx& c, double mu, int m, int n, double tol, int max_cycles, u
             if (!c.comb(Vb, n, Sm, m, Out)) return false;
             if (!c.apply(0, mu, Out, Zm, m)) return false;
             sr.theta.assign(m, cd(0));
+            sr.next = n > m && std::abs(th[m]) > 0.0 ? 1.0 / th[m] : cd(0.0);
             double rmax = 0.0;
             for (int i = 0; i < m; ++i) {
                 c64* xi = Out + (size_t)i * c.nf;
@@ -660,8 +662,11 @@ int eigs_compute(const EigParams& P, EigResult& out) {
     const int m = P.m, l = P.l;
     const int p = P.p > m ? P.p : 2 * m + 20;   // Arnoldi basis size
     out = EigResult{};
+    // on failure the context still owns (and frees) every buffer, including
+    // those already named in out: the caller must not free them again
     auto fail = [&](int code) {
         out.err = c.err.empty() ? "eigensolver failed" : c.err;
+        out.R = out.L = out.dR = out.dL = nullptr;
         return code;
     };
     c64* Rv = c.fields(m);
@@ -767,12 +772,21 @@ int eigs_compute(const EigParams& P, EigResult& out) {
         if (!c.proj(Lv, m, D, m, C)) return fail(-3);
         std::vector<cd> lam(m);
         for (int i = 0; i < m; ++i) lam[i] = right.theta[i];
-        for (int j = 0; j < l; ++j)
+        // the derivatives of pair j divide by lam_j - lam_i and invert lam_j - H
+        // outside the set: an eigenvalue equal to lam_j elsewhere in the set, or
+        // just beyond it (the next Ritz value), makes them undefined
+        for (int j = 0; j < l; ++j) {
             for (int i = 0; i < m; ++i)
                 if (i != j && std::abs(lam[j] - lam[i]) < 1e-9 * (1.0 + std::abs(lam[j]))) {
                     c.err = "degenerate eigenvalues among the derivative pairs";
                     return fail(-7);
                 }
+            if (std::abs(right.next) > 0.0 && std::abs(lam[j] - right.next) < 1e-9 * (1.0 + std::abs(lam[j]))) {
+                c.err = "a derivative pair's eigenvalue recurs just beyond the m-th (a degenerate cluster "
+                        "straddles the cut; choose another m)";
+                return fail(-7);
+            }
+        }
         auto record = [&](const char* side, const std::vector<int>& its, const std::vector<double>& res) {
             for (int j = 0; j < l; ++j) {
                 if (verbose()) {

@@ -68,23 +68,32 @@ def test_block_sign_general_source(field):
 @pytest.mark.parametrize("k", [48, 160])
 def test_eps_estimates_against_oracle(field, k):
     """eps_A and eps_B at the same k as the oracle's (same algorithm, so the
-    same number up to rounding): |eps_gpu - eps_oracle| <= 1e-9 eps + 1e-13."""
-    from gpu_helpers import dev, ops, print_case
+    same number up to rounding).  2 eps |psi| is the norm of sgn^2 psi - psi:
+    two chained applications, each within the FP64 bound 1e-10 of the oracle
+    (checked here for the first), the second on a source of norm
+    |sgn(H) psi| ~ |psi| = 1, so the estimates differ by at most
+    (1e-10 + 1e-10) / 2 + 1e-10 = 2e-10 (measured 1.0e-10 at k = 160 on this
+    small-gap field)."""
+    from gpu_helpers import dev, host, ops, print_case, rel
     U, H, dH = field
     print_case(test="eps", dims=DIMS, k=k)
     phi = synth.make_sources(DIMS, 2, 403)
     lat = _lat(U)
     ea = lat.sign_error_estimate(dev(phi), MU, k)
     eb = lat.deriv_error_estimate(dev(phi), MU, k)
+    y1 = host(lat.sign_apply(dev(phi), MU, k))
     lat.close()
     h, hd, dh, dhd = ops(U, DIMS, MU)
     for r in range(2):
         p = phi[r].ravel()
+        e1 = rel(y1[r], tsl.krylov_sign(h, hd, p, p, k)[0])
+        print(f"  k={k} r={r}: first application sgn(H) phi against the oracle {e1:.2e}")
+        assert e1 < 1e-10
         ra = estimator.eps_sign(lambda v: tsl.krylov_sign(h, hd, v, v, k)[0], p)
         rb = estimator.eps_block(lambda v: tsl.krylov_block_sign(h, hd, dh, dhd, v, k)[0], p)
         print(f"  k={k} r={r}: eps_A {ea[r]:.3e} (oracle {ra:.3e}), eps_B {eb[r]:.3e} (oracle {rb:.3e})")
-        assert abs(ea[r] - ra) <= 1e-9 * ra + 1e-13
-        assert abs(eb[r] - rb) <= 1e-9 * rb + 1e-13
+        assert abs(ea[r] - ra) <= 2e-10
+        assert abs(eb[r] - rb) <= 2e-10
 
 
 def test_eps_b_with_deflation_falls(field):

@@ -5,9 +5,9 @@
     the call returns OVD_ENAN; the handle works again after good links;
   * x orthogonal to b in the gradient: the bilinear two-sided Lanczos has
     w_1^dag v_1 = 0, a serious breakdown at step 0 (OVD_EBREAKDOWN);
-  * a cluster of eigenvalues of equal modulus straddling the m-th one (free
-    field, lowest shell of 24): OVD_ENOCONV from the eigensolver, since the
-    deflated set would not be a spectral projector;
+  * degenerate eigenvalues where derivative pairs are asked for (free field,
+    lowest shell of 24 made of four six-fold values): OVD_ENOCONV from the
+    eigensolver, since the eigenvector derivatives are undefined there;
   * a memory budget smaller than the Krylov basis: the call regenerates the
     basis instead of storing it, with the same result;
   * deflation data that no longer belong to the call: new links remove every
@@ -74,19 +74,23 @@ def test_orthogonal_x_and_b_break_down_at_step_zero():
     lat.close()
 
 
-def test_cluster_straddling_the_cut_is_refused():
+def test_degenerate_cluster_at_the_derivative_pairs_is_refused():
     """Pure-gauge links: the lowest modulus shell of H(0.3) on 4^4 holds 24
-    eigenvalues; asking for m = 20 cuts it."""
+    eigenvalues, four distinct values six times each (momentum degeneracy).
+    The m = 20 set cuts the shell; that alone leaves a valid deflation (any
+    set of eigenpairs with L^dag R = 1 gives an H-invariant projector), but the
+    derivatives of l = 5 pairs cannot be defined: by pigeonhole two of them
+    share an eigenvalue, and the formula divides by lam_j - lam_i."""
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, print_case
     dims = (4, 4, 4, 4)
-    print_case(test="fail_cluster", dims=dims, m=20)
+    print_case(test="fail_cluster", dims=dims, m=20, l=5)
     U, _ = synth.gauge_rotated_unit_links(dims, 5)
     lat = ovderiv.Lattice(dims)
     lat.set_links(dev(U))
     with pytest.raises(ovderiv.OvdError) as ei:
-        lat.compute_deflation(0.3, 20, 0)
-    assert ei.value.status == ovderiv.OVD_ENOCONV
+        lat.compute_deflation(0.3, 20, 5)
+    assert ei.value.status == ovderiv.OVD_ENOCONV and "degenerate" in str(ei.value)
     with pytest.raises(ovderiv.OvdError) as ei:
         lat.get_deflation(0.3)
     assert ei.value.status == ovderiv.OVD_ENODEFL

@@ -83,3 +83,28 @@ def test_krylov_vjp_converges_to_dense(setup):
     assert err_s[1] < err_s[0] and err_s[1] < 1e-12
     assert err_d[1] < err_d[0] and err_d[1] < 1e-7
     assert err_F[1] < err_F[0] and err_F[1] < 1e-8
+
+
+def test_deflated_krylov_vjp_against_dense():
+    """The deflated gradient (12 eigenpairs of the rough 4x2x2x4 field, dense
+    eigen-data) converges to the dense gradient, faster than the undeflated
+    form (measured at k = 256: ds/dmu 1.3e-6 against 4.3e-4, force 2.4e-6
+    against 4.0e-4; at k = 600 all below 1e-12), and with no pairs it is the
+    undeflated form."""
+    from oracle import deflation
+    dims = (4, 2, 2, 4)
+    U = synth.make_links(dims, 1.0, 301)
+    x = synth.make_source(dims, 42).ravel()
+    b = synth.make_source(dims, 43).ravel()
+    s, dsdmu, F = vjp.dense_vjp(U, dims, MU, x, b)
+    H = dirac.dense_h(U, dims, MU)
+    lam, R, L = deflation.eigpairs_dense(H, 12)
+    err = lambda o: (abs(o[0] - s) / abs(s), abs(o[1] - dsdmu) / abs(dsdmu), np.abs(o[2] - F).max() / np.abs(F).max())
+    e_u = err(vjp.krylov_vjp(U, dims, MU, x, b, 256))
+    e_d = err(vjp.krylov_vjp_deflated(U, dims, MU, x, b, 256, lam, R, L))
+    assert all(d < 0.05 * u for d, u in zip(e_d, e_u)), (e_d, e_u)
+    e_600 = err(vjp.krylov_vjp_deflated(U, dims, MU, x, b, 600, lam, R, L))
+    assert max(e_600) < 1e-10, e_600
+    o0 = vjp.krylov_vjp(U, dims, MU, x, b, 48)
+    o1 = vjp.krylov_vjp_deflated(U, dims, MU, x, b, 48, lam[:0], R[:, :0], L[:, :0])
+    assert abs(o1[0] - o0[0]) < 1e-14 and abs(o1[1] - o0[1]) < 1e-14 and np.abs(o1[2] - o0[2]).max() < 1e-14
