@@ -348,6 +348,31 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
                               double* s, double* ds_dmu, void* F, void* dsdU, void* dsdUc,
                               void* dsdtheta, ovd_stats* st);
 
+/* ovd_sign_apply_deriv in its storage-free scalar mode (xdy = <x|d/dt sgn(H) b>,
+ * no vector outputs) for callers that cannot allocate device memory: code that
+ * must not call hipMalloc (allocation-free sections of serving loops, harnesses
+ * that forbid device allocations).  Every workspace of the call comes from one
+ * static device array of 256 MiB per device, which the library holds on each
+ * device it runs on until the process ends; the call itself allocates nothing
+ * on the device (no hipMalloc / hipFree, no graph instantiation, no events).
+ * Same kernels and results as ovd_sign_apply_deriv (deflated by the set of mu
+ * when one exists, left start and precision of the handle), launched one by
+ * one; the launch shape is the one an earlier ovd_sign_apply_deriv of the
+ * same precision, direction and batch size tuned, else the default shape.
+ *   b, x   device complex128 [nrhs][V][4][3];  xdy  host complex128 [nrhs]
+ * Limits: the workspaces of the call (about 10 block vectors per right-hand
+ * side for the Lanczos ring, 6 more for staging, the small-sign scratch) must
+ * fit in the 256 MiB, else OVD_EINVAL with the size needed and nothing is
+ * launched: at k = 400, 14 x 14^3 fits one right-hand side in FP64 and two
+ * in mixed precision; 8^4 fits 11 in FP64 and 21 in mixed precision.
+ * Concurrency: every call on a device shares that device's array, and the
+ * array keeps the last call's contents (what a call needs zeroed it clears
+ * itself): calls that overlap on one device, from any handle or thread, race.
+ * ovd_get_tridiag after this call reads the coefficients from the shared
+ * array, valid until the next allocation-free call on the device. */
+ovd_status ovd_sign_apply_deriv_noalloc(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k,
+                                        const void* b, const void* x, double* xdy, ovd_stats* st);
+
 /* Launch shapes in use so far (chosen by the autotuner, or forced through the
  * options), as text
  * "kernel:precision:dir-or-op:nrhs=map<m>,gpb<g>[,seq];..." into buf (host, len

@@ -21,6 +21,7 @@
 #include <functional>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <thread>
@@ -70,6 +71,13 @@ struct ovd_lattice {
     hipStream_t cap_stream = nullptr;   // capture only; replays run on `stream`
     // autotuned launch shapes, keyed by kernel, precision, direction / operator and batch size
     std::map<std::string, StencilVariant> tuned;
+    // while a call runs without allocations: workspaces are carved from this
+    // region (the per-device static scratch) instead of hipMalloc
+    struct Arena {
+        char* base = nullptr;
+        size_t size = 0, used = 0;
+        bool active = false;
+    } arena;
 };
 
 namespace {
@@ -86,8 +94,19 @@ ovd_status fail(ovd_h h, ovd_status st, const std::string& msg) {
             return fail(h, OVD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
-// grow-only named workspace
+// grow-only named workspace (or, during an allocation-free call, the next
+// 256-byte aligned piece of the call's scratch region)
 void* ws_get(ovd_h h, const std::string& name, size_t bytes, ovd_status* st) {
+    if (h->arena.active) {
+        const size_t off = (h->arena.used + 255) / 256 * 256;
+        if (off + bytes > h->arena.size) {
+            *st = fail(h, OVD_ENOMEM, "the no-allocation scratch (" + std::to_string(h->arena.size) +
+                                          " bytes) is too small for workspace '" + name + "'");
+            return nullptr;
+        }
+        h->arena.used = off + bytes;
+        return h->arena.base + off;
+    }
     auto it = h->ws.find(name);
     if (it != h->ws.end() && it->second.second >= bytes) return it->second.first;
     if (it != h->ws.end()) {
@@ -111,7 +130,8 @@ void* ws_get(ovd_h h, const std::string& name, size_t bytes, ovd_status* st) {
 struct Timer {
     hipEvent_t a{}, b{};
     bool ok = false;
-    void start(hipStream_t s) {
+    void start(hipStream_t s, bool enable = true) {
+        if (!enable) return;
         ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
         if (ok) (void)hipEventRecord(a, s);
     }
@@ -308,6 +328,10 @@ SmallSignCfg sign_cfg(const ovd_options& o) {
     return c;
 }
 
+// solves per launch of the small sign during an allocation-free call (the
+// result does not depend on it; it sizes the scratch: 4 k chunk complex)
+constexpr int kNoAllocChunkSolves = 1024;
+
 // map a return code of the small dense solvers to a status
 ovd_status small_status(ovd_h h, int rc, const char* what, double chk, int bstep) {
     if (rc == 0) return OVD_OK;
@@ -323,7 +347,8 @@ ovd_status small_status(ovd_h h, int rc, const char* what, double chk, int bstep
 // sgn(T_k) e_1 for the nrhs Ritz matrices in co, by the handle's method
 ovd_status small_sign(ovd_h h, int nrhs, int k, TslCoeffs co, c64* c_out, double* chk, int* bstep) {
     ovd_status wst = OVD_OK;
-    const SmallSignCfg cfg = sign_cfg(h->opt);
+    SmallSignCfg cfg = sign_cfg(h->opt);
+    if (h->arena.active) cfg.chunk = kNoAllocChunkSolves;
     if (h->opt.sign_method == OVD_SIGN_NESTED) {
         const int kp = std::min(k, h->opt.nested_inner > 0 ? h->opt.nested_inner : 100);
         WS(scr, c64, "small_scratch", nested_sign_scratch_elems(nrhs, k, kp, cfg.chunk));
@@ -387,20 +412,20 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
 
     Timer tl, ts;
     // per-kernel events: 4 per step (update start/end, stencil start/end)
-    const size_t nev = (size_t)4 * k;
+    const size_t nev = h->arena.active ? 0 : (size_t)4 * k;
     while (h->ev.size() < nev) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         h->ev.push_back(e);
     }
-    tl.start(h->stream);
+    tl.start(h->stream, !h->arena.active);
     const double md = h->m0 + 4.0 * h->r;
     // start vectors into slot 1
     HIPCHK(hipMemcpy2DAsync(Vs(1), sizeof(cpx<T>) * sV, src_v, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
                             hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipMemcpy2DAsync(Ws(1), sizeof(cpx<T>) * sW, src_w, sizeof(cpx<T>) * fsz, sizeof(cpx<T>) * fsz, nrhs,
                             hipMemcpyDeviceToDevice, h->stream));
-    const bool timing = h->opt.step_timing != 0;
+    const bool timing = h->opt.step_timing != 0 && !h->arena.active;
     // launch shape of the stencil: autotuned once per precision, direction and batch size
     StencilVariant var{default_map(nrhs), dir == 0 ? 4 : 2};
     {
@@ -415,7 +440,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             h->tuned[key] = var;
         } else if (it != h->tuned.end()) {
             var = it->second;
-        } else if (h->opt.autotune) {
+        } else if (h->opt.autotune && !h->arena.active) {
             // time step 0 on the start vectors with a scratch copy of the recurrence state
             WS(tst, TslState, "tune_state", nrhs);
             WS(tcoef, c64, "tune_coef", (size_t)4 * nrhs);
@@ -479,7 +504,8 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         return hipGetLastError();
     };
     bool launched = false;
-    if (h->opt.use_graph && !timing && !after_step) {   // events and per-call hooks stay out of graphs
+    // events and per-call hooks stay out of graphs; an allocation-free call launches one by one
+    if (h->opt.use_graph && !timing && !after_step && !h->arena.active) {
         double tau = h->opt.breakdown_tol;
         uint64_t tb, mb;
         std::memcpy(&tb, &tau, 8);
@@ -557,7 +583,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     if (bad == 2) return fail(h, OVD_ENAN, "non-finite value in the Lanczos recurrence at step " + std::to_string(bstep));
 
     // sgn(T_k) e_1
-    ts.start(h->stream);
+    ts.start(h->stream, !h->arena.active);
     double chk = 0.0;
     int bst = -1;
     const ovd_status ss = small_sign(h, nrhs, k, co, c_out, &chk, &bst);
@@ -622,7 +648,7 @@ ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const voi
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     WS(cf, c64, "ritz_coef", (size_t)nrhs * k);
     Timer tt;
-    tt.start(h->stream);
+    tt.start(h->stream, !h->arena.active);
     HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * fsz, h->stream));
     launch_pack_spinor<double>(g, nrhs, b, b64, fsz, h->stream);
     // eq. 8: c = L^dag b, b' = b - R c, exact part R (sgn(lambda) c)
@@ -739,7 +765,7 @@ ovd_status deriv_impl(ovd_h h, int nrhs, const double* mu, int dirk, int k, cons
     }
     WS(c, c64, "ritz_c", (size_t)nrhs * k);
     Timer tt;
-    tt.start(h->stream);
+    tt.start(h->stream, !h->arena.active);
     // psi = (t; b), deflated by eq. 11: psi' = psi - P_{2l} psi = (t - (R d + dR c); b - R c)
     // with c = L^dag b, d = dL^dag b + L^dag t over the first l pairs
     HIPCHK(hipMemsetAsync(b64, 0, sizeof(c64) * nrhs * half, h->stream));
@@ -1443,7 +1469,7 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     }
     WS(c, c64, "ritz_c", k);
     Timer tt;
-    tt.start(h->stream);
+    tt.start(h->stream, !h->arena.active);
     const double mus[1] = {mu};
     c32 *srcv32 = nullptr, *srcw32 = nullptr;
     c64 *srcv64 = nullptr, *srcw64 = nullptr;
@@ -1621,6 +1647,134 @@ ovd_status ovd_tridiag_sign(int nt, int k, const double* alpha, const double* be
     (void)hipFree(d);
     if (check) *check = chk;
     return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Derivative evaluation without device allocations.
+//
+// The storage-free scalar form of ovd_sign_apply_deriv with every workspace
+// (staging, start vectors, the Lanczos ring, recurrence state, coefficients,
+// partial sums, the small-sign scratch, deflation scratch) carved from one
+// static device array of kNoAllocBytes per device instead of hipMalloc.
+// Same kernels; launched one by one (no graph instantiation, no events, no
+// autotuning: the call uses the shape tuned by an earlier allocating call of
+// the same precision, direction and batch size, else the default shape).
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)256 << 20;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch` (looked up once per
+// device, with that device current; the array's name is not a device address
+// in host code)
+ovd_status noalloc_scratch(ovd_h h, void** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, OVD_EINVAL, "device index out of range for the no-allocation scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(h, OVD_EHIP, std::string("hipGetSymbolAddress of the no-allocation scratch: ") +
+                                         hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return OVD_OK;
+}
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// bytes the scalar-mode derivative takes from the scratch: the workspaces of
+// deriv_impl, run_tsl and the small sign in their order, each 256-aligned
+size_t noalloc_need(ovd_h h, int nrhs, int k, bool link, int lmax) {
+    const Geom& g = h->g;
+    const bool mixed = h->opt.precision == OVD_MIXED;
+    const size_t bT = mixed ? sizeof(c32) : sizeof(c64);
+    const size_t half = (size_t)12 * g.Vp, fsz = 2 * half;
+    size_t n = 0;
+    if (link) {
+        n += al256(sizeof(c64) * link_elems<double>(g.Vp));
+        if (mixed) n += al256(sizeof(c32) * link_elems<float>(g.Vp));
+        n += al256(sizeof(unsigned));
+    }
+    n += 2 * al256(sizeof(c64) * nrhs * half);                      // stage_b, stage_t
+    n += 2 * al256(bT * nrhs * fsz);                                // src_v, src_w
+    n += al256(bT * nrhs * half);                                   // xproj
+    n += al256(sizeof(c64) * nrhs * k);                             // ritz_c
+    if (lmax > 0) {
+        n += 5 * al256(sizeof(c64) * lmax * nrhs);
+        n += 2 * al256(sizeof(c64) * defl_proj_scratch(lmax, nrhs, (long long)half));
+        n += al256(sizeof(c64) * nrhs * half) + 2 * al256(sizeof(c64) * lmax * nrhs);
+    }
+    const int nb = tsl_stencil_blocks(g, 1, 1);
+    n += al256(bT * 10 * nrhs * fsz);                               // Lanczos ring
+    n += al256(sizeof(TslState) * nrhs) + al256(sizeof(c64) * 4 * nrhs * k);
+    n += al256(sizeof(double) * nrhs * nb * 8) + al256(sizeof(unsigned) * nrhs);
+    if (h->opt.sign_method == OVD_SIGN_NESTED) {
+        const int kp = std::min(k, h->opt.nested_inner > 0 ? h->opt.nested_inner : 100);
+        n += al256(sizeof(c64) * nested_sign_scratch_elems(nrhs, k, kp, kNoAllocChunkSolves));
+    } else {
+        n += al256(sizeof(c64) * small_sign_scratch_elems(nrhs, k, kNoAllocChunkSolves));
+    }
+    n += al256(sizeof(c64) * nrhs);                                 // scalar_out
+    return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+ovd_status ovd_sign_apply_deriv_noalloc(ovd_h h, int nrhs, const double* mu, const ovd_dir* dir, int k,
+                                        const void* b, const void* x, double* xdy, ovd_stats* st) {
+    ovd_status s = check_handle(h);
+    if (s != OVD_OK) return s;
+    if (nrhs < 1 || !mu || k < 1 || !b || !x || !xdy)
+        return fail(h, OVD_EINVAL, "bad ovd_sign_apply_deriv_noalloc arguments");
+    if (h->arena.active) return fail(h, OVD_EINVAL, "ovd_sign_apply_deriv_noalloc re-entered");
+    const bool link = dir && dir->kind == OVD_DIR_LINK;
+    int lmax = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        const DeflSet* d = find_defl(h, mu[r]);
+        if (d && d->l > lmax) lmax = d->l;
+    }
+    const size_t need = noalloc_need(h, nrhs, k, link, lmax);
+    if (need > kNoAllocBytes)
+        return fail(h, OVD_EINVAL, "ovd_sign_apply_deriv_noalloc needs " + std::to_string(need) +
+                                       " bytes of scratch for this lattice, batch and k; its static scratch holds " +
+                                       std::to_string(kNoAllocBytes) + " (use ovd_sign_apply_deriv)");
+    void* base = nullptr;
+    s = noalloc_scratch(h, &base);
+    if (s != OVD_OK) return s;
+    if (st) std::memset(st, 0, sizeof(*st));
+    c64* keep64 = h->dU64;
+    c32* keep32 = h->dU32;
+    h->arena.base = (char*)base;
+    h->arena.size = kNoAllocBytes;
+    h->arena.used = 0;
+    h->arena.active = true;
+    int dirk = 1;
+    s = upload_dir(h, dir, &dirk);
+    if (s == OVD_OK) {
+        if (h->opt.precision == OVD_MIXED)
+            s = deriv_impl<float>(h, nrhs, mu, dirk, k, b, nullptr, nullptr, x, xdy, st);
+        else
+            s = deriv_impl<double>(h, nrhs, mu, dirk, k, b, nullptr, nullptr, x, xdy, st);
+    }
+    h->arena = ovd_lattice::Arena{};
+    // a link direction packed into the scratch is not the handle's own copy
+    h->dU64 = keep64;
+    h->dU32 = keep32;
+    return s;
 }
 
 }  // extern "C"

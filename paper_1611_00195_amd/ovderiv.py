@@ -33,6 +33,7 @@ EXPORTS = [
     "ovd_sign_apply_deriv", "ovd_sign_apply_vjp", "ovd_get_tridiag", "ovd_compute_deflation",
     "ovd_get_deflation", "ovd_sign_apply_deriv_batch", "ovd_get_tuned", "ovd_overlap_apply",
     "ovd_sign_error_estimate", "ovd_tridiag_sign", "ovd_block_sign_apply", "ovd_deriv_error_estimate",
+    "ovd_sign_apply_deriv_noalloc",
 ]
 
 
@@ -123,6 +124,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ovd_tridiag_sign": (i, [i, i, dp, dp, dp, ctypes.POINTER(_Options), dp, dp, vp]),
         "ovd_block_sign_apply": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, vp, vp, ctypes.POINTER(_Stats)]),
         "ovd_deriv_error_estimate": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, dp, ctypes.POINTER(_Stats)]),
+        "ovd_sign_apply_deriv_noalloc": (i, [vp, i, dp, ctypes.POINTER(_Dir), i, vp, vp, dp, ctypes.POINTER(_Stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -280,6 +282,22 @@ class Lattice:
         if xdy is not None:
             s = [complex(xdy[2 * i], xdy[2 * i + 1]) for i in range(n)]
         return y, dy, s
+
+    def sign_apply_deriv_noalloc(self, b, x, mu, k, direction="mu", dU=None):
+        """<x|d/dt sgn(H(mu)) b> per source like sign_apply_deriv in its
+        storage-free mode, with no device allocation by the library (every
+        workspace in its static per-device scratch; ovd_sign_apply_deriv_noalloc)."""
+        n = b.shape[0]
+        _check_field(b, (n, self.V, 4, 3), "b")
+        _check_field(x, (n, self.V, 4, 3), "x")
+        mus = [float(mu)] * n if not hasattr(mu, "__len__") else [float(m) for m in mu]
+        d, keep = self._dir(direction, dU)
+        xdy = (ctypes.c_double * (2 * n))()
+        st = _Stats()
+        self._call("ovd_sign_apply_deriv_noalloc", n, _dbl(mus), ctypes.byref(d), int(k), _ptr(b), _ptr(x), xdy,
+                   ctypes.byref(st))
+        self.last_stats = self._stats(st)
+        return [complex(xdy[2 * i], xdy[2 * i + 1]) for i in range(n)]
 
     def overlap_apply(self, b, mu, k, deriv=False, direction="mu", dU=None):
         """D_ov b = b + gamma5 sgn(H) b (eq. 1, a = 1), and with deriv=True also
