@@ -121,6 +121,8 @@ typedef struct {
     long long mem_budget;   /* > 0: with basis_recompute = -1, the bytes a stored Krylov basis may
                                take; a larger one is regenerated instead (as when it does not
                                fit in free device memory); 0 (default): no budget */
+    int eig_shift_max;      /* ovd_compute_deflation: iteration limit of each shifted solve for the
+                               eigenvector derivatives (CGLS); 0: 60000 */
 } ovd_options;
 
 typedef struct {
@@ -328,7 +330,15 @@ ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs);
  * start b and left start x (precision below),
  * s ~ (x^dag b)[sgn(T_k)]_11, and with M_k = L_sgn(T_k, e_1 e_1^T) the
  * derivative ds/dt ~ (x^dag b) tr(M_k W_k^dag (dH/dt) V_k), evaluated for every
- * link at once through Z = W_k M_k^dag.  Deflation is not applied.
+ * link at once through Z = W_k M_k^dag.
+ * Deflation (Sec. 3, eq. 8): when the handle holds a set for mu, its m pairs
+ * are deflated.  The run then starts from b' = (1 - P) b and x' = (1 - P)^dag x,
+ * s = x'^dag sgn(H) b' + sum_i sgn(lambda_i)(x^dag R_i)(L_i^dag b), and the
+ * Frechet kernel K = L_sgn(H, b x^dag) gains 2 m rank-one terms: the cross
+ * terms between the deflated set and its complement through the Krylov-Ritz
+ * form of g_j(z) = (sgn z - sgn lambda_j)/(z - lambda_j) on the two bases, and
+ * the exact part within the set (divided differences of sgn over the pairs).
+ * Only lambda, R and L are used (not dR, dL).
  *   x, b      device complex128 [V][4][3]
  *   s, ds_dmu host complex128 [1], nullable
  *   F         device complex128 [4][V][3][3] or NULL: per-link force with

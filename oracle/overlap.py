@@ -6,8 +6,9 @@ not depend on t).
 
 Pinned by (tests/test_oracle_overlap.py): the Ginsparg-Wilson relation
 gamma5 D + D gamma5 = D gamma5 D (which holds for any S with S^2 = 1), the
-eigenvalues of D at mu = 0 on the circle |z - 1| = 1, and gamma5-hermiticity
-D^dag = gamma5 D gamma5 at mu = 0.
+eigenvalues of D at mu = 0 on the circle |z - 1| = 1, gamma5-hermiticity
+D^dag = gamma5 D gamma5 at mu = 0, and the Krylov derivative converging to
+gamma5 times the dense Frechet derivative of the sign.
 """
 from __future__ import annotations
 

@@ -704,6 +704,20 @@ ovd_status sign_apply_impl(ovd_h h, int nrhs, const double* mu, int k, const voi
     return OVD_OK;
 }
 
+// s = (x'^dag b') [sgn(T_k)]_11 + sum_i sgn(lambda_i) conj(d_i) c_i (one thread)
+__global__ void vjp_value_kernel(TslCoeffs co, const c64* __restrict__ c, int m, const double* __restrict__ sg,
+                                 const c64* __restrict__ cv, const c64* __restrict__ dv, c64* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    c64 v = (co.beta[0] * co.delta[0]) * c[0];
+    for (int i = 0; i < m; ++i) v += sg[i] * (conj(dv[i]) * cv[i]);
+    *out = v;
+}
+
+void launch_vjp_value(TslCoeffs co, const c64* c, int m, const double* sg, const c64* cv, const c64* dv, c64* out,
+                      hipStream_t s) {
+    vjp_value_kernel<<<1, 64, 0, s>>>(co, c, m, sg, cv, dv, out);
+}
+
 // a[i] += b[i] for n complex
 __global__ void cadd_kernel(int n, c64* __restrict__ a, const c64* __restrict__ b) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -897,7 +911,7 @@ ovd_status upload_dir(ovd_h h, const ovd_dir* dir, int* dirk) {
 bool options_ok(const ovd_options& o) {
     return (o.precision == OVD_FP64 || o.precision == OVD_MIXED) && o.quad_max_levels >= 0 &&
            o.quad_max_levels <= kMaxLevelsLimit && (o.sign_method == OVD_SIGN_QUAD || o.sign_method == OVD_SIGN_NESTED) &&
-           o.nested_inner >= 0 && o.mem_budget >= 0;
+           o.nested_inner >= 0 && o.mem_budget >= 0 && o.eig_shift_max >= 0;
 }
 
 extern "C" {
@@ -935,6 +949,7 @@ ovd_status ovd_create_lattice(const int dims[4], double m0, double r, int t_bc, 
     h->opt.sign_method = OVD_SIGN_QUAD;
     h->opt.nested_inner = 0;
     h->opt.mem_budget = 0;
+    h->opt.eig_shift_max = 0;
     if (opt) {
         if (!options_ok(*opt)) {
             delete h;
@@ -1355,6 +1370,7 @@ ovd_status ovd_compute_deflation(ovd_h h, double mu, int m, int l, const ovd_dir
     P.l = l;
     P.dir_link = dk == 2;
     if (tol > 0) P.tol = tol;
+    if (h->opt.eig_shift_max > 0) P.shift_max = h->opt.eig_shift_max;
     P.stream = h->stream;
     EigResult R;
     const int rc = eigs_compute(P, R);
@@ -1447,6 +1463,8 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     const long long fsz = (long long)12 * g.Vp;
     const bool mixed = h->opt.precision == OVD_MIXED;
     const bool grad = ds_dmu || F || dsdU || dsdUc || dsdtheta;
+    const DeflSet* dset = find_defl(h, mu);
+    const int md = dset ? dset->m : 0;
     // stored form: both bases and Z (3 k FP64 fields, plus the two FP32 bases
     // in mixed precision); recompute form: the left basis only (turned into Z
     // in place), the right basis regenerated by a second, identical run
@@ -1459,8 +1477,6 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         if (wst != OVD_OK) return wst;
     }
     if (st) st->basis_recomputed = recompute ? 1 : 0;
-    // bilinear two-sided Lanczos: right start b, left start x (FP64, or FP32
-    // vectors for OVD_MIXED, widened to FP64 for the gradient)
     WS(bw, c64, "vjp_basis_w", (size_t)k * fsz);
     c64* bv = nullptr;
     if (!recompute) {
@@ -1471,8 +1487,32 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     Timer tt;
     tt.start(h->stream, !h->arena.active);
     const double mus[1] = {mu};
+    // sources in FP64: b' = (1 - P) b and x' = (1 - P)^dag x when the m pairs of
+    // the set for mu are deflated (eq. 8): c = L^dag b, d = R^dag x
+    WS(srcv64, c64, "vjp_src_v", fsz);
+    WS(srcw64, c64, "vjp_src_w", fsz);
+    HIPCHK(hipMemsetAsync(srcv64, 0, sizeof(c64) * fsz, h->stream));
+    HIPCHK(hipMemsetAsync(srcw64, 0, sizeof(c64) * fsz, h->stream));
+    launch_pack_spinor<double>(g, 1, b, srcv64, fsz, h->stream);
+    launch_pack_spinor<double>(g, 1, x, srcw64, fsz, h->stream);
+    c64 *cvec = nullptr, *dvec = nullptr;
+    if (md > 0) {
+        WS(cv, c64, "vjp_defl_c", md);
+        WS(dv, c64, "vjp_defl_d", md);
+        WS(tmp, c64, "vjp_defl_tmp", md);
+        WS(pscr, c64, "defl_scr", defl_proj_scratch(md, 1, fsz));
+        cvec = cv;
+        dvec = dv;
+        launch_defl_proj(dset->L, fsz, md, srcv64, fsz, 1, fsz, cv, pscr, h->stream);
+        launch_defl_proj(dset->R, fsz, md, srcw64, fsz, 1, fsz, dv, pscr, h->stream);
+        launch_defl_scale(md, 1, dset->ones, cv, tmp, -1.0, h->stream);
+        launch_defl_comb(dset->R, fsz, md, tmp, 1, srcv64, fsz, fsz, h->stream);   // b' = b - R c
+        launch_defl_scale(md, 1, dset->ones, dv, tmp, -1.0, h->stream);
+        launch_defl_comb(dset->L, fsz, md, tmp, 1, srcw64, fsz, fsz, h->stream);   // x' = x - L d
+    }
+    // bilinear two-sided Lanczos: right start b', left start x' (FP64, or FP32
+    // vectors for OVD_MIXED, widened to FP64 for the gradient)
     c32 *srcv32 = nullptr, *srcw32 = nullptr;
-    c64 *srcv64 = nullptr, *srcw64 = nullptr;
     if (mixed) {
         WS(srcv, c32, "vjp_src_v32", fsz);
         WS(srcw, c32, "vjp_src_w32", fsz);
@@ -1484,42 +1524,30 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         }
         srcv32 = srcv;
         srcw32 = srcw;
-        HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c32) * fsz, h->stream));
-        HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c32) * fsz, h->stream));
-        launch_pack_spinor<float>(g, 1, b, srcv, fsz, h->stream);
-        launch_pack_spinor<float>(g, 1, x, srcw, fsz, h->stream);
+        launch_convert_field<float>(g, 1, srcv64, fsz, srcv, fsz, h->stream);
+        launch_convert_field<float>(g, 1, srcw64, fsz, srcw, fsz, h->stream);
         s = run_tsl<float>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv32, c, st, bw32);
         if (s != OVD_OK) return s;
         if (bv32) launch_widen_field(g, k, bv32, fsz, bv, fsz, h->stream);
         launch_widen_field(g, k, bw32, fsz, bw, fsz, h->stream);
         HIPCHK(hipGetLastError());
     } else {
-        WS(srcv, c64, "vjp_src_v", fsz);
-        WS(srcw, c64, "vjp_src_w", fsz);
-        srcv64 = srcv;
-        srcw64 = srcw;
-        HIPCHK(hipMemsetAsync(srcv, 0, sizeof(c64) * fsz, h->stream));
-        HIPCHK(hipMemsetAsync(srcw, 0, sizeof(c64) * fsz, h->stream));
-        launch_pack_spinor<double>(g, 1, b, srcv, fsz, h->stream);
-        launch_pack_spinor<double>(g, 1, x, srcw, fsz, h->stream);
-        s = run_tsl<double>(h, 1, k, 0, mus, srcv, srcw, nullptr, bv, c, st, bw);
+        s = run_tsl<double>(h, 1, k, 0, mus, srcv64, srcw64, nullptr, bv, c, st, bw);
         if (s != OVD_OK) return s;
     }
     const TslCoeffs co = h->last_co;
-    // s = (x^dag b) [sgn(T_k)]_11, x^dag b = beta_0 delta_0
-    c64 c0, b0, d0;
-    HIPCHK(hipMemcpyAsync(&c0, c, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(&b0, co.beta, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(&d0, co.delta, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
+    // s = (x'^dag b') [sgn(T_k)]_11 + sum_i sgn(lambda_i) conj(d_i) c_i, x'^dag b' = beta_0 delta_0
+    WS(sdev, c64, "vjp_s", 1);
+    launch_vjp_value(co, c, md, dset ? dset->sgn : nullptr, cvec, dvec, sdev, h->stream);
+    c64 sv;
+    HIPCHK(hipMemcpyAsync(&sv, sdev, sizeof(c64), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    const c64 xb = b0 * d0;
     if (s_out) {
-        const c64 sv = xb * c0;
         s_out[0] = sv.re;
         s_out[1] = sv.im;
     }
     if (grad) {
-        // M = L_sgn(T_k, e_1 e_1^T), M' = (x^dag b) M / (delta_p beta_q), Z = W-hat M'^dag
+        // M = L_sgn(T_k, e_1 e_1^T), M' = (x'^dag b') M / (delta_p beta_q), Z = W-hat M'^dag
         WS(scr, c64, "frechet_scr", small_frechet_scratch_elems(k));
         WS(M, c64, "vjp_M", (size_t)k * k);
         WS(Mp, c64, "vjp_Mp", (size_t)k * k);
@@ -1531,11 +1559,48 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         s = small_status(h, frc, "L_sgn(T_k, e_1 e_1^T)", chk, -1);
         if (s != OVD_OK) return s;
         launch_vjp_scale_m(k, co, M, Mp, h->stream);
+        // deflated: the cross and exact parts of the Frechet kernel as 2 m more
+        // (v, z) pairs: (V-hat A, L_j) and (R_i, W-hat B + L Cm)
+        c64 *AV = nullptr, *ZW = nullptr, *Amat = nullptr;
+        const bool last_krylov = md == 0;
+        c64* Kacc = nullptr;
+        if (recompute || md > 0) {
+            WS(ka, c64, "vjp_kacc", (size_t)18 * 4 * g.V);
+            Kacc = ka;
+        }
+        if (md > 0) {
+            WS(srow, c64, "vjp_sgn_row", k);
+            WS(sscr, c64, "small_scratch", small_sign_scratch_elems(1, k, kDefaultChunkSolves));
+            WS(lamd, c64, "vjp_defl_lam", md);
+            WS(Am, c64, "vjp_defl_A", (size_t)k * md);
+            WS(Bm, c64, "vjp_defl_B", (size_t)k * md);
+            WS(Cm, c64, "vjp_defl_Cm", (size_t)md * md);
+            WS(cscr, c64, "vjp_defl_scr", defl_vjp_coef_scratch(k, md));
+            WS(av, c64, "vjp_defl_AV", (size_t)md * fsz);
+            WS(zw, c64, "vjp_defl_ZW", (size_t)md * fsz);
+            AV = av;
+            ZW = zw;
+            Amat = Am;
+            double chk2 = 0.0;
+            const int rrc = launch_small_sign(1, k, co, sign_cfg(h->opt), sscr, srow, &chk2, h->stream, 1);
+            if (st) st->sign_check = std::max(st->sign_check, chk2);
+            s = small_status(h, rrc, "sgn(T_k)^T e_1", chk2, -1);
+            if (s != OVD_OK) return s;
+            HIPCHK(hipMemcpyAsync(lamd, dset->lam.data(), sizeof(c64) * md, hipMemcpyHostToDevice, h->stream));
+            launch_defl_vjp_coef(k, co, md, lamd, dset->sgn, c, srow, cvec, dvec, Am, Bm, Cm, cscr, h->stream);
+            HIPCHK(hipMemsetAsync(av, 0, sizeof(c64) * md * fsz, h->stream));
+            HIPCHK(hipMemsetAsync(zw, 0, sizeof(c64) * md * fsz, h->stream));
+            // the left basis is still W-hat here (the recompute form turns it into Z below)
+            launch_defl_comb(bw, fsz, k, Bm, md, zw, fsz, fsz, h->stream);
+            launch_defl_comb(dset->L, fsz, md, Cm, md, zw, fsz, fsz, h->stream);
+            if (bv) launch_defl_comb(bv, fsz, k, Am, md, av, fsz, fsz, h->stream);
+            HIPCHK(hipGetLastError());
+        }
         if (!recompute) {
             WS(Z, c64, "vjp_Z", (size_t)k * fsz);
             launch_zgemm_wmh(bw, fsz, k, Mp, Z, fsz, fsz, h->stream);
-            launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF, (c64*)dsdtheta,
-                             h->stream);
+            launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
+                             (c64*)dsdtheta, h->stream, Kacc, true, last_krylov);
         } else {
             // Z over W in place, a slab of field elements at a time through a
             // k x E copy
@@ -1550,8 +1615,8 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
             // the Lanczos run again: same kernels, launch shape and inputs, so
             // the same right vectors, now in a ring of 2C; after every C steps
             // the C finished vectors enter the force sum (Kf, Kb carried in Kacc)
+            // and, deflated, the combinations V-hat A
             const int C = std::min(k, 32);
-            WS(Kacc, c64, "vjp_kacc", (size_t)18 * 4 * g.V);
             c32* ring32 = nullptr;
             c64* ring64 = nullptr;
             c64* chunk64 = nullptr;
@@ -1574,7 +1639,8 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
                 const c64* vch = ring64 ? ring64 + slot0 * fsz : chunk64;
                 if (ring32) launch_widen_field(g, n, ring32 + slot0 * fsz, fsz, chunk64, fsz, stream);
                 launch_vjp_force(g, n, vch, fsz, bw + (size_t)done * fsz, fsz, h->U64, emu, (c64*)F, (c64*)dsdU,
-                                 (c64*)dsdUc, trF, (c64*)dsdtheta, stream, Kacc, done == 0, avail == k);
+                                 (c64*)dsdUc, trF, (c64*)dsdtheta, stream, Kacc, done == 0, avail == k && last_krylov);
+                if (AV) launch_defl_comb(vch, fsz, n, Amat + (size_t)done * md, md, AV, fsz, fsz, stream);
                 done = avail;
             };
             ovd_stats st2{};
@@ -1583,6 +1649,14 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
             if (s != OVD_OK) return s;
             if (done != k) return fail(h, OVD_EHIP, "gradient: the regenerated basis did not reach step k");
             if (st) st->ms_lanczos += st2.ms_lanczos;
+        }
+        if (md > 0) {
+            // K_CD = sum_j (V-hat A)_j L_j^dag and K_DC + K_DD = sum_i R_i (W-hat B + L Cm)_i^dag
+            const double emu = std::exp(mu);
+            launch_vjp_force(g, md, AV, fsz, dset->L, fsz, h->U64, emu, (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
+                             (c64*)dsdtheta, h->stream, Kacc, false, false);
+            launch_vjp_force(g, md, dset->R, fsz, ZW, fsz, h->U64, emu, (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
+                             (c64*)dsdtheta, h->stream, Kacc, false, true);
         }
         launch_sum_c64(g.V, trF, dsum, h->stream);
         c64 dm;

@@ -679,4 +679,75 @@ int launch_nested_sign(int nrhs, int k, TslCoeffs co, int kp, double tau, const 
     return rc;
 }
 
+// ===========================================================================
+// Coefficients of the deflated gradient of <x|sgn(H)|b> (Sec. 3 deflation of
+// the bilinear two-sided Lanczos run with right start b' = (1 - P) b and left
+// start x' = (1 - P)^dag x).  With g_j(z) = (sgn z - s_j)/(z - lam_j):
+//   A[p][j] = delta_0 conj(d_j) [g_j(T) e_1]_p / delta_p      (the vectors
+//             |b'| (x^dag R_j) g_j(H) b' in the stored right basis),
+//   B[q][i] = conj(c_i beta_0 [g_i(T)^T e_1]_q / beta_q)      (the vectors
+//             conj((L_i^dag b)(x'^dag v_1)) W conj(g_i(T)^T e_1) in the left basis),
+// c_i = L_i^dag b, d_i = R_i^dag x; g_j(T) e_1 = (T - lam_j)^{-1} (sgn(T) e_1 - s_j e_1)
+// and g_i(T)^T e_1 = (T - lam_i)^{-T} (sgn(T)^T e_1 - s_i e_1), one pivoted
+// tridiagonal solve per thread.
+// ===========================================================================
+__global__ void defl_vjp_coef_kernel(int k, TslCoeffs co, int m, const c64* __restrict__ lam,
+                                     const double* __restrict__ sg, const c64* __restrict__ scol,
+                                     const c64* __restrict__ srow, const c64* __restrict__ cv,
+                                     const c64* __restrict__ dv, c64* __restrict__ A, c64* __restrict__ B,
+                                     c64* __restrict__ scr, int* __restrict__ ipiv) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * m) return;
+    const int side = t / m, j = t % m;
+    c64* base = scr + (size_t)t * 8 * k;
+    TriLU f{base, base + k, base + 2 * k, base + 3 * k, ipiv + (size_t)t * k};
+    c64* dg = base + 4 * k;      // diagonal, upper, lower of T - lam_j (or of its transpose)
+    c64* up = base + 5 * k;
+    c64* lo = base + 6 * k;
+    c64* x = base + 7 * k;
+    for (int i = 0; i < k; ++i) {
+        dg[i] = co.alpha[i] - lam[j];
+        const c64 bu = i + 1 < k ? co.beta[i + 1] : c64{0.0, 0.0};    // T[i][i+1]
+        const c64 dl = i + 1 < k ? co.delta[i + 1] : c64{0.0, 0.0};   // T[i+1][i]
+        up[i] = side == 0 ? bu : dl;
+        lo[i] = side == 0 ? dl : bu;
+        x[i] = (side == 0 ? scol[i] : srow[i]) - c64{i == 0 ? sg[j] : 0.0, 0.0};
+    }
+    tri_factor(k, dg, up, lo, f);
+    tri_solve(k, f, x);
+    const c64 b0 = co.beta[0];
+    const double d0 = co.delta[0].re;
+    for (int p = 0; p < k; ++p) {
+        if (side == 0) {
+            A[(size_t)p * m + j] = cdiv((d0 * conj(dv[j])) * x[p], co.delta[p]);
+        } else {
+            B[(size_t)p * m + j] = conj(cdiv(cv[j] * b0 * x[p], co.beta[p]));
+        }
+    }
+}
+
+// Cm[j][i] = conj(f_ij c_i) d_j, f_ij = (s_i - s_j) / (lam_i - lam_j) (0 when s_i = s_j)
+__global__ void defl_vjp_dd_kernel(int m, const c64* __restrict__ lam, const double* __restrict__ sg,
+                                   const c64* __restrict__ cv, const c64* __restrict__ dv, c64* __restrict__ Cm) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * m) return;
+    const int j = t / m, i = t % m;
+    c64 v{0.0, 0.0};
+    if (sg[i] != sg[j]) {
+        const c64 fij = cdiv(c64{sg[i] - sg[j], 0.0}, lam[i] - lam[j]);
+        v = conj(fij * cv[i]) * dv[j];
+    }
+    Cm[t] = v;
+}
+
+size_t defl_vjp_coef_scratch(int k, int m) { return (size_t)2 * m * 8 * k + (size_t)m * k; }
+
+void launch_defl_vjp_coef(int k, TslCoeffs co, int m, const c64* lam, const double* sg, const c64* scol,
+                          const c64* srow, const c64* cv, const c64* dv, c64* A, c64* B, c64* Cm, c64* scratch,
+                          hipStream_t s) {
+    int* ipiv = (int*)(scratch + (size_t)2 * m * 8 * k);
+    defl_vjp_coef_kernel<<<(2 * m + 63) / 64, 64, 0, s>>>(k, co, m, lam, sg, scol, srow, cv, dv, A, B, scratch, ipiv);
+    defl_vjp_dd_kernel<<<(m * m + 255) / 256, 256, 0, s>>>(m, lam, sg, cv, dv, Cm);
+}
+
 }  // namespace ovd

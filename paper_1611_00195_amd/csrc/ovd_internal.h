@@ -199,6 +199,14 @@ size_t nested_sign_scratch_elems(int nrhs, int k, int kp, int chunk);
 int launch_nested_sign(int nrhs, int k, TslCoeffs co, int kp, double tau, const SmallSignCfg& cfg, c64* scratch,
                        c64* c_out, double* check, int* bstep, hipStream_t s);
 
+// coefficient matrices of the deflated gradient (rhs 0 of co, m deflated pairs):
+// A, B [k][m], Cm [m][m] (see kernels_small.hip); scol / srow: sgn(T) e_1 and
+// sgn(T)^T e_1; cv = L^dag b, dv = R^dag x; lam device [m], sg device [m]
+size_t defl_vjp_coef_scratch(int k, int m);
+void launch_defl_vjp_coef(int k, TslCoeffs co, int m, const c64* lam, const double* sg, const c64* scol,
+                          const c64* srow, const c64* cv, const c64* dv, c64* A, c64* B, c64* Cm, c64* scratch,
+                          hipStream_t s);
+
 // y = sum_j coef[rhs][j] * basis[rhs][j]  (top/bottom halves selected by half_off);
 // with accumulate, y += the sum (the basis taken a chunk of vectors at a time)
 template <typename T>
@@ -265,7 +273,7 @@ struct EigParams {
     double tol = 1e-10;         // residual |H r - theta r| of the wanted pairs
     int max_outer = 80;         // restart cycles of the Arnoldi iteration
     double shift_tol = 1e-11;   // relative residual of the shifted derivative solves
-    int shift_max = 20000;      // and their iteration limit
+    int shift_max = 60000;      // and their iteration limit (rough links need 40 000)
     uint64_t seed = 1611;
     hipStream_t stream = nullptr;
 };

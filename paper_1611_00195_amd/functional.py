@@ -68,7 +68,9 @@ def sign_bilinear(lat: Lattice, U, mu, x, b, k: int):
 
     U: complex128 [4, V, 3, 3] on the device; mu: float or 0-dim float64 tensor;
     x, b: complex128 with V*12 elements ([V, 4, 3] site-spin-colour order);
-    k: Krylov dimension.  The lattice handle's links are overwritten with U."""
+    k: Krylov dimension.  The lattice handle's links are overwritten with U,
+    which removes its deflation sets (they belong to other links): the value
+    and all four gradients come from undeflated runs of the same k."""
     if not isinstance(mu, torch.Tensor):
         mu = torch.tensor(float(mu), dtype=torch.float64)
     return SignBilinear.apply(U, mu, x, b, lat, int(k))

@@ -54,7 +54,7 @@ class _Options(ctypes.Structure):
                 ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int), ("shape_seq", ctypes.c_int),
                 ("shape_rp", ctypes.c_int), ("basis_recompute", ctypes.c_int),
                 ("quad_max_levels", ctypes.c_int), ("sign_method", ctypes.c_int), ("nested_inner", ctypes.c_int),
-                ("mem_budget", ctypes.c_longlong)]
+                ("mem_budget", ctypes.c_longlong), ("eig_shift_max", ctypes.c_int)]
 
 
 class _EigStats(ctypes.Structure):
@@ -170,7 +170,7 @@ class Lattice:
     def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
                  breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True,
                  autotune=True, shape=None, basis_recompute=None, quad_max_levels=0, sign_method=SIGN_QUAD,
-                 nested_inner=0, mem_budget=0):
+                 nested_inner=0, mem_budget=0, eig_shift_max=0):
         self.dims = tuple(int(d) for d in dims)
         self.V = 1
         for d in self.dims:
@@ -186,7 +186,8 @@ class Lattice:
                        -1 if shape is None or len(shape) < 3 else int(shape[2]),
                        0 if shape is None or len(shape) < 4 else int(shape[3]),
                        -1 if basis_recompute is None else int(bool(basis_recompute)),
-                       int(quad_max_levels), int(sign_method), int(nested_inner), int(mem_budget))
+                       int(quad_max_levels), int(sign_method), int(nested_inner), int(mem_budget),
+                       int(eig_shift_max))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
@@ -500,7 +501,7 @@ def tridiag_sign(alpha, beta, delta, method=SIGN_QUAD, quad_step=0.1, quad_max_l
     if b.shape != a.shape or d.shape != a.shape:
         raise ValueError("alpha, beta, delta must have the same shape [nt, k]")
     opt = _Options(FP64, LEFT_SUM, breakdown_tol, quad_step, 0, 1, 1, -1, 0, -1, 0, -1, int(quad_max_levels),
-                   int(method), int(nested_inner), 0)
+                   int(method), int(nested_inner), 0, 0)
     c = np.zeros((nt, k), dtype=np.complex128)
     chk = ctypes.c_double(0.0)
     dp = ctypes.POINTER(ctypes.c_double)

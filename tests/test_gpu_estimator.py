@@ -65,16 +65,19 @@ def test_block_sign_general_source(field):
     lat.close()
 
 
-@pytest.mark.parametrize("k", [48, 160])
+@pytest.mark.parametrize("k", [48, 96, 160])
 def test_eps_estimates_against_oracle(field, k):
     """eps_A and eps_B at the same k as the oracle's (same algorithm, so the
     same number up to rounding).  2 eps |psi| is the norm of sgn^2 psi - psi:
-    two chained applications, each within the FP64 bound 1e-10 of the oracle
+    two chained applications, each within the FP64 bound of the oracle
     (checked here for the first), the second on a source of norm
-    |sgn(H) psi| ~ |psi| = 1, so the estimates differ by at most
-    (1e-10 + 1e-10) / 2 + 1e-10 = 2e-10 (measured 1.0e-10 at k = 160 on this
-    small-gap field)."""
-    from gpu_helpers import dev, host, ops, print_case, rel
+    |sgn(H) psi| ~ |psi| = 1, so the estimates differ by at most twice that
+    bound.  The bound is 1e-10 where the recurrence is well conditioned.  On
+    this small-gap field at k = 160 the two-sided Lanczos passes near
+    breakdowns (|w^dag v| / |w||v| down to 2e-4) and the oracle itself moves by
+    1e-9 .. 8e-8 under relative noise of 1e-16 per operator application; there
+    the bound is ten times that measured sensitivity."""
+    from gpu_helpers import dev, host, noise_sensitivity, ops, print_case, rel
     U, H, dH = field
     print_case(test="eps", dims=DIMS, k=k)
     phi = synth.make_sources(DIMS, 2, 403)
@@ -86,14 +89,18 @@ def test_eps_estimates_against_oracle(field, k):
     h, hd, dh, dhd = ops(U, DIMS, MU)
     for r in range(2):
         p = phi[r].ravel()
+        sens = noise_sensitivity(lambda w: tsl.krylov_sign(w(h), w(hd), p, p, k)[0])
+        bound = max(1e-10, 10 * sens)
         e1 = rel(y1[r], tsl.krylov_sign(h, hd, p, p, k)[0])
-        print(f"  k={k} r={r}: first application sgn(H) phi against the oracle {e1:.2e}")
-        assert e1 < 1e-10
+        print(f"  k={k} r={r}: first application sgn(H) phi against the oracle {e1:.2e}; "
+              f"oracle noise sensitivity {sens:.2e}")
+        assert e1 < bound
         ra = estimator.eps_sign(lambda v: tsl.krylov_sign(h, hd, v, v, k)[0], p)
         rb = estimator.eps_block(lambda v: tsl.krylov_block_sign(h, hd, dh, dhd, v, k)[0], p)
         print(f"  k={k} r={r}: eps_A {ea[r]:.3e} (oracle {ra:.3e}), eps_B {eb[r]:.3e} (oracle {rb:.3e})")
-        assert abs(ea[r] - ra) <= 2e-10
-        assert abs(eb[r] - rb) <= 2e-10
+        assert abs(ea[r] - ra) <= 2 * bound
+        assert abs(eb[r] - rb) <= 2 * max(bound, 10 * noise_sensitivity(
+            lambda w: tsl.krylov_block_sign(w(h), w(hd), w(dh), w(dhd), np.concatenate([0 * p, p]), k)[0]))
 
 
 def test_eps_b_with_deflation_falls(field):
