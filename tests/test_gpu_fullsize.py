@@ -86,8 +86,8 @@ def test_c3_batch_of_64_mixed_and_fp64():
     """12^4, 16 sources x mu in {0.1, 0.2, 0.3, 0.4} = 64 right-hand sides,
     k = 300, in one call: the first three Lanczos coefficients of sources 0
     and 63 against the oracle (FP64 1e-11; mixed 1e-6), and every mixed <x|dy>
-    within 1e-3 of the FP64 one (the bound of the mixed-precision parity test;
-    measured 1.3e-4 on MI355X, at mu = 0.4 where k = 300 is least converged)."""
+    within 1.2e-4 of the FP64 one (measured 3.7e-5 on MI355X over the 64, at
+    mu = 0.4 where k = 300 is least converged)."""
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, print_case
     dims, k, ns = (12, 12, 12, 12), 300, 16
@@ -116,7 +116,7 @@ def test_c3_batch_of_64_mixed_and_fp64():
             assert np.abs(np.array(de[1:]) - L["delta"][1:3]).max() < tol, (r, prec)
     dev_max = np.max(np.abs(res[ovderiv.MIXED] - res[ovderiv.FP64]) / np.abs(res[ovderiv.FP64]))
     print(f"  mixed vs FP64 over 64 rhs: max rel {dev_max:.2e}", flush=True)
-    assert dev_max < 1e-3
+    assert dev_max < 1.2e-4
 
 
 @pytest.mark.parametrize("direction", ["mu", "link"])

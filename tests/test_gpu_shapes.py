@@ -58,8 +58,9 @@ def test_autotuner_records_a_shape():
 def test_sequential_and_paired_forms_against_oracle(prec):
     """Both forms of the stencil (paired and sequential) against the oracle on
     a lattice whose volume is not a multiple of the 64-site group, with the
-    x-projection of the scalar mode: FP64 to 1e-10; mixed precision to the
-    bounds of the mixed-precision parity test (1e-4 sign, 1e-3 derivative).
+    x-projection of the scalar mode: FP64 to 1e-10; mixed precision to 5e-5
+    (sign) and 3e-4 (derivative, vectors and <x|dy>), about three times the
+    measured 1.8e-5 and 9.0e-5 of this short (k = 24) recurrence on MI355X.
     The two forms round differently where the mu-derivative terms enter, so
     they are compared with the oracle, not bit for bit with each other."""
     import numpy as np
@@ -78,7 +79,7 @@ def test_sequential_and_paired_forms_against_oracle(prec):
         dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, bh[r].ravel(), k)
         sref, _ = tsl.krylov_sign(h, hd, bh[r].ravel(), bh[r].ravel(), k)
         refs.append((yref, dref, np.vdot(xh[r].ravel(), dref), sref))
-    t_sign, t_der = (1e-10, 1e-10) if prec == "fp64" else (1e-4, 1e-3)
+    t_sign, t_der = (1e-10, 1e-10) if prec == "fp64" else (5e-5, 3e-4)
     U, b, x = dev(Uh), dev(bh), dev(xh)
     for seq in (0, 1):
         lat = ovderiv.Lattice(dims, precision=p, shape=(1, 2, seq))
@@ -88,12 +89,14 @@ def test_sequential_and_paired_forms_against_oracle(prec):
         assert ("seq" in lat.tuned_shapes()) == bool(seq)
         lat.close()
         y, dy = host(y), host(dy)
+        e_sign = e_der = 0.0
         for r in range(nrhs):
             yref, dref, sref_x, sref = refs[r]
-            assert rel(y[r], yref) < t_sign
-            assert rel(ys[r], sref) < t_sign
-            assert rel(dy[r], dref) < t_der
-            assert abs(complex(s[r]) - sref_x) <= t_der * np.linalg.norm(xh[r]) * np.linalg.norm(dref)
+            e_sign = max(e_sign, rel(y[r], yref), rel(ys[r], sref))
+            e_der = max(e_der, rel(dy[r], dref),
+                        abs(complex(s[r]) - sref_x) / (np.linalg.norm(xh[r]) * np.linalg.norm(dref)))
+        print(f"{prec} seq={seq}: sign {e_sign:.2e}  derivative {e_der:.2e}")
+        assert e_sign < t_sign and e_der < t_der
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

@@ -128,8 +128,10 @@ def test_mixed_precision_bounds():
     dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, b[0].ravel(), k)
     e2 = rel(host(dy2)[0], dref)
     print(f"mixed precision errors: sign {e1:.2e}  derivative {e2:.2e}")
-    assert e1 < 1e-4
-    assert e2 < 1e-3
+    # measured on MI355X: sign 6.9e-6, derivative 4.5e-6 (relative 2-norm and
+    # largest element); bounds about three times that
+    assert e1 < 2e-5
+    assert e2 < 1.5e-5
 
 
 def test_small_k_edge_cases():
@@ -275,7 +277,11 @@ def test_vectors_with_recomputed_basis_match_stored(prec):
     lattice whose volume is not a multiple of 64: the vectors are the same, only
     the grouping of the sum over j of the (partly cancelling, unnormalised)
     Krylov terms changes, so the results agree to 1e-11 (measured 1.5e-12); the
-    FP64 ones also match the oracle to 1e-10."""
+    FP64 ones also match the oracle to 1e-10.  Both handles run one forced launch
+    shape: each handle tunes its own, and two shapes group the partial sums of
+    the step's reductions differently, which in mixed precision changes the
+    FP32 rounding of the stored vectors and, through the recurrence, the
+    results at the 1e-5 level."""
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, host, ops, print_case, rel
     dims, k, nrhs, mu = (5, 3, 4, 3), 70, 3, 0.3
@@ -285,7 +291,7 @@ def test_vectors_with_recomputed_basis_match_stored(prec):
     xh = synth.make_sources(dims, nrhs, 243)
     out = {}
     for rc in (0, 1):
-        lat = ovderiv.Lattice(dims, precision=prec, basis_recompute=bool(rc))
+        lat = ovderiv.Lattice(dims, precision=prec, basis_recompute=bool(rc), shape=(1, 2))
         lat.set_links(dev(Uh))
         ys = host(lat.sign_apply(dev(bh), mu, k))
         assert lat.last_stats.basis_recomputed == rc
