@@ -366,7 +366,10 @@ def time_uneven(args):
     """Uneven batch: 12 derivative solves on each of 6^4, 10^4, 16^4 and 20x20^3
     (mu ~ U[0, 0.5], k = 150, 250, 400, 500 by size), one handle and stream per
     lattice, all four submitted together (ovd_sign_apply_deriv_batch), in the
-    mixed precision; per-solve deviation from the same batch in FP64."""
+    mixed precision and in FP64: with the Lanczos steps shared (one update and
+    one stencil launch per step for every lattice still running) and, for
+    comparison, with each lattice's steps on its own stream; per-solve
+    deviation of mixed from FP64."""
     import numpy as np
     import torch
 
@@ -383,29 +386,38 @@ def time_uneven(args):
         mus = list(rng.uniform(0.0, 0.5, 12))
         inputs.append((dims, k, U, b, x, mus))
 
-    def batch(prec):
+    def batch(prec, separate):
         jobs = []
         for dims, k, U, b, x, mus in inputs:
-            lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, stream=torch.cuda.Stream())
+            lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, stream=torch.cuda.Stream(),
+                                  batch_separate=separate)
             lat.set_links(U)
             jobs.append((lat, b, mus, k, x))
         return jobs
 
     out = {}
     for name, prec in (("fp64", ovderiv.FP64), ("mixed", ovderiv.MIXED)):
-        jobs = batch(prec)
-        ovderiv.sign_apply_deriv_batch(jobs)          # warm-up: graphs and launch shapes
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ovderiv.sign_apply_deriv_batch(jobs)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out[name] = {"evals_per_s": round(48 / dt, 3), "s": round(dt, 3), "vals": res}
-        for j in jobs:
-            j[0].close()
+        for separate in (False, True):
+            jobs = batch(prec, separate)
+            ovderiv.sign_apply_deriv_batch(jobs)          # warm-up: graphs and launch shapes
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ovderiv.sign_apply_deriv_batch(jobs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out[name + ("_separate" if separate else "")] = {"evals_per_s": round(48 / dt, 3), "s": round(dt, 3),
+                                                             "vals": res}
+            for j in jobs:
+                j[0].close()
     errs = [[abs(a - b) / abs(b) for a, b in zip(ra, rb)] for ra, rb in zip(out["mixed"]["vals"], out["fp64"]["vals"])]
+    dsep = max(abs(a - b) / abs(b) for ra, rb in zip(out["fp64"]["vals"], out["fp64_separate"]["vals"])
+               for a, b in zip(ra, rb))
     return {"lattices": ["x".join(map(str, d)) for d, _ in shapes], "k": [k for _, k in shapes], "solves": 48,
             "mixed_evals_per_s": out["mixed"]["evals_per_s"], "fp64_evals_per_s": out["fp64"]["evals_per_s"],
+            "form": "shared Lanczos steps: one update and one stencil launch per step for all lattices",
+            "separate_streams": {"mixed_evals_per_s": out["mixed_separate"]["evals_per_s"],
+                                 "fp64_evals_per_s": out["fp64_separate"]["evals_per_s"],
+                                 "fp64_max_rel_diff_vs_shared": dsep},
             "mixed_vs_fp64_rel_err_max_per_lattice": [float(max(e)) for e in errs],
             "mixed_vs_fp64_rel_err_median_per_lattice": [float(np.median(e)) for e in errs],
             "note": "k = 150 on 6^4 and 250 on 10^4 leave the FP64 result itself unconverged at the 4e-3 level "

@@ -123,6 +123,9 @@ typedef struct {
                                fit in free device memory); 0 (default): no budget */
     int eig_shift_max;      /* ovd_compute_deflation: iteration limit of each shifted solve for the
                                eigenvector derivatives (CGLS); 0: 60000 */
+    int batch_separate;     /* ovd_sign_apply_deriv_batch: 1 runs this lattice's Lanczos steps as
+                               launches of its own on its own stream, even where the batch could
+                               share them; 0 (default): shared when the batch allows */
 } ovd_options;
 
 typedef struct {
@@ -318,11 +321,23 @@ typedef struct {
 
 /* Uneven batch (derivatives on several lattices of different sizes at once,
  * each lattice with its own handle, batch of sources, mu values and k): every
- * job runs ovd_sign_apply_deriv on its handle from a host thread of its own,
- * so that the lattices' Lanczos graphs run concurrently when the handles were
- * created on different streams.  A handle may appear only once.  Returns
- * OVD_OK if every job succeeded, else the first failing job's status (each
- * job's status is in its status field). */
+ * job runs ovd_sign_apply_deriv on its handle from a host thread of its own.
+ * When all handles have the same precision, all jobs the same kind of
+ * direction (mu, or a link direction) and no handle sets batch_separate, the
+ * lattices share their Lanczos steps: each job prepares its sources on its own
+ * stream, then step j of every lattice whose k exceeds j runs in one update
+ * launch and one stencil launch (the blocks split into one range per lattice,
+ * each running that lattice's own kernel body), on a stream of the batch
+ * after all jobs' preparation; each job then finishes on its own stream
+ * (sgn(T_k) e_1, outputs, deflation terms).  The shared launches use the
+ * paired stencil form with two site groups per block, or one if every
+ * lattice's shape has one, and each lattice's XCD work order; the shape is
+ * recorded as the handle's tuned shape, so later single calls give identical
+ * results.  Otherwise each lattice's steps run as its own graph on its own
+ * stream, concurrently when the handles were created on different streams.
+ * A handle may appear only once.  Returns OVD_OK if every job succeeded,
+ * else the first failing job's status (each job's status is in its status
+ * field). */
 ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs);
 
 /* Gradient of s = <x|sgn(H(mu))|b> (the bilinear the paper's currents and

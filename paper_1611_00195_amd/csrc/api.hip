@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -365,6 +366,163 @@ ovd_status small_sign(ovd_h h, int nrhs, int k, TslCoeffs co, c64* c_out, double
 //   dir 0: A = H;  dir 1/2: A = B (d/dmu, d/dlink).
 //   src_v/src_w: SoA start vectors (stride fsz per rhs).  xproj: SoA (stride 12*Vp) or null.
 //   basis: if non-null, V-hat_1..V-hat_k are kept there ([rhs][k][fsz]).
+// ---------------------------------------------------------------------------
+// Shared Lanczos steps of an uneven batch.  Each job's host thread runs its
+// call up to the Lanczos loop and then hands the loop to the batch: it
+// records an event after its preparation and publishes the kernel arguments
+// of its k steps (a plan).  The thread that completes the set (the last to
+// publish, or the last job to leave without publishing) enqueues, on the
+// batch's stream and after every plan's event, one update launch and one
+// stencil launch per step for all lattices still running at that step.  Each
+// job's stream then waits for that work, and the job finishes on its own.
+// ---------------------------------------------------------------------------
+struct MultiPlan {
+    ovd_h h = nullptr;
+    int dir = 0, nrhs = 0, k = 0;
+    long long fsz = 0;
+    std::vector<StepPtrs> steps;   // kernel arguments of steps 0 .. k-1
+    const void* U = nullptr;
+    const void* dU = nullptr;
+    double md = 0.0;
+    TslState* st = nullptr;
+    TslCoeffs co{};
+    double* partials = nullptr;
+    unsigned* counters = nullptr;
+    StencilVariant var;            // in: the handle's shape; out: the shape used
+};
+
+struct MultiCoord {
+    std::mutex m;
+    std::condition_variable cv;
+    int n = 0, arrived = 0, resigned = 0;
+    bool done = false;
+    ovd_status status = OVD_OK;
+    std::string err;
+    std::vector<MultiPlan*> plans;
+    std::vector<hipEvent_t> ready;
+    void (*lead)(MultiCoord&) = nullptr;   // enqueue the shared steps (precision of the plans)
+    hipStream_t stream = nullptr;
+    hipEvent_t finished = nullptr;
+    void* table = nullptr;                 // TslSegment [max k][plans] on the device
+
+    ~MultiCoord() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (table) (void)hipFree(table);
+        for (hipEvent_t e : ready) (void)hipEventDestroy(e);
+        if (finished) (void)hipEventDestroy(finished);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+    // called with m held, once every job has published or left
+    void complete() {
+        if (lead && !plans.empty()) lead(*this);
+        done = true;
+        cv.notify_all();
+    }
+};
+
+// the batch the calling thread's job belongs to (set by ovd_sign_apply_deriv_batch)
+thread_local MultiCoord* tls_multi = nullptr;
+
+void multi_resign(MultiCoord& C) {
+    std::lock_guard<std::mutex> lk(C.m);
+    ++C.resigned;
+    if (C.arrived + C.resigned == C.n) C.complete();
+}
+
+template <typename T>
+void multi_lead(MultiCoord& C) {
+    auto bad = [&](const std::string& what, hipError_t e) {
+        C.status = OVD_EHIP;
+        C.err = "shared Lanczos steps of the batch: " + what + ": " + hipGetErrorString(e);
+    };
+    const std::vector<MultiPlan*>& P = C.plans;
+    const size_t np = P.size();
+    // one launch shape for all: the paired form, one site group per block if
+    // every lattice's shape has one, else two; each lattice's XCD order
+    int gpb = 1;
+    for (const MultiPlan* q : P)
+        if (q->var.gpb != 1) gpb = 2;
+    int maxk = 0, maxr = 0;
+    for (MultiPlan* q : P) {
+        q->var.gpb = gpb;
+        q->var.seq = 0;
+        if (q->var.map < 0) q->var.map = default_map(q->nrhs);
+        maxk = std::max(maxk, q->k);
+        maxr = std::max(maxr, q->nrhs);
+    }
+    std::vector<TslSegment> tab((size_t)maxk * np);
+    std::vector<int> nseg(maxk), nblk(maxk), nub(maxk);
+    for (int j = 0; j < maxk; ++j) {
+        int b0 = 0, u0 = 0, c = 0;
+        for (const MultiPlan* q : P) {
+            if (q->k <= j) continue;
+            TslSegment& S = tab[(size_t)j * np + c++];
+            S.g = q->h->g;
+            S.ngroups = (S.g.V + 63) / 64;
+            S.nrhs = q->nrhs;
+            S.map = q->var.map;
+            S.nblocks = tsl_stencil_blocks(S.g, q->dir, gpb) * q->nrhs;
+            S.block0 = b0;
+            b0 += S.nblocks;
+            S.unblocks = tsl_update_xblocks(q->fsz);
+            S.ublock0 = u0;
+            u0 += S.unblocks;
+            S.fsz = q->fsz;
+            S.tau = q->h->opt.breakdown_tol;
+            S.p = q->steps[j];
+            S.U = q->U;
+            S.dU = q->dU;
+            S.mdiag = q->md;
+            S.st = q->st;
+            S.co = q->co;
+            S.partials = q->partials;
+            S.counters = q->counters;
+        }
+        nseg[j] = c;
+        nblk[j] = b0;
+        nub[j] = u0;
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&C.table, sizeof(TslSegment) * tab.size())) != hipSuccess) return bad("table", e);
+    if ((e = hipMemcpy(C.table, tab.data(), sizeof(TslSegment) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return bad("table upload", e);
+    if ((e = hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking)) != hipSuccess) return bad("stream", e);
+    for (hipEvent_t ev : C.ready)
+        if ((e = hipStreamWaitEvent(C.stream, ev, 0)) != hipSuccess) return bad("wait for the jobs", e);
+    const TslSegment* dtab = (const TslSegment*)C.table;
+    for (int j = 0; j < maxk; ++j)
+        launch_tsl_step_multi<T>(P[0]->dir, gpb, j == 0 ? 0 : (j == 1 ? 2 : 3), dtab + (size_t)j * np, nseg[j],
+                                 nblk[j], nub[j], maxr, j, C.stream);
+    if ((e = hipGetLastError()) != hipSuccess) return bad("launch", e);
+    if ((e = hipEventCreateWithFlags(&C.finished, hipEventDisableTiming)) != hipSuccess) return bad("event", e);
+    if ((e = hipEventRecord(C.finished, C.stream)) != hipSuccess) return bad("event", e);
+}
+
+// publish plan and wait until the batch's steps are enqueued; then the
+// handle's stream waits for them
+template <typename T>
+ovd_status multi_join(ovd_h h, MultiCoord& C, MultiPlan& plan) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, h->stream);
+    std::unique_lock<std::mutex> lk(C.m);
+    if (e != hipSuccess) {   // leave the batch
+        if (ev) (void)hipEventDestroy(ev);
+        ++C.resigned;
+        if (C.arrived + C.resigned == C.n) C.complete();
+        return fail(h, OVD_EHIP, std::string("batch event: ") + hipGetErrorString(e));
+    }
+    C.ready.push_back(ev);
+    C.plans.push_back(&plan);
+    C.lead = &multi_lead<T>;
+    ++C.arrived;
+    if (C.arrived + C.resigned == C.n) C.complete();
+    else C.cv.wait(lk, [&] { return C.done; });
+    if (C.status != OVD_OK) return fail(h, C.status, C.err);
+    HIPCHK(hipStreamWaitEvent(h->stream, C.finished, 0));
+    return OVD_OK;
+}
+
 template <typename T>
 ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cpx<T>* src_v,
                    const cpx<T>* src_w, const cpx<T>* xproj, cpx<T>* basis, c64* c_out, ovd_stats* stats,
@@ -472,24 +630,29 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             h->tuned[key] = var;
         }
     }
+    // kernel arguments of step j
+    auto step_ptrs = [&](int j) {
+        StepPtrs p{};
+        if (j > 0) {
+            p.Xv = Us(j); p.sXv = fsz;
+            p.Yv = Vs(j); p.sYv = sV;
+            p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
+            p.Xw = Zs(j); p.sXw = fsz;
+            p.Yw = Ws(j); p.sYw = sW;
+            p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = sW;
+        }
+        p.outV = Vs(j + 1); p.sV = sV;
+        p.outU = Us(j + 1); p.sU = fsz;
+        p.outW = Ws(j + 1); p.sW = sW;
+        p.outZ = Zs(j + 1); p.sZ = fsz;
+        p.xproj = xproj;
+        p.sx = (long long)12 * g.Vp;
+        return p;
+    };
     // the k steps: update (from the second step on) and stencil with the step's reductions
     auto enqueue_steps = [&](hipStream_t stream) -> hipError_t {
         for (int j = 0; j < k; ++j) {
-            StepPtrs p{};
-            if (j > 0) {
-                p.Xv = Us(j); p.sXv = fsz;
-                p.Yv = Vs(j); p.sYv = sV;
-                p.Zv = (j >= 2) ? Vs(j - 1) : Vs(j); p.sZv = sV;
-                p.Xw = Zs(j); p.sXw = fsz;
-                p.Yw = Ws(j); p.sYw = sW;
-                p.Zw = (j >= 2) ? Ws(j - 1) : Ws(j); p.sZw = sW;
-            }
-            p.outV = Vs(j + 1); p.sV = sV;
-            p.outU = Us(j + 1); p.sU = fsz;
-            p.outW = Ws(j + 1); p.sW = sW;
-            p.outZ = Zs(j + 1); p.sZ = fsz;
-            p.xproj = xproj;
-            p.sx = (long long)12 * g.Vp;
+            const StepPtrs p = step_ptrs(j);
             if (j > 0) {
                 if (timing) (void)hipEventRecord(h->ev[4 * j], stream);
                 launch_tsl_update<T>(nrhs, j == 1 ? 2 : 3, fsz, p, st, stream);
@@ -504,8 +667,37 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         return hipGetLastError();
     };
     bool launched = false;
+    // the first Lanczos run of a job of a shared-step batch hands its steps to the batch
+    if (MultiCoord* C = tls_multi) {
+        tls_multi = nullptr;
+        if (dir != 0 && !timing && !after_step && !h->arena.active && !h->opt.batch_separate) {
+            MultiPlan plan;
+            plan.h = h;
+            plan.dir = dir;
+            plan.nrhs = nrhs;
+            plan.k = k;
+            plan.fsz = fsz;
+            plan.steps.reserve(k);
+            for (int j = 0; j < k; ++j) plan.steps.push_back(step_ptrs(j));
+            plan.U = U;
+            plan.dU = dU;
+            plan.md = md;
+            plan.st = st;
+            plan.co = co;
+            plan.partials = partials;
+            plan.counters = counters;
+            plan.var = var;
+            const ovd_status js = multi_join<T>(h, *C, plan);
+            if (js != OVD_OK) return js;
+            h->tuned[std::string("tsl:") + (sizeof(T) == 8 ? "d" : "f") + ":" + std::to_string(dir) + ":" +
+                     std::to_string(nrhs)] = plan.var;
+            launched = true;
+        } else {
+            multi_resign(*C);
+        }
+    }
     // events and per-call hooks stay out of graphs; an allocation-free call launches one by one
-    if (h->opt.use_graph && !timing && !after_step && !h->arena.active) {
+    if (!launched && h->opt.use_graph && !timing && !after_step && !h->arena.active) {
         double tau = h->opt.breakdown_tol;
         uint64_t tb, mb;
         std::memcpy(&tb, &tau, 8);
@@ -911,7 +1103,8 @@ ovd_status upload_dir(ovd_h h, const ovd_dir* dir, int* dirk) {
 bool options_ok(const ovd_options& o) {
     return (o.precision == OVD_FP64 || o.precision == OVD_MIXED) && o.quad_max_levels >= 0 &&
            o.quad_max_levels <= kMaxLevelsLimit && (o.sign_method == OVD_SIGN_QUAD || o.sign_method == OVD_SIGN_NESTED) &&
-           o.nested_inner >= 0 && o.mem_budget >= 0 && o.eig_shift_max >= 0;
+           o.nested_inner >= 0 && o.mem_budget >= 0 && o.eig_shift_max >= 0 &&
+           (o.batch_separate == 0 || o.batch_separate == 1);
 }
 
 extern "C" {
@@ -1194,11 +1387,27 @@ ovd_status ovd_sign_apply_deriv_batch(int njobs, ovd_deriv_job* jobs) {
                 return OVD_EINVAL;
             }
     }
+    // shared Lanczos steps when the lattices allow one kernel for all of them
+    bool shared = njobs > 1;
+    const int kind0 = jobs[0].dir ? jobs[0].dir->kind : OVD_DIR_MU;
+    for (int i = 0; i < njobs; ++i) {
+        const int kind = jobs[i].dir ? jobs[i].dir->kind : OVD_DIR_MU;
+        if (jobs[i].h->opt.precision != jobs[0].h->opt.precision || kind != kind0 || jobs[i].h->opt.batch_separate)
+            shared = false;
+    }
+    MultiCoord C;
+    C.n = njobs;
     // one host thread per lattice: each call enqueues on its handle's stream
-    // and waits only for its own results, so the lattices run side by side
+    // and waits only for its own results (and for the shared steps), so the
+    // lattices run side by side
     auto run = [&](int i) {
         ovd_deriv_job& J = jobs[i];
+        tls_multi = shared ? &C : nullptr;
         J.status = ovd_sign_apply_deriv(J.h, J.nrhs, J.mu, J.dir, J.k, J.b, J.y, J.dy, J.x, J.xdy, J.st);
+        if (tls_multi) {   // left before its Lanczos steps
+            tls_multi = nullptr;
+            multi_resign(C);
+        }
     };
     std::vector<std::thread> pool;
     pool.reserve(njobs - 1);

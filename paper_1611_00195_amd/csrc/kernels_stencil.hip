@@ -548,12 +548,11 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* [16
 // FP32 products and sums.  The kernel is HBM-bound; FP64 costs nothing here.
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n_elem,
-                                                         const TslState* __restrict__ st) {
-    const int rhs = blockIdx.y;
+__device__ __forceinline__ void tsl_update_body(const int bx, const int nbx, const int rhs, const bool vside,
+                                                const StepPtrs& p, long long n_elem,
+                                                const TslState* __restrict__ st) {
     const TslState* S = st + rhs;
     if (S->flag) return;
-    const bool vside = blockIdx.z == 0;
     const c64 a = vside ? S->av : S->aw;
     const c64 b = vside ? S->bv : S->bw;
     const c64 c = vside ? S->cv : S->cw;
@@ -561,12 +560,32 @@ __global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n
     const cpx<T>* Y = vside ? (const cpx<T>*)p.Yv + rhs * p.sYv : (const cpx<T>*)p.Yw + rhs * p.sYw;
     const cpx<T>* Z = vside ? (const cpx<T>*)p.Zv + rhs * p.sZv : (const cpx<T>*)p.Zw + rhs * p.sZw;
     cpx<T>* O = vside ? (cpx<T>*)p.outV + rhs * p.sV : (cpx<T>*)p.outW + rhs * p.sW;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+    const long long stride = (long long)nbx * blockDim.x;
+    for (long long e = (long long)bx * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
         c64 r = a * cast<double>(X[e]) + b * cast<double>(Y[e]);
         if constexpr (NT == 3) r += c * cast<double>(Z[e]);
         O[e] = cast<T>(r);
     }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void tsl_update_kernel(StepPtrs p, long long n_elem,
+                                                         const TslState* __restrict__ st) {
+    tsl_update_body<T, NT>((int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y, blockIdx.z == 0, p, n_elem, st);
+}
+
+// The update of several lattices in one launch: x ranges of blocks per
+// lattice (as in its own launch), y the rhs (blocks past a lattice's count
+// return), z the side.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void tsl_update_multi_kernel(const TslSegment* __restrict__ seg, int nseg) {
+    int i = 0;
+    for (int q = 1; q < nseg; ++q)
+        if ((int)blockIdx.x >= seg[q].ublock0) i = q;
+    const TslSegment& S = seg[i];
+    if ((int)blockIdx.y >= S.nrhs) return;
+    tsl_update_body<T, NT>((int)blockIdx.x - S.ublock0, S.unblocks, (int)blockIdx.y, blockIdx.z == 0, S.p, S.fsz,
+                           S.st);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,21 +856,23 @@ __device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[1
 // fields staged in LDS for the x and y hops.
 constexpr int PLANE_GPB = 8;
 
+// The body of one launch's block `bid` of `nblocks` (blocks per rhs = nblocks / nrhs);
+// a standalone launch passes its own grid, a multi-lattice launch the block's
+// place inside its lattice's range of blocks.
 template <typename T, int DIR, int GPB, bool SEQ>
-__global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
-                                                          const cpx<T>* __restrict__ dU, T mdiag,
-                                                          TslState* __restrict__ st, TslCoeffs co,
-                                                          double* __restrict__ partials,
-                                                          unsigned* __restrict__ counters, int j, double tau,
-                                                          int ngroups, int nrhs, int map) {
+__device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblocks, Geom g, StepPtrs p,
+                                                 const cpx<T>* __restrict__ U, const cpx<T>* __restrict__ dU, T mdiag,
+                                                 TslState* __restrict__ st, TslCoeffs co,
+                                                 double* __restrict__ partials, unsigned* __restrict__ counters, int j,
+                                                 double tau, int ngroups, int nrhs, int map) {
     constexpr bool PLANE = GPB == PLANE_GPB;
     static_assert(!SEQ || (!PLANE && DIR != 2), "sequential form: DIR 0/1 without the plane in LDS");
     constexpr int NQ = sizeof(T) == 8 ? 12 : 6;     // 16-byte entries per site
     extern __shared__ float4 plane_lds[];           // PLANE: [2][NQ][P]
     __shared__ double lds[16 * 8];
     __shared__ int am_last;
-    const int nb = gridDim.x / nrhs;                // blocks per rhs
-    const Work wk = xcd_work(blockIdx.x, nb, nrhs, map);
+    const int nb = (int)((unsigned)nblocks / (unsigned)nrhs);   // blocks per rhs
+    const Work wk = xcd_work(bid, nb, nrhs, map);
     const int rhs = wk.rhs;
     TslState* S = st + rhs;
     if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
@@ -1162,12 +1183,43 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
     S->step = j + 1;
 }
 
+template <typename T, int DIR, int GPB, bool SEQ>
+__global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U,
+                                                          const cpx<T>* __restrict__ dU, T mdiag,
+                                                          TslState* __restrict__ st, TslCoeffs co,
+                                                          double* __restrict__ partials,
+                                                          unsigned* __restrict__ counters, int j, double tau,
+                                                          int ngroups, int nrhs, int map) {
+    tsl_stencil_body<T, DIR, GPB, SEQ>((int)blockIdx.x, (int)gridDim.x, g, p, U, dU, mdiag, st, co, partials,
+                                       counters, j, tau, ngroups, nrhs, map);
+}
+
+// One Lanczos step of several lattices in one launch: the blocks are split
+// into consecutive ranges, one per lattice (each range a multiple of 8 blocks
+// long and starting at a multiple of 8, so a block's XCD is the one it has in
+// the lattice's own launch), and every block runs the standalone body with
+// its lattice's arguments: results identical to the lattice's own launch.
+template <typename T, int DIR, int GPB>
+__global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_multi_kernel(const TslSegment* __restrict__ seg,
+                                                                           int nseg, int j) {
+    int i = 0;
+    for (int q = 1; q < nseg; ++q)
+        if ((int)blockIdx.x >= seg[q].block0) i = q;
+    const TslSegment& S = seg[i];
+    tsl_stencil_body<T, DIR, GPB, false>((int)blockIdx.x - S.block0, S.nblocks, S.g, S.p, (const cpx<T>*)S.U,
+                                         (const cpx<T>*)S.dU, T(S.mdiag), S.st, S.co, S.partials, S.counters, j, S.tau,
+                                         S.ngroups, S.nrhs, S.map);
+}
+
+int tsl_update_xblocks(long long fsz) {
+    long long nblk = (fsz + 255) / 256;
+    return (int)(nblk > 2048 ? 2048 : nblk);
+}
+
 template <typename T>
 void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, const TslState* st,
                        hipStream_t s) {
-    long long nblk = (fsz + 255) / 256;
-    if (nblk > 2048) nblk = 2048;
-    dim3 grid((unsigned)nblk, nrhs, 2);
+    dim3 grid((unsigned)tsl_update_xblocks(fsz), nrhs, 2);
     if (nterms == 3)
         tsl_update_kernel<T, 3><<<grid, 256, 0, s>>>(p, fsz, st);
     else
@@ -1243,7 +1295,25 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
 #undef OVD_TSL
 }
 
+template <typename T>
+void launch_tsl_step_multi(int dir, int gpb, int nterms, const TslSegment* seg, int nseg, int nblocks,
+                           int ublocks, int max_nrhs, int j, hipStream_t s) {
+    if (nterms == 3)
+        tsl_update_multi_kernel<T, 3><<<dim3(ublocks, max_nrhs, 2), 256, 0, s>>>(seg, nseg);
+    else if (nterms == 2)
+        tsl_update_multi_kernel<T, 2><<<dim3(ublocks, max_nrhs, 2), 256, 0, s>>>(seg, nseg);
+    if (dir == 1) {
+        if (gpb == 1) tsl_stencil_multi_kernel<T, 1, 1><<<nblocks, 128, 0, s>>>(seg, nseg, j);
+        else tsl_stencil_multi_kernel<T, 1, 2><<<nblocks, 256, 0, s>>>(seg, nseg, j);
+    } else {
+        if (gpb == 1) tsl_stencil_multi_kernel<T, 2, 1><<<nblocks, 128, 0, s>>>(seg, nseg, j);
+        else tsl_stencil_multi_kernel<T, 2, 2><<<nblocks, 256, 0, s>>>(seg, nseg, j);
+    }
+}
+
 #define OVD_INST(T)                                                                                        \
+    template void launch_tsl_step_multi<T>(int, int, int, const TslSegment*, int, int, int, int, int,     \
+                                           hipStream_t);                                                   \
     template void launch_tsl_update<T>(int, int, long long, const StepPtrs&, const TslState*, hipStream_t); \
     template void launch_tsl_stencil<T>(const Geom&, int, int, const StepPtrs&, const cpx<T>*, const cpx<T>*, \
                                         double, TslState*, TslCoeffs, double*, unsigned*, int, double,     \

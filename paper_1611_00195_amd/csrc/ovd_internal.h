@@ -167,6 +167,34 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
                         unsigned* counters, int j, double tau, hipStream_t s, StencilVariant v = StencilVariant{});
 
+// One lattice of a multi-lattice Lanczos step (several handles' recurrences
+// advanced by one stencil launch and one update launch per step).  Stencil
+// blocks [block0, block0 + nblocks) and update x-blocks [ublock0, ublock0 +
+// unblocks) belong to this lattice; block0 and nblocks are multiples of 8.
+struct TslSegment {
+    Geom g;
+    int ngroups, nrhs, map;
+    int block0, nblocks;       // stencil blocks: tsl_stencil_blocks(g, dir, gpb) * nrhs
+    int ublock0, unblocks;     // update x-blocks per (rhs, side)
+    long long fsz;             // elements per rhs and side
+    double tau;                // breakdown tolerance of the lattice's handle
+    StepPtrs p;
+    const void* U;
+    const void* dU;
+    double mdiag;
+    TslState* st;
+    TslCoeffs co;
+    double* partials;
+    unsigned* counters;
+};
+// update x-blocks per (rhs, side) of launch_tsl_update
+int tsl_update_xblocks(long long fsz);
+// the two kernels of step j over nseg lattices (device table seg[nseg]);
+// gpb 1 or 2, paired form; nterms as launch_tsl_update (0: no update, step 0)
+template <typename T>
+void launch_tsl_step_multi(int dir, int gpb, int nterms, const TslSegment* seg, int nseg, int nblocks,
+                           int ublocks, int max_nrhs, int j, hipStream_t s);
+
 // sgn(T_k) e_1 for nrhs tridiagonal matrices by the resolvent quadrature.
 // quad_step: first refined step of the trapezoidal rule in log(y); max_levels:
 // refinement levels before giving up (<= 0: kDefaultMaxLevels); chunk: solves

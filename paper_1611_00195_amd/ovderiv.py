@@ -54,7 +54,8 @@ class _Options(ctypes.Structure):
                 ("shape_map", ctypes.c_int), ("shape_gpb", ctypes.c_int), ("shape_seq", ctypes.c_int),
                 ("shape_rp", ctypes.c_int), ("basis_recompute", ctypes.c_int),
                 ("quad_max_levels", ctypes.c_int), ("sign_method", ctypes.c_int), ("nested_inner", ctypes.c_int),
-                ("mem_budget", ctypes.c_longlong), ("eig_shift_max", ctypes.c_int)]
+                ("mem_budget", ctypes.c_longlong), ("eig_shift_max", ctypes.c_int),
+                ("batch_separate", ctypes.c_int)]
 
 
 class _EigStats(ctypes.Structure):
@@ -170,7 +171,7 @@ class Lattice:
     def __init__(self, dims, m0=-1.5, r=1.0, t_bc=-1, precision=FP64, left_start=LEFT_SUM,
                  breakdown_tol=1e-14, quad_step=0.1, stream=None, step_timing=False, use_graph=True,
                  autotune=True, shape=None, basis_recompute=None, quad_max_levels=0, sign_method=SIGN_QUAD,
-                 nested_inner=0, mem_budget=0, eig_shift_max=0):
+                 nested_inner=0, mem_budget=0, eig_shift_max=0, batch_separate=False):
         self.dims = tuple(int(d) for d in dims)
         self.V = 1
         for d in self.dims:
@@ -187,7 +188,7 @@ class Lattice:
                        0 if shape is None or len(shape) < 4 else int(shape[3]),
                        -1 if basis_recompute is None else int(bool(basis_recompute)),
                        int(quad_max_levels), int(sign_method), int(nested_inner), int(mem_budget),
-                       int(eig_shift_max))
+                       int(eig_shift_max), int(bool(batch_separate)))
         h = ctypes.c_void_p()
         dims_c = (ctypes.c_int * 4)(*self.dims)
         st = self._lib.ovd_create_lattice(dims_c, m0, r, t_bc, ctypes.byref(opt),
@@ -455,8 +456,10 @@ class Lattice:
 def sign_apply_deriv_batch(jobs):
     """Uneven batch: jobs = [(lattice, b, mu, k, x), ...], one per lattice
     (distinct handles, ideally created on distinct streams); every lattice's
-    derivative <x|d/dmu sgn(H) b> runs concurrently (ovd_sign_apply_deriv_batch).
-    Returns a list of per-lattice lists of complex values."""
+    derivative <x|d/dmu sgn(H) b> (ovd_sign_apply_deriv_batch).  Lattices of
+    one precision share one update and one stencil launch per Lanczos step
+    unless a handle was created with batch_separate=True.  Returns a list of
+    per-lattice lists of complex values."""
     n = len(jobs)
     arr = (_Job * n)()
     keep = []

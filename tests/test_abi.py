@@ -68,9 +68,9 @@ def test_bad_options_and_small_sign_arguments_rejected():
     ok = (ctypes.c_int * 4)(4, 4, 4, 4)
     base = dict(precision=0, left_start=0, breakdown_tol=1e-14, quad_step=0.1, step_timing=0, use_graph=1,
                 autotune=1, shape_map=-1, shape_gpb=0, shape_seq=-1, shape_rp=0, basis_recompute=-1,
-                quad_max_levels=0, sign_method=0, nested_inner=0, mem_budget=0, eig_shift_max=0)
+                quad_max_levels=0, sign_method=0, nested_inner=0, mem_budget=0, eig_shift_max=0, batch_separate=0)
     for bad in (dict(quad_max_levels=21), dict(sign_method=2), dict(nested_inner=-1), dict(mem_budget=-5),
-                dict(precision=3), dict(eig_shift_max=-1)):
+                dict(precision=3), dict(eig_shift_max=-1), dict(batch_separate=2)):
         opt = ovderiv._Options(**{**base, **bad})
         assert lib.ovd_create_lattice(ok, ctypes.c_double(-1.5), ctypes.c_double(1.0), -1, ctypes.byref(opt), None,
                                       ctypes.byref(h)) == -1, bad

@@ -10,16 +10,22 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+@pytest.mark.parametrize("separate", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_uneven_batch_matches_single_calls(prec):
+def test_uneven_batch_matches_single_calls(prec, separate):
+    """Three lattices of different sizes, batch sizes and k: the shared steps
+    (one update and one stencil launch per step for all lattices still
+    running, the longest k last alone) and the separate form both equal the
+    single calls made afterwards bit for bit (the batch records its launch
+    shape as the handle's shape), and FP64 matches the oracle."""
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, ops, print_case
     shapes = [((4, 4, 4, 4), 3, 40), ((4, 4, 4, 6), 2, 56), ((6, 4, 2, 4), 4, 32)]
-    print_case(test="uneven_batch", shapes=shapes, prec=prec)
+    print_case(test="uneven_batch", shapes=shapes, prec=prec, separate=separate)
     jobs, singles, data = [], [], []
     for i, (dims, nr, k) in enumerate(shapes):
         U = synth.make_links(dims, 0.5, 801 + i)
-        lat = ovderiv.Lattice(dims, precision=prec, stream=torch.cuda.Stream())
+        lat = ovderiv.Lattice(dims, precision=prec, stream=torch.cuda.Stream(), batch_separate=separate)
         lat.set_links(dev(U))
         b = dev(synth.make_sources(dims, nr, 810 + i))
         x = dev(synth.make_sources(dims, nr, 820 + i))
@@ -49,3 +55,34 @@ def test_batch_rejects_repeated_handle():
     b = dev(synth.make_sources(dims, 1, 831))
     with pytest.raises(ovderiv.OvdError):
         ovderiv.sign_apply_deriv_batch([(lat, b, 0.3, 8, b), (lat, b, 0.3, 8, b)])
+
+
+def test_batch_with_a_failing_job_and_mixed_precisions():
+    """A job that fails its argument checks leaves the shared steps to the
+    others, which still finish (the call reports the failure); a batch whose
+    handles differ in precision runs each lattice on its own and equals the
+    single calls."""
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, print_case
+    print_case(test="batch_failing_job")
+    lats, bs, xs = [], [], []
+    for i, dims in enumerate(((4, 4, 4, 4), (4, 4, 2, 4), (6, 4, 4, 2))):
+        lat = ovderiv.Lattice(dims, precision=ovderiv.MIXED if i == 2 else ovderiv.FP64,
+                              stream=torch.cuda.Stream())
+        lat.set_links(dev(synth.make_links(dims, 0.5, 840 + i)))
+        lats.append(lat)
+        bs.append(dev(synth.make_sources(dims, 2, 850 + i)))
+        xs.append(dev(synth.make_sources(dims, 2, 860 + i)))
+    # k = 0 fails before any device work; the other FP64 job runs the shared steps alone
+    with pytest.raises(ovderiv.OvdError) as ei:
+        ovderiv.sign_apply_deriv_batch([(lats[0], bs[0], 0.3, 0, xs[0]), (lats[1], bs[1], 0.3, 24, xs[1])])
+    assert ei.value.status == ovderiv.OVD_EINVAL
+    _, _, s1 = lats[1].sign_apply_deriv(bs[1], 0.3, 24, x=xs[1], want_vectors=False)
+    assert all(np.isfinite(abs(v)) for v in s1)
+    # FP64 and mixed handles: separate runs
+    res = ovderiv.sign_apply_deriv_batch([(lats[0], bs[0], 0.2, 28, xs[0]), (lats[2], bs[2], 0.25, 20, xs[2])])
+    _, _, r0 = lats[0].sign_apply_deriv(bs[0], 0.2, 28, x=xs[0], want_vectors=False)
+    _, _, r2 = lats[2].sign_apply_deriv(bs[2], 0.25, 20, x=xs[2], want_vectors=False)
+    assert res[0] == r0 and res[1] == r2
+    for lat in lats:
+        lat.close()
