@@ -8,6 +8,12 @@ sizes, far too long for a test, so the results are computed once here and
 read by ``tests/test_gpu_golden.py``.
 
 What is computed (the paper's hot path at the workload sizes):
+  * (case c4_vjp) the gradient of s = <x|sgn(H(mu))|b> at the headline size:
+    s, ds/dmu and the force F on every link from the bilinear two-sided
+    Lanczos run (left start x, right start b) with the Frechet derivative of
+    sgn(T_k) (the gradient form built on Sec. 2; not in the paper), stored at
+    64 sampled links with i tr F (the U(1) derivative of Sec. 4-5), the
+    largest |F| entry and the Lanczos coefficients;
   * Sec. 2, eq. 6-7: the derivative d/dt sgn(H(mu)) b, and sgn(H(mu)) b, as
     the Krylov-Ritz approximation of sgn(B) (0; b) for the block matrix
     B = [[H, dH], [0, H]], k two-sided Lanczos steps (the closing part of
@@ -40,7 +46,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
-from oracle import dirac, matfun, tsl  # noqa: E402
+from oracle import dirac, matfun, tsl, vjp  # noqa: E402
 
 NSITES = 64
 SITE_SEED = 99
@@ -81,6 +87,10 @@ def cases():
         c[f"c5_10_r{r}"] = _case((10, 10, 10, 10), 0.4, 1621, float(mus[1][r]), 250, 1640 + r, 1690 + r,
                                  vectors=False)
     c["c5_16_r0"] = _case((16, 16, 16, 16), 0.4, 1622, float(mus[2][0]), 400, 1650, 1700, vectors=False)
+    # the gradient at the headline size: source 0 of the bench (b seed 4000, x seed 5000)
+    c["c4_vjp"] = dict(_case((14, 14, 14, 14), 0.4, 1611, 0.3, 400, 4000, 5000,
+                             cite="gradient of <x|sgn(H)|b>: bilinear two-sided Lanczos (Sec. 2) and the "
+                                  "Frechet derivative of sgn(T_k) (eq. 6 applied to T_k)"), kind="vjp")
     return c
 
 
@@ -160,9 +170,29 @@ def run_case(name: str, p: dict) -> dict:
     return out
 
 
+def run_vjp_case(name: str, p: dict) -> dict:
+    t0 = time.time()
+    dims = tuple(p["dims"])
+    V = synth.volume(dims)
+    U = synth.make_links(dims, p["eps"], p["link_seed"])
+    b = synth.make_source(dims, p["b_seed"]).ravel()
+    x = synth.make_source(dims, p["x_seed"]).ravel()
+    s, ds_dmu, F, L = vjp.krylov_vjp(U, dims, p["mu"], x, b, p["k"], m0=p["m0"])
+    rng = np.random.default_rng(SITE_SEED)
+    links = np.stack([rng.integers(0, 4, NSITES), np.sort(rng.choice(V, NSITES, replace=False))], axis=1)
+    Fs = F[links[:, 0], links[:, 1]]
+    th = vjp.u1_derivative(F)[links[:, 0], links[:, 1]]
+    out = dict(case=name, params=p, generator="tests/golden/make_golden.py (oracle/ and synth/ only)",
+               s=_cl(s), ds_dmu=_cl(ds_dmu), links=links.tolist(), F_links=_cl(Fs), u1_links=_cl(th),
+               F_absmax=float(np.abs(F).max()), F_norm=float(np.linalg.norm(F)), min_margin=float(L["min_margin"]))
+    out.update(_coeffs(L, p["k"]))
+    out["oracle_seconds"] = round(time.time() - t0, 1)
+    return out
+
+
 def _work(item):
     name, p = item
-    res = run_case(name, p)
+    res = run_vjp_case(name, p) if p.get("kind") == "vjp" else run_case(name, p)
     path = os.path.join(HERE, f"{name}.json")
     with open(path, "w") as f:
         json.dump(res, f, separators=(",", ":"))
