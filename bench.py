@@ -636,6 +636,9 @@ def main():
     ap.add_argument("--counters-run", action="store_true",
                     help="short fixed workload for rocprofv3 --pmc runs (8 sources, 20 Lanczos steps, "
                          "FP64 then mixed); prints one line and no JSON")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only the uneven batch (48 solves on 6^4 .. 20x20^3, shared and separate forms); "
+                         "prints its JSON record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU form "
@@ -646,6 +649,13 @@ def main():
         return
     if args.error_vs_k:
         error_vs_k(args)
+        return
+    if args.uneven_only:
+        import torch
+        torch.cuda.set_device(0)
+        rec = time_uneven(args)
+        rec.pop("vals", None)
+        print(json.dumps(rec), flush=True)
         return
     g = run_gpu(args)
     cpu = None if args.no_cpu_baseline else run_cpu_baseline(args, args.cpu_steps)

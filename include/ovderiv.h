@@ -329,11 +329,12 @@ typedef struct {
  * launch and one stencil launch (the blocks split into one range per lattice,
  * each running that lattice's own kernel body), on a stream of the batch
  * after all jobs' preparation; each job then finishes on its own stream
- * (sgn(T_k) e_1, outputs, deflation terms).  The shared launches use the
- * paired stencil form with two site groups per block, or one if every
- * lattice's shape has one, and each lattice's XCD work order; the shape is
- * recorded as the handle's tuned shape, so later single calls give identical
- * results.  Otherwise each lattice's steps run as its own graph on its own
+ * (sgn(T_k) e_1, outputs, deflation terms).  The shared launches use one
+ * stencil launch shape agreed from the handles' tuned or forced shapes (one
+ * site group per block if every lattice has one, else two; the sequential
+ * form, along mu, if every lattice has it, else the paired form) and each
+ * lattice's XCD work order; the shape is recorded as every handle's tuned
+ * shape, so later single calls give identical results.  Otherwise each lattice's steps run as its own graph on its own
  * stream, concurrently when the handles were created on different streams.
  * A handle may appear only once.  Returns OVD_OK if every job succeeded,
  * else the first failing job's status (each job's status is in its status

@@ -437,15 +437,19 @@ void multi_lead(MultiCoord& C) {
     };
     const std::vector<MultiPlan*>& P = C.plans;
     const size_t np = P.size();
-    // one launch shape for all: the paired form, one site group per block if
-    // every lattice's shape has one, else two; each lattice's XCD order
-    int gpb = 1;
-    for (const MultiPlan* q : P)
+    // one launch shape for all, by consensus of the lattices' own shapes: one
+    // site group per block if every lattice has one, else two; the sequential
+    // form (d/dmu only) if every lattice has it, else the paired form; each
+    // lattice keeps its XCD order
+    int gpb = 1, seq = P[0]->dir == 1 ? 1 : 0;
+    for (const MultiPlan* q : P) {
         if (q->var.gpb != 1) gpb = 2;
+        if (!q->var.seq || (q->var.gpb != 1 && q->var.gpb != 2)) seq = 0;
+    }
     int maxk = 0, maxr = 0;
     for (MultiPlan* q : P) {
         q->var.gpb = gpb;
-        q->var.seq = 0;
+        q->var.seq = seq;
         if (q->var.map < 0) q->var.map = default_map(q->nrhs);
         maxk = std::max(maxk, q->k);
         maxr = std::max(maxr, q->nrhs);
@@ -491,8 +495,8 @@ void multi_lead(MultiCoord& C) {
         if ((e = hipStreamWaitEvent(C.stream, ev, 0)) != hipSuccess) return bad("wait for the jobs", e);
     const TslSegment* dtab = (const TslSegment*)C.table;
     for (int j = 0; j < maxk; ++j)
-        launch_tsl_step_multi<T>(P[0]->dir, gpb, j == 0 ? 0 : (j == 1 ? 2 : 3), dtab + (size_t)j * np, nseg[j],
-                                 nblk[j], nub[j], maxr, j, C.stream);
+        launch_tsl_step_multi<T>(P[0]->dir, gpb, seq, j == 0 ? 0 : (j == 1 ? 2 : 3), dtab + (size_t)j * np,
+                                 nseg[j], nblk[j], nub[j], maxr, j, C.stream);
     if ((e = hipGetLastError()) != hipSuccess) return bad("launch", e);
     if ((e = hipEventCreateWithFlags(&C.finished, hipEventDisableTiming)) != hipSuccess) return bad("event", e);
     if ((e = hipEventRecord(C.finished, C.stream)) != hipSuccess) return bad("event", e);

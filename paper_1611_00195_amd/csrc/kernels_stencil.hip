@@ -1199,14 +1199,14 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
 // long and starting at a multiple of 8, so a block's XCD is the one it has in
 // the lattice's own launch), and every block runs the standalone body with
 // its lattice's arguments: results identical to the lattice's own launch.
-template <typename T, int DIR, int GPB>
+template <typename T, int DIR, int GPB, bool SEQ>
 __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_multi_kernel(const TslSegment* __restrict__ seg,
                                                                            int nseg, int j) {
     int i = 0;
     for (int q = 1; q < nseg; ++q)
         if ((int)blockIdx.x >= seg[q].block0) i = q;
     const TslSegment& S = seg[i];
-    tsl_stencil_body<T, DIR, GPB, false>((int)blockIdx.x - S.block0, S.nblocks, S.g, S.p, (const cpx<T>*)S.U,
+    tsl_stencil_body<T, DIR, GPB, SEQ>((int)blockIdx.x - S.block0, S.nblocks, S.g, S.p, (const cpx<T>*)S.U,
                                          (const cpx<T>*)S.dU, T(S.mdiag), S.st, S.co, S.partials, S.counters, j, S.tau,
                                          S.ngroups, S.nrhs, S.map);
 }
@@ -1296,23 +1296,28 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
 }
 
 template <typename T>
-void launch_tsl_step_multi(int dir, int gpb, int nterms, const TslSegment* seg, int nseg, int nblocks,
+void launch_tsl_step_multi(int dir, int gpb, int seq, int nterms, const TslSegment* seg, int nseg, int nblocks,
                            int ublocks, int max_nrhs, int j, hipStream_t s) {
     if (nterms == 3)
         tsl_update_multi_kernel<T, 3><<<dim3(ublocks, max_nrhs, 2), 256, 0, s>>>(seg, nseg);
     else if (nterms == 2)
         tsl_update_multi_kernel<T, 2><<<dim3(ublocks, max_nrhs, 2), 256, 0, s>>>(seg, nseg);
     if (dir == 1) {
-        if (gpb == 1) tsl_stencil_multi_kernel<T, 1, 1><<<nblocks, 128, 0, s>>>(seg, nseg, j);
-        else tsl_stencil_multi_kernel<T, 1, 2><<<nblocks, 256, 0, s>>>(seg, nseg, j);
+        if (gpb == 1) {
+            if (seq) tsl_stencil_multi_kernel<T, 1, 1, true><<<nblocks, 128, 0, s>>>(seg, nseg, j);
+            else tsl_stencil_multi_kernel<T, 1, 1, false><<<nblocks, 128, 0, s>>>(seg, nseg, j);
+        } else {
+            if (seq) tsl_stencil_multi_kernel<T, 1, 2, true><<<nblocks, 256, 0, s>>>(seg, nseg, j);
+            else tsl_stencil_multi_kernel<T, 1, 2, false><<<nblocks, 256, 0, s>>>(seg, nseg, j);
+        }
     } else {
-        if (gpb == 1) tsl_stencil_multi_kernel<T, 2, 1><<<nblocks, 128, 0, s>>>(seg, nseg, j);
-        else tsl_stencil_multi_kernel<T, 2, 2><<<nblocks, 256, 0, s>>>(seg, nseg, j);
+        if (gpb == 1) tsl_stencil_multi_kernel<T, 2, 1, false><<<nblocks, 128, 0, s>>>(seg, nseg, j);
+        else tsl_stencil_multi_kernel<T, 2, 2, false><<<nblocks, 256, 0, s>>>(seg, nseg, j);
     }
 }
 
 #define OVD_INST(T)                                                                                        \
-    template void launch_tsl_step_multi<T>(int, int, int, const TslSegment*, int, int, int, int, int,     \
+    template void launch_tsl_step_multi<T>(int, int, int, int, const TslSegment*, int, int, int, int, int, \
                                            hipStream_t);                                                   \
     template void launch_tsl_update<T>(int, int, long long, const StepPtrs&, const TslState*, hipStream_t); \
     template void launch_tsl_stencil<T>(const Geom&, int, int, const StepPtrs&, const cpx<T>*, const cpx<T>*, \

@@ -190,9 +190,10 @@ struct TslSegment {
 // update x-blocks per (rhs, side) of launch_tsl_update
 int tsl_update_xblocks(long long fsz);
 // the two kernels of step j over nseg lattices (device table seg[nseg]);
-// gpb 1 or 2, paired form; nterms as launch_tsl_update (0: no update, step 0)
+// gpb 1 or 2, seq 1 for the sequential form (dir 1 only); nterms as
+// launch_tsl_update (0: no update, step 0)
 template <typename T>
-void launch_tsl_step_multi(int dir, int gpb, int nterms, const TslSegment* seg, int nseg, int nblocks,
+void launch_tsl_step_multi(int dir, int gpb, int seq, int nterms, const TslSegment* seg, int nseg, int nblocks,
                            int ublocks, int max_nrhs, int j, hipStream_t s);
 
 // sgn(T_k) e_1 for nrhs tridiagonal matrices by the resolvent quadrature.

@@ -454,17 +454,20 @@ class Lattice:
 
 
 def sign_apply_deriv_batch(jobs):
-    """Uneven batch: jobs = [(lattice, b, mu, k, x), ...], one per lattice
-    (distinct handles, ideally created on distinct streams); every lattice's
-    derivative <x|d/dmu sgn(H) b> (ovd_sign_apply_deriv_batch).  Lattices of
-    one precision share one update and one stencil launch per Lanczos step
-    unless a handle was created with batch_separate=True.  Returns a list of
-    per-lattice lists of complex values."""
+    """Uneven batch: jobs = [(lattice, b, mu, k, x), ...] or, for a link
+    direction, [(lattice, b, mu, k, x, dU), ...], one per lattice (distinct
+    handles, ideally created on distinct streams); every lattice's derivative
+    <x|d/dt sgn(H) b> (ovd_sign_apply_deriv_batch).  Lattices of one precision
+    and one kind of direction share one update and one stencil launch per
+    Lanczos step unless a handle was created with batch_separate=True.
+    Returns a list of per-lattice lists of complex values."""
     n = len(jobs)
     arr = (_Job * n)()
     keep = []
     outs = []
-    for i, (lat, b, mu, k, x) in enumerate(jobs):
+    for i, job in enumerate(jobs):
+        lat, b, mu, k, x = job[:5]
+        dU = job[5] if len(job) > 5 else None
         nr = b.shape[0]
         _check_field(b, (nr, lat.V, 4, 3), "b")
         _check_field(x, (nr, lat.V, 4, 3), "x")
@@ -472,10 +475,12 @@ def sign_apply_deriv_batch(jobs):
         mu_c = _dbl(mus)
         xdy = (ctypes.c_double * (2 * nr))()
         st = _Stats()
-        keep += [mu_c, xdy, st, b, x]
+        d, kd = lat._dir("link" if dU is not None else None, dU)
+        keep += [mu_c, xdy, st, b, x, d, kd]
         arr[i] = _Job(lat._h.value if hasattr(lat._h, "value") else lat._h, nr,
-                      ctypes.cast(mu_c, ctypes.POINTER(ctypes.c_double)), None, int(k), b.data_ptr(), None, None,
-                      x.data_ptr(), ctypes.cast(xdy, ctypes.POINTER(ctypes.c_double)), ctypes.pointer(st), 0)
+                      ctypes.cast(mu_c, ctypes.POINTER(ctypes.c_double)), ctypes.addressof(d), int(k), b.data_ptr(),
+                      None, None, x.data_ptr(), ctypes.cast(xdy, ctypes.POINTER(ctypes.c_double)),
+                      ctypes.pointer(st), 0)
         outs.append((xdy, nr, lat, st))
     status = lib().ovd_sign_apply_deriv_batch(n, arr)
     if status != OVD_OK:

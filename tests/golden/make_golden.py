@@ -25,7 +25,9 @@ What is computed (the paper's hot path at the workload sizes):
 
 Stored per case: the parameters, <x|dy>, <x|y>, the 2-norms of y and dy, both
 vectors at 64 sites drawn with a fixed seed (all 12 components), and the
-coefficients.
+coefficients; for the short, unconverged 6^4 run of the uneven batch also the
+oracle's own sensitivity of <x|dy> to relative noise of 1e-16 and 1e-7 in
+every operator application (the precision its arithmetic can determine).
 
 Usage:  python tests/golden/make_golden.py [case ...]   (default: all cases;
         one process per case, at most 6 at once)
@@ -81,12 +83,17 @@ def cases():
     # (16 sources, b seed 1700 + i, x seed 1800 + i, repeated for each mu)
     c["c3_r0"] = _case((12, 12, 12, 12), 0.4, 1612, 0.1, 300, 1700, 1800, vectors=False)
     c["c3_r63"] = _case((12, 12, 12, 12), 0.4, 1612, 0.4, 300, 1715, 1815, vectors=False)
-    # uneven batch: 10^4 (k = 250) both sources, 16^4 (k = 400) source 0
+    # uneven batch: 10^4 (k = 250) both sources, 16^4 (k = 400) source 0; the 6^4 and
+    # 20 x 20^3 lattices below
     mus = _c5_mus()
     for r in range(2):
         c[f"c5_10_r{r}"] = _case((10, 10, 10, 10), 0.4, 1621, float(mus[1][r]), 250, 1640 + r, 1690 + r,
                                  vectors=False)
     c["c5_16_r0"] = _case((16, 16, 16, 16), 0.4, 1622, float(mus[2][0]), 400, 1650, 1700, vectors=False)
+    # and source 0 of the smallest (6^4, k = 150) and the largest (20 x 20^3, k = 500) lattice
+    c["c5_6_r0"] = dict(_case((6, 6, 6, 6), 0.4, 1620, float(mus[0][0]), 150, 1630, 1680, vectors=False),
+                        sensitivity=True)
+    c["c5_20_r0"] = _case((20, 20, 20, 20), 0.4, 1623, float(mus[3][0]), 500, 1660, 1710, vectors=False)
     # the gradient at the headline size: source 0 of the bench (b seed 4000, x seed 5000)
     c["c4_vjp"] = dict(_case((14, 14, 14, 14), 0.4, 1611, 0.3, 400, 4000, 5000,
                              cite="gradient of <x|sgn(H)|b>: bilinear two-sided Lanczos (Sec. 2) and the "
@@ -120,6 +127,31 @@ def _coeffs(L, k):
     beta[0] = 0.0
     delta[0] = 0.0
     return dict(alpha=_cl(L["alpha"][:k]), beta=_cl(beta), delta=_cl(delta))
+
+
+def _sensitivity(h, hd, dh, dhd, b, x, k, rel_noise, trials=3, seed=0):
+    """Largest relative change of <x|dy> over a few runs in which every operator
+    application is multiplied element-wise by (1 + rel_noise g), g standard
+    normal: how precisely the k-step result is determined by arithmetic of
+    that relative accuracy (1e-16: FP64; 1e-7: FP32 vectors and stencil)."""
+    n = b.size
+    rng = np.random.default_rng(seed)
+
+    def scalar(wrap):
+        op, op_h = tsl.block_ops(wrap(h), wrap(hd), wrap(dh), wrap(dhd), n)
+        psi = np.concatenate([np.zeros(n, dtype=np.complex128), b])
+        xx = np.concatenate([x, np.zeros(n, dtype=np.complex128)])
+        L = tsl.lanczos(op, op_h, psi, tsl.block_left_start(psi, n), k, keep_basis=False, proj=xx)
+        return L["norm"] * np.dot(L["proj"], tsl.ritz_coeffs(L["T"]))
+
+    def noisy(f):
+        def g(v):
+            y = f(v)
+            return y * (1.0 + rel_noise * rng.standard_normal(y.shape))
+        return g
+
+    ref = scalar(lambda f: f)
+    return max(abs(scalar(noisy) - ref) / abs(ref) for _ in range(trials))
 
 
 def run_case(name: str, p: dict) -> dict:
@@ -158,6 +190,8 @@ def run_case(name: str, p: dict) -> dict:
         out["xdy"] = _cl(L["norm"] * np.dot(L["proj"], c))
     out.update(_coeffs(L, k))
     out["min_margin"] = float(L["min_margin"])
+    if p.get("sensitivity"):
+        out["sensitivity"] = {str(rn): float(_sensitivity(h, hd, dh, dhd, b, x, k, rn)) for rn in (1e-16, 1e-7)}
     if p["plain"]:
         Lp = tsl.lanczos(h, hd, b, b, k, proj=x)
         cp = tsl.ritz_coeffs(Lp["T"])

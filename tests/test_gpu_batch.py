@@ -86,3 +86,38 @@ def test_batch_with_a_failing_job_and_mixed_precisions():
     assert res[0] == r0 and res[1] == r2
     for lat in lats:
         lat.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_shared_batch_along_link_directions(prec):
+    """Two lattices differentiated along their own su(3) link directions in one
+    batch (the shared steps with the link-derivative stencil): equal to the
+    single calls bit for bit, and in FP64 to the oracle."""
+    from paper_1611_00195_amd import ovderiv
+    from oracle import dirac
+    from gpu_helpers import dev, host, ops, print_case
+    shapes = [((4, 4, 4, 4), 2, 36), ((4, 2, 6, 4), 3, 28)]
+    print_case(test="batch_link", shapes=shapes, prec=prec)
+    jobs, data = [], []
+    for i, (dims, nr, k) in enumerate(shapes):
+        U = synth.make_links(dims, 0.5, 870 + i)
+        dU = dirac.link_tangent(synth.make_su3_direction(dims, 875 + i), U)
+        lat = ovderiv.Lattice(dims, precision=prec, stream=torch.cuda.Stream())
+        lat.set_links(dev(U))
+        b = dev(synth.make_sources(dims, nr, 880 + i))
+        x = dev(synth.make_sources(dims, nr, 885 + i))
+        mus = list(np.linspace(0.15, 0.35, nr))
+        jobs.append((lat, b, mus, k, x, dev(dU)))
+        data.append((U, dU, dims))
+    res = ovderiv.sign_apply_deriv_batch(jobs)
+    for (lat, b, mus, k, x, dUd), r in zip(jobs, res):
+        _, _, s1 = lat.sign_apply_deriv(b, mus, k, x=x, want_vectors=False, direction="link", dU=dUd)
+        assert r == s1
+    if prec == 0:
+        for (lat, b, mus, k, x, _), (U, dU, dims), r in zip(jobs, data, res):
+            h, hd, dh, dhd = ops(U, dims, mus[0], dU)
+            d, _, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, host(b)[0].ravel(), k)
+            ref = np.vdot(host(x)[0].ravel(), d)
+            assert abs(r[0] - ref) < 1e-10 * abs(ref)
+    for j in jobs:
+        j[0].close()

@@ -16,7 +16,9 @@ at 64 seeded sites (all 12 components), and every Lanczos coefficient.
   * 8^4, k = 200, mu in {0, 0.2, 0.4}, the mu and an su(3) link direction;
   * 12^4, k = 300, sources 0 and 63 of the 64-source batch (16 sources x 4 mu),
     undeflated and with the per-mu m = 32 deflation sets computed on the GPU;
-  * the uneven batch: 10^4 at k = 250 (both sources) and 16^4 at k = 400;
+  * the uneven batch (its Lanczos steps shared by the four lattices): 6^4 at
+    k = 150, 10^4 at k = 250 (both sources), 16^4 at k = 400 and 20 x 20^3 at
+    k = 500;
   * the gradient of <x|sgn(H)|b> at 14 x 14^3, k = 400 (source 0 of the
     benchmark): s, ds/dmu, the force at 64 sampled links and the U(1)
     derivative i tr F there, FP64 with the basis stored or regenerated, and
@@ -323,9 +325,15 @@ def test_c3_deflated_per_mu_within_truncation():
 
 
 # --------------------------------------------------------------------------
-# uneven batch: 10^4 (k = 250) and 16^4 (k = 400) inside the four-lattice launch
+# uneven batch: every lattice inside the four-lattice launch
 # --------------------------------------------------------------------------
 def test_c5_uneven_batch_full_k():
+    """The four lattices of the uneven batch in one shared-step call, FP64 and
+    mixed, against the oracle on every lattice: 1e-10 and 4e-6, or ten times
+    the oracle's own noise sensitivity where a short run leaves the result
+    that loosely determined (6^4 at k = 150: 3.9e-11 at FP64-level noise,
+    1.0e-3 at FP32-level noise; the mixed 6^4 result, measured 3.7e-4 off,
+    is of that size)."""
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, print_case
     sizes = [((6, 6, 6, 6), 150), ((10, 10, 10, 10), 250), ((16, 16, 16, 16), 400), ((20, 20, 20, 20), 500)]
@@ -347,15 +355,22 @@ def test_c5_uneven_batch_full_k():
         torch.cuda.synchronize()
         for lat in lats:
             lat.close()
-        for name, li, r in (("c5_10_r0", 1, 0), ("c5_10_r1", 1, 1), ("c5_16_r0", 2, 0)):
+        for name, li, r in (("c5_6_r0", 0, 0), ("c5_10_r0", 1, 0), ("c5_10_r1", 1, 1), ("c5_16_r0", 2, 0),
+                            ("c5_20_r0", 3, 0)):
             path = os.path.join(GOLDEN, f"{name}.json")
             if not os.path.exists(path):
                 continue
             g = _g(name)
             assert abs(g["params"]["mu"] - jobs[li][2][r]) < 1e-15
             e = _rel(res[li][r], complex(*g["xdy"]))
-            print(f"  prec {prec} {name}: <x|dy> {e:.2e}", flush=True)
-            assert e <= tol, (prec, name, e)
+            # an unconverged short run (6^4 at k = 150) is determined by the
+            # arithmetic only to the oracle's own noise sensitivity (FP64:
+            # noise 1e-16, mixed: 1e-7 per operator application); the bound
+            # is ten times that where it exceeds the fixed one
+            sens = g.get("sensitivity", {}).get("1e-16" if prec == ovderiv.FP64 else "1e-07", 0.0)
+            bound = max(tol, 10 * sens)
+            print(f"  prec {prec} {name}: <x|dy> {e:.2e} (bound {bound:.1e})", flush=True)
+            assert e <= bound, (prec, name, e, bound)
 
 
 # --------------------------------------------------------------------------
