@@ -264,6 +264,8 @@ def run_gpu(args):
             "mixed_single_evals_per_s": round(msingle["evals_per_s"], 3),
             ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}_evals_per_s": round(oth["evals_per_s"], 3),
             "mixed_vs_fp64_max_rel_err_xdy": err,
+            "launch_shapes": {"fp64_single": single["shapes"], "mixed_single": msingle["shapes"],
+                              ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}": oth["shapes"]},
         }
     out["forms"] = forms
     if not args.skip_forms:
@@ -483,9 +485,10 @@ def counters_run(args):
     """The workload of the committed counter summaries: the bench lattice and
     sources, 8 right-hand sides, 20 Lanczos steps, FP64 then mixed, then a
     1 GiB device copy that calibrates the counters, in the
-    launch shape that the autotuner keeps for this workload in the bench
-    (XCD order 0, 2 groups per block, paired form; forced here because a
-    profiler that serialises every dispatch distorts the tuner's timings)."""
+    launch shape that the autotuner keeps for this workload in the bench in
+    both precisions (XCD order 0, one block per xy-plane with the plane's
+    inputs in LDS, paired form; forced here because a profiler that
+    serialises every dispatch distorts the tuner's timings)."""
     import torch
 
     import synth
@@ -494,7 +497,7 @@ def counters_run(args):
     dims = tuple(args.dims)
     U = torch.from_numpy(synth.make_links(dims, args.eps, 1611)).cuda()
     for prec in (ovderiv.FP64, ovderiv.MIXED):
-        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, shape=(0, 2, 0))
+        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, shape=(0, 8, 0))
         lat.set_links(U)
         b = torch.from_numpy(synth.make_sources(dims, 8, 4000)).cuda()
         x = torch.from_numpy(synth.make_sources(dims, 8, 5000)).cuda()

@@ -1121,17 +1121,23 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
 
     }
 
+    // Grid reduction without a device-wide fence.  The block's partial sums are
+    // stored with device-scope relaxed atomic stores, which are written through
+    // to the level that all XCDs see; the wait for those stores to complete
+    // orders them before the counter increment; the last block reads the
+    // partials with device-scope loads from that same level.  A full fence
+    // (__threadfence) here would write back and invalidate the XCD's L2 at the
+    // end of every block, costing the stencil a third of its time.
     block_reduce<8>(part, lds);
     if (threadIdx.x == 0) {
         double* dst = partials + ((size_t)rhs * nb + wk.grp) * 8;
         for (int i = 0; i < 8; ++i) __hip_atomic_store(dst + i, part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned prev = atomicAdd(counters + rhs, 1u);
+        __builtin_amdgcn_s_waitcnt(0);   // the partials have reached the device-coherent level
+        const unsigned prev = __hip_atomic_fetch_add(counters + rhs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         am_last = (prev == (unsigned)(nb - 1));
     }
     __syncthreads();
     if (!am_last) return;
-    __threadfence();
     double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         const double* src = partials + ((size_t)rhs * nb + b) * 8;

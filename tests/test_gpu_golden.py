@@ -97,10 +97,12 @@ def _rel(a, b):
 # Bounds of the mixed-precision results (FP32 vectors and stencil, FP64
 # scalars) against the FP64 oracle, per workload: about three times the
 # largest value measured on MI355X, never above the 1e-5 target where the
-# measurement allows it.  Measured: 14 x 14^3 k = 400: <x|dy> 2.3e-6, dy at the
-# sampled sites 3.1e-6, deflated 3.7e-6; 8^4 k = 200: 3.5e-6 (dy at sites,
-# mu = 0.4); 12^4 k = 300: 1.7e-5 (source 63, mu = 0.4; 1.6e-7 at mu = 0.1);
-# uneven batch: 1.1e-6.
+# measurement allows it.  Measured, over the launch shapes the tuner has kept
+# (each rounds differently): 14 x 14^3 k = 400: <x|dy> up to 2.3e-6, dy at the
+# sampled sites up to 4.0e-6, deflated up to 5.2e-6; 8^4 k = 200: 3.5e-6 (dy at
+# sites, mu = 0.4); 12^4 k = 300: up to 1.7e-5 (source 63, mu = 0.4; below
+# 7e-7 at mu = 0.1); uneven batch: up to 1.1e-6 (the 6^4 run is bounded by
+# the oracle's own noise sensitivity instead).
 MIXED_TOL = {"c4": 1e-5, "c2": 1e-5, "c3": 5e-5, "c5": 4e-6}
 
 
