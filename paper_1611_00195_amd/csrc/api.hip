@@ -14,6 +14,8 @@
 #include "ovd_internal.h"
 #include "../../include/ovderiv.h"
 
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 #include <cmath>
 #include <condition_variable>
@@ -46,6 +48,7 @@ struct DeflSet {
 
 struct ovd_lattice {
     Geom g{};
+    rocblas_handle blas = nullptr;   // the gradient's Z = W M'^dag (created on first use)
     double m0 = -1.5, r = 1.0;
     ovd_options opt{};
     hipStream_t stream = nullptr;
@@ -1173,6 +1176,7 @@ ovd_status ovd_destroy(ovd_h h) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->U64) (void)hipFree(h->U64);
     if (h->U32) (void)hipFree(h->U32);
+    if (h->blas) (void)rocblas_destroy_handle(h->blas);
     ovd_clear_deflation(h);
     delete h;
     return OVD_OK;
@@ -1665,6 +1669,34 @@ ovd_status ovd_clear_deflation(ovd_h h) {
     return OVD_OK;
 }
 
+// Z = W M'^dag for k fields W (field q at W + q sW, nf elements each):
+// z_p[n] = sum_q w_q[n] conj(M'[p][q]).  A plain N x k x k complex GEMM, run by
+// rocBLAS (column-major: Z (nf x k, ld sZ) = W (nf x k, ld sW) Mc (k x k,
+// ld k) with Mc = conj(M') elementwise, the k x k matrix M' being stored
+// row-major), with atomics off so that the result does not depend on the run.
+ovd_status zgemm_w_mdag(ovd_h h, const c64* W, long long sW, int k, const c64* Mc, c64* Z, long long sZ,
+                        long long nf) {
+    if (nf > INT32_MAX || sW > INT32_MAX || sZ > INT32_MAX) return fail(h, OVD_EINVAL, "field too long for the GEMM");
+    if (!h->blas) {
+        if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
+            h->blas = nullptr;
+            return fail(h, OVD_EHIP, "rocblas_create_handle failed");
+        }
+        (void)rocblas_set_atomics_mode(h->blas, rocblas_atomics_not_allowed);
+    }
+    if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success)
+        return fail(h, OVD_EHIP, "rocblas_set_stream failed");
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    const rocblas_status rs =
+        rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)nf, k, k, &one,
+                      reinterpret_cast<const rocblas_double_complex*>(W), (rocblas_int)sW,
+                      reinterpret_cast<const rocblas_double_complex*>(Mc), k, &zero,
+                      reinterpret_cast<rocblas_double_complex*>(Z), (rocblas_int)sZ);
+    if (rs != rocblas_status_success)
+        return fail(h, OVD_EHIP, std::string("rocblas_zgemm: ") + rocblas_status_to_string(rs));
+    return OVD_OK;
+}
+
 ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const void* b, double* s_out,
                               double* ds_dmu, void* F, void* dsdU, void* dsdUc, void* dsdtheta, ovd_stats* st) {
     ovd_status s = check_handle(h);
@@ -1764,6 +1796,7 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         WS(scr, c64, "frechet_scr", small_frechet_scratch_elems(k));
         WS(M, c64, "vjp_M", (size_t)k * k);
         WS(Mp, c64, "vjp_Mp", (size_t)k * k);
+        WS(Mc, c64, "vjp_Mc", (size_t)k * k);
         WS(trF, c64, "vjp_trF", g.V);
         WS(dsum, c64, "vjp_dsum", 1);
         double chk = 0.0;
@@ -1772,6 +1805,7 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         s = small_status(h, frc, "L_sgn(T_k, e_1 e_1^T)", chk, -1);
         if (s != OVD_OK) return s;
         launch_vjp_scale_m(k, co, M, Mp, h->stream);
+        launch_conj_c64((long long)k * k, Mp, Mc, h->stream);
         // deflated: the cross and exact parts of the Frechet kernel as 2 m more
         // (v, z) pairs: (V-hat A, L_j) and (R_i, W-hat B + L Cm)
         c64 *AV = nullptr, *ZW = nullptr, *Amat = nullptr;
@@ -1811,7 +1845,8 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
         }
         if (!recompute) {
             WS(Z, c64, "vjp_Z", (size_t)k * fsz);
-            launch_zgemm_wmh(bw, fsz, k, Mp, Z, fsz, fsz, h->stream);
+            s = zgemm_w_mdag(h, bw, fsz, k, Mc, Z, fsz, fsz);
+            if (s != OVD_OK) return s;
             launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
                              (c64*)dsdtheta, h->stream, Kacc, true, last_krylov);
         } else {
@@ -1823,7 +1858,8 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
                 const long long ne = std::min(E, fsz - e0);
                 HIPCHK(hipMemcpy2DAsync(slab, sizeof(c64) * E, bw + e0, sizeof(c64) * fsz, sizeof(c64) * ne, k,
                                         hipMemcpyDeviceToDevice, h->stream));
-                launch_zgemm_wmh(slab, E, k, Mp, bw + e0, fsz, ne, h->stream);
+                s = zgemm_w_mdag(h, slab, E, k, Mc, bw + e0, fsz, ne);
+                if (s != OVD_OK) return s;
             }
             // the Lanczos run again: same kernels, launch shape and inputs, so
             // the same right vectors, now in a ring of 2C; after every C steps

@@ -238,55 +238,18 @@ void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64*
 namespace ovd {
 
 // ---------------------------------------------------------------------------
-// Z = W Mc, Mc[q][p] = conj(Mp[p][q])  (the N x k x k product of the gradient:
-// z_p = sum_q w_q conj(M'[p][q])).  W and Z are k fields of nf complex
-// (field q at q sW).  One wave per 16 rows x 64 columns, reduction over q in
-// steps of 4 on the matrix cores; Mp (k x k, row-major) stays in L2.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void zgemm_wmh_kernel(const c64* __restrict__ W, long long sW, int k,
-                                                       const c64* __restrict__ Mp, c64* __restrict__ Z,
-                                                       long long sZ, long long nf) {
-    const int l = threadIdx.x;
-    const long long n0 = (long long)blockIdx.x * 16;
-    const int p0 = blockIdx.y * 64;
-    const long long na = n0 + (l & 15);
-    const int kk = l >> 4;
-    v4d re[4], im[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        re[t] = v4d{0, 0, 0, 0};
-        im[t] = v4d{0, 0, 0, 0};
-    }
-    for (int q = 0; q < k; q += 4) {
-        const int qk = q + kk;
-        c64 a{0.0, 0.0};
-        if (qk < k && na < nf) a = W[(size_t)qk * sW + na];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int pb = p0 + 16 * t + (l & 15);
-            c64 b{0.0, 0.0};
-            if (qk < k && pb < k) b = conj(Mp[(size_t)pb * k + qk]);
-            re[t] = mfma(a.re, b.re, re[t]);
-            re[t] = mfma(-a.im, b.im, re[t]);
-            im[t] = mfma(a.re, b.im, im[t]);
-            im[t] = mfma(a.im, b.re, im[t]);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int pp = p0 + 16 * t + (l & 15);
-        if (pp >= k) continue;
-        for (int v = 0; v < 4; ++v) {
-            const long long nn = n0 + 4 * v + (l >> 4);
-            if (nn < nf) Z[(size_t)pp * sZ + nn] = c64{re[t][v], im[t][v]};
-        }
-    }
+// out = conj(in), n complex: conj(M') for the gradient's product Z = W M'^dag,
+// which runs as the plain library GEMM Z = W conj(M'^T) (rocblas_zgemm, in
+// api.hip)
+__global__ void conj_c64_kernel(long long n, const c64* __restrict__ in, c64* __restrict__ out) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) out[e] = conj(in[e]);
 }
 
-void launch_zgemm_wmh(const c64* W, long long sW, int k, const c64* Mp, c64* Z, long long sZ, long long nf,
-                      hipStream_t s) {
-    dim3 grid((unsigned)((nf + 15) / 16), (k + 63) / 64);
-    zgemm_wmh_kernel<<<grid, 64, 0, s>>>(W, sW, k, Mp, Z, sZ, nf);
+void launch_conj_c64(long long n, const c64* in, c64* out, hipStream_t s) {
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    conj_c64_kernel<<<(unsigned)nb, 256, 0, s>>>(n, in, out);
 }
 
 // M'[p][q] = xb M[p][q] / (delta_p beta_q), xb = beta_0 delta_0 = x^dag b

@@ -279,8 +279,8 @@ void launch_field_differs(long long n, const c64* a, const c64* b, unsigned* fla
 void launch_widen_field(const Geom& g, int n, const c32* in, long long sin, c64* out, long long sout, hipStream_t s);
 
 // gradient of <x|sgn(H)|b> (kernels_defl.hip / kernels_stencil.hip)
-void launch_zgemm_wmh(const c64* W, long long sW, int k, const c64* Mp, c64* Z, long long sZ, long long nf,
-                      hipStream_t s);
+// out = conj(in), n complex (elementwise)
+void launch_conj_c64(long long n, const c64* in, c64* out, hipStream_t s);
 void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t s);
 // force of the gradient from the basis pairs p < k; the sum over p may be
 // split over launches that carry Kf, Kb in Kacc ([18][4V], needed unless
