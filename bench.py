@@ -54,9 +54,9 @@ def update_bytes_per_site(prec_bytes: int) -> float:
 
 def measured_traffic(pb: int, nrhs: int, shapes: str = ""):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current stencil source, this workload and
-    the launch shape (groups per block, paired or sequential form) that the
-    autotuner kept in this run; else None."""
+    summary, if it was taken on the current stencil source and this workload,
+    for the launch shape (XCD order, groups per block, paired or sequential
+    form) that the autotuner kept in this run; else None."""
     import hashlib
     import re
     src = os.path.join(ROOT, "paper_1611_00195_amd", "csrc", "kernels_stencil.hip")
@@ -69,19 +69,13 @@ def measured_traffic(pb: int, nrhs: int, shapes: str = ""):
         if ":" in line:
             a, b = line.split(":", 1)
             kv[a.strip()] = b.strip()
-    key = f"bytes_per_launch_{'fp64' if pb == 8 else 'fp32'}_nrhs{nrhs}"
-    if kv.get("kernels_stencil_sha256_16") != digest or key not in kv:
+    # the tuned entry "tsl:d:1:<nrhs>=map<m>,gpb<G>[,seq];" of this run
+    run = re.search(rf"tsl:{'d' if pb == 8 else 'f'}:1:{nrhs}=map(\d+),gpb(\d+)(,seq)?;", shapes)
+    if kv.get("kernels_stencil_sha256_16") != digest or run is None:
         return None
-    tag = "fp64" if pb == 8 else "fp32"
-    # kernel name "tsl_stencil_kernel<double, 1, G, false|true>" against the
-    # tuned entry "tsl:d:1:<nrhs>=map<m>,gpb<G>[,seq];" of this run
-    prof = re.search(r"<\w+, \d+, (\d+), (true|false)>", kv.get(f"kernel_{tag}_nrhs{nrhs}", ""))
-    run = re.search(rf"tsl:{'d' if pb == 8 else 'f'}:1:{nrhs}=map\d+,gpb(\d+)(,seq)?;", shapes)
-    if prof is None or (shapes and run is None):
-        return None
-    if run is not None and (prof.group(1) != run.group(1) or (prof.group(2) == "true") != bool(run.group(2))):
-        return None
-    return float(kv[key])
+    key = (f"bytes_per_launch_{'fp64' if pb == 8 else 'fp32'}_nrhs{nrhs}_map{run.group(1)}_gpb{run.group(2)}"
+           f"{'_seq' if run.group(3) else ''}")
+    return float(kv[key]) if key in kv else None
 
 
 def dwv_bytes_per_site(prec_bytes: int) -> float:
@@ -481,14 +475,19 @@ def error_vs_k(args):
     print(json.dumps({"error_vs_k": out}))
 
 
+# the stencil launch shapes the autotuner chooses among at 14^4 with 8 sources
+# (groups per block, sequential form); each is run in both XCD orders
+COUNTER_SHAPES = ((8, 0), (1, 0), (2, 0), (1, 1), (2, 1))
+
+
 def counters_run(args):
     """The workload of the committed counter summaries: the bench lattice and
-    sources, 8 right-hand sides, 20 Lanczos steps, FP64 then mixed, then a
-    1 GiB device copy that calibrates the counters, in the
-    launch shape that the autotuner keeps for this workload in the bench in
-    both precisions (XCD order 0, one block per xy-plane with the plane's
-    inputs in LDS, paired form; forced here because a profiler that
-    serialises every dispatch distorts the tuner's timings)."""
+    sources, 8 right-hand sides, 20 Lanczos steps, FP64 then mixed, in every
+    launch shape the autotuner chooses among (each kernel in XCD order 0 and
+    then order 1), then a 1 GiB device copy that calibrates the counters.
+    The shapes are forced, since a profiler that serialises every dispatch
+    distorts the tuner's timings; the bench then takes the counts of the
+    shape its own run kept."""
     import torch
 
     import synth
@@ -496,13 +495,16 @@ def counters_run(args):
 
     dims = tuple(args.dims)
     U = torch.from_numpy(synth.make_links(dims, args.eps, 1611)).cuda()
+    b = torch.from_numpy(synth.make_sources(dims, 8, 4000)).cuda()
+    x = torch.from_numpy(synth.make_sources(dims, 8, 5000)).cuda()
     for prec in (ovderiv.FP64, ovderiv.MIXED):
-        lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, shape=(0, 8, 0))
-        lat.set_links(U)
-        b = torch.from_numpy(synth.make_sources(dims, 8, 4000)).cuda()
-        x = torch.from_numpy(synth.make_sources(dims, 8, 5000)).cuda()
-        lat.sign_apply_deriv(b, [args.mu] * 8, 20, x=x, want_vectors=False)
-        lat.close()
+        for gpb, seq in COUNTER_SHAPES:
+            for order in (0, 1):
+                lat = ovderiv.Lattice(dims, m0=args.m0, precision=prec, shape=(order, gpb, seq))
+                lat.set_links(U)
+                lat.sign_apply_deriv(b, [args.mu] * 8, 20, x=x, want_vectors=False)
+                torch.cuda.synchronize()
+                lat.close()
     # calibration: a plain 1 GiB device-to-device copy (1 GiB read, 1 GiB written)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)

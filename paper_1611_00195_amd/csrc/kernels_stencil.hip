@@ -198,6 +198,9 @@ __device__ __forceinline__ cpx<T> mulk(cpx<T> z) {
     else return {z.im, -z.re};
 }
 
+typedef double ovd_d2 __attribute__((ext_vector_type(2)));
+typedef float ovd_f4 __attribute__((ext_vector_type(4)));
+
 // one 16-byte plane entry: one complex in FP64, two in FP32
 template <typename T>
 __device__ __forceinline__ void ld_plane(const char* __restrict__ base, uint32_t off, cpx<T>* dst) {
@@ -218,6 +221,22 @@ __device__ __forceinline__ void ld_site(const char* __restrict__ P, uint32_t Vp1
     for (int q = 0; q < 12 / per; ++q) ld_plane<T>(P + (size_t)q * Vp16, off, v + q * per);
 }
 
+// a site read once per launch (the x projection field), non-temporal
+template <typename T>
+__device__ __forceinline__ void ld_site_nt(const char* __restrict__ P, uint32_t Vp16, uint32_t off, cpx<T> (&v)[12]) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        if constexpr (sizeof(T) == 8) {
+            const ovd_d2 d = __builtin_nontemporal_load(reinterpret_cast<const ovd_d2*>(P + (size_t)q * Vp16 + off));
+            v[q] = {d.x, d.y};
+        } else if (q < 6) {
+            const ovd_f4 t = __builtin_nontemporal_load(reinterpret_cast<const ovd_f4*>(P + (size_t)q * Vp16 + off));
+            v[2 * q] = {t.x, t.y};
+            v[2 * q + 1] = {t.z, t.w};
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void ld_link(const char* __restrict__ W, uint32_t Vp16, int nu, uint32_t off,
                                         cpx<T> (&u)[9]) {
@@ -233,17 +252,20 @@ __device__ __forceinline__ void ld_link(const char* __restrict__ W, uint32_t Vp1
     }
 }
 
+// The stencil's outputs are written once and not read again by the launch:
+// non-temporal stores keep them from displacing the neighbour planes and
+// links that the launch still reuses from the L2.
 template <typename T>
 __device__ __forceinline__ void store_site(char* __restrict__ P, uint32_t Vp16, uint32_t off, const cpx<T> (&v)[12]) {
     if constexpr (sizeof(T) == 8) {
 #pragma unroll
         for (int c = 0; c < 12; ++c)
-            *reinterpret_cast<double2*>(P + (size_t)c * Vp16 + off) = double2{v[c].re, v[c].im};
+            __builtin_nontemporal_store(ovd_d2{v[c].re, v[c].im}, reinterpret_cast<ovd_d2*>(P + (size_t)c * Vp16 + off));
     } else {
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-            *reinterpret_cast<float4*>(P + (size_t)q * Vp16 + off) =
-                float4{v[2 * q].re, v[2 * q].im, v[2 * q + 1].re, v[2 * q + 1].im};
+            __builtin_nontemporal_store(ovd_f4{v[2 * q].re, v[2 * q].im, v[2 * q + 1].re, v[2 * q + 1].im},
+                                        reinterpret_cast<ovd_f4*>(P + (size_t)q * Vp16 + off));
     }
 }
 
@@ -547,6 +569,25 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* [16
 // up to that one rounding, instead of coefficients rounded to FP32 and three
 // FP32 products and sums.  The kernel is HBM-bound; FP64 costs nothing here.
 // ---------------------------------------------------------------------------
+// The update streams each element once: non-temporal loads and stores (the
+// fields are far larger than the L2, and the hint keeps them from evicting
+// lines still in use).
+typedef float ovd_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ c64 ld_nt(const cpx<double>* p) {
+    const ovd_d2 v = __builtin_nontemporal_load(reinterpret_cast<const ovd_d2*>(p));
+    return c64{v.x, v.y};
+}
+__device__ __forceinline__ c64 ld_nt(const cpx<float>* p) {
+    const ovd_f2 v = __builtin_nontemporal_load(reinterpret_cast<const ovd_f2*>(p));
+    return c64{(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void st_nt(cpx<double>* p, c64 r) {
+    __builtin_nontemporal_store(ovd_d2{r.re, r.im}, reinterpret_cast<ovd_d2*>(p));
+}
+__device__ __forceinline__ void st_nt(cpx<float>* p, c64 r) {
+    __builtin_nontemporal_store(ovd_f2{(float)r.re, (float)r.im}, reinterpret_cast<ovd_f2*>(p));
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ void tsl_update_body(const int bx, const int nbx, const int rhs, const bool vside,
                                                 const StepPtrs& p, long long n_elem,
@@ -562,9 +603,9 @@ __device__ __forceinline__ void tsl_update_body(const int bx, const int nbx, con
     cpx<T>* O = vside ? (cpx<T>*)p.outV + rhs * p.sV : (cpx<T>*)p.outW + rhs * p.sW;
     const long long stride = (long long)nbx * blockDim.x;
     for (long long e = (long long)bx * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
-        c64 r = a * cast<double>(X[e]) + b * cast<double>(Y[e]);
-        if constexpr (NT == 3) r += c * cast<double>(Z[e]);
-        O[e] = cast<T>(r);
+        c64 r = a * ld_nt(X + e) + b * ld_nt(Y + e);
+        if constexpr (NT == 3) r += c * ld_nt(Z + e);
+        st_nt(O + e, r);
     }
 }
 
@@ -1038,7 +1079,8 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
                 nrm_acc(part, (DIR == 0 || vside) ? 6 : 7, a);
                 if ((DIR == 0 || vside) && Xb) {          // p = x^dag vhat_top
                     cpx<T> x[12];
-                    ld_site<T>(Xb, Vp16, so, x);
+                                        if constexpr (sizeof(T) == 8) ld_site_nt<T>(Xb, Vp16, so, x);   // measured: FP32 gains nothing
+                    else ld_site<T>(Xb, Vp16, so, x);
                     dot_acc(part, 4, x, a);
                 }
                 if (DIR == 0) {                           // omega = what^dag vhat
