@@ -1716,9 +1716,10 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
     bool recompute = false;
     if (grad) {
         const size_t f64 = sizeof(c64) * fsz, f32 = sizeof(c32) * fsz;
-        const size_t need = (size_t)3 * k * f64 + (mixed ? (size_t)2 * k * f32 : 0);
-        recompute = recompute_basis(h, need, {"vjp_basis_v", "vjp_basis_w", "vjp_Z", "vjp_basis_v32", "vjp_basis_w32"},
-                                    &wst);
+        const size_t need = (size_t)3 * k * f64 + (mixed ? (size_t)2 * k * f32 : 0) +
+                            sizeof(c64) * vjp_force_scratch_elems(g, vjp_force_chunks(g, k));
+        recompute = recompute_basis(
+            h, need, {"vjp_basis_v", "vjp_basis_w", "vjp_Z", "vjp_basis_v32", "vjp_basis_w32", "vjp_kpart"}, &wst);
         if (wst != OVD_OK) return wst;
     }
     if (st) st->basis_recomputed = recompute ? 1 : 0;
@@ -1847,8 +1848,14 @@ ovd_status ovd_sign_apply_vjp(ovd_h h, double mu, int k, const void* x, const vo
             WS(Z, c64, "vjp_Z", (size_t)k * fsz);
             s = zgemm_w_mdag(h, bw, fsz, k, Mc, Z, fsz, fsz);
             if (s != OVD_OK) return s;
+            const int nchunk = vjp_force_chunks(g, k);
+            c64* Kpart = nullptr;
+            if (nchunk > 1) {
+                WS(kp, c64, "vjp_kpart", vjp_force_scratch_elems(g, nchunk));
+                Kpart = kp;
+            }
             launch_vjp_force(g, k, bv, fsz, Z, fsz, h->U64, std::exp(mu), (c64*)F, (c64*)dsdU, (c64*)dsdUc, trF,
-                             (c64*)dsdtheta, h->stream, Kacc, true, last_krylov);
+                             (c64*)dsdtheta, h->stream, Kacc, true, last_krylov, Kpart, nchunk);
         } else {
             // Z over W in place, a slab of field elements at a time through a
             // k x E copy

@@ -144,12 +144,116 @@ __global__ void axpy_ratio_kernel(long long n_elem, const c64* X, double sgn, co
     }
 }
 
+// out_j = a_j X_j + b_j Y_j + c_j Z_j for nr columns of nf elements (column j
+// at offset j nf), coefficients coef[j][3] on the device; Y, Z may be null;
+// out may be X or Y (each element is read before it is written)
+__global__ void blincomb_kernel(long long nf, int nr, const c64* __restrict__ coef, const c64* X, const c64* Y,
+                                const c64* Z, c64* out) {
+    const int j = blockIdx.y;
+    const c64 a = coef[3 * j], b = coef[3 * j + 1], c = coef[3 * j + 2];
+    const size_t o = (size_t)j * nf;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += stride) {
+        c64 r = a * X[o + e];
+        if (Y) r += b * Y[o + e];
+        if (Z) r += c * Z[o + e];
+        out[o + e] = r;
+    }
+}
+
+// CGLS scalars of nr systems on the device (one thread per system), so that an
+// iteration needs no host round trip; the coefficient triples feed
+// blincomb_kernel.
+struct CglsState {
+    double *bn, *gam, *qq, *rn, *gn, *relres;
+    int *active, *iters;
+    c64 *cz, *cr, *cp;   // Z += alpha p,  r -= alpha q,  p = s + beta p
+};
+// squared 2-norms of nr columns (column j at offset j nf) in two launches with
+// a fixed summation order: kDotBlocks partial sums per column, then one block
+// per column adds them in order
+__global__ __launch_bounds__(256) void colnorm2_partial_kernel(long long nf, const c64* __restrict__ X,
+                                                               double* __restrict__ part) {
+    __shared__ double lds[8];
+    const c64* x = X + (size_t)blockIdx.y * nf;
+    double re = 0.0, im = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += stride) {
+        const c64 a = x[e];
+        re += a.re * a.re + a.im * a.im;
+    }
+    block_sum2(re, im, lds);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = re;
+}
+__global__ __launch_bounds__(256) void colnorm2_final_kernel(int nb, const double* __restrict__ part,
+                                                             double* __restrict__ out) {
+    __shared__ double lds[8];
+    const double* pj = part + (size_t)blockIdx.x * nb;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) re += pj[i];
+    block_sum2(re, im, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = re;
+}
+// start: bn = |rhs_j| (from its squared norm), systems with a zero right-hand side inactive
+__global__ void cgls_init_kernel(int nr, CglsState d) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nr) return;
+    d.bn[j] = sqrt(d.bn[j]);
+    d.active[j] = d.bn[j] > 0 ? 1 : 0;
+    d.relres[j] = d.active[j] ? 1.0 : 0.0;
+    d.iters[j] = 0;
+}
+// alpha = gam / |q|^2 for the active systems (a system with |q| = 0 stops)
+__global__ void cgls_alpha_kernel(int nr, CglsState d) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nr) return;
+    const c64 one{1.0, 0.0}, zero{0.0, 0.0};
+    if (d.active[j] && !(d.qq[j] > 0)) d.active[j] = 0;
+    if (!d.active[j]) {
+        d.cz[3 * j] = one; d.cz[3 * j + 1] = zero; d.cz[3 * j + 2] = zero;
+        d.cr[3 * j] = one; d.cr[3 * j + 1] = zero; d.cr[3 * j + 2] = zero;
+        return;
+    }
+    const double alpha = d.gam[j] / d.qq[j];
+    d.cz[3 * j] = one; d.cz[3 * j + 1] = c64{alpha, 0.0}; d.cz[3 * j + 2] = zero;
+    d.cr[3 * j] = one; d.cr[3 * j + 1] = c64{-alpha, 0.0}; d.cr[3 * j + 2] = zero;
+    ++d.iters[j];
+}
+// relative residual of the active systems; a system at tolerance stops
+__global__ void cgls_conv_kernel(int nr, CglsState d, double tol) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nr || !d.active[j]) return;
+    d.relres[j] = sqrt(d.rn[j]) / d.bn[j];
+    if (d.relres[j] <= tol) d.active[j] = 0;
+}
+// beta = |s|^2 / gam for the active systems (p unchanged for the others)
+__global__ void cgls_beta_kernel(int nr, CglsState d) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nr) return;
+    const c64 zero{0.0, 0.0};
+    if (!d.active[j]) {
+        d.cp[3 * j] = zero; d.cp[3 * j + 1] = c64{1.0, 0.0}; d.cp[3 * j + 2] = zero;
+        return;
+    }
+    d.cp[3 * j] = c64{1.0, 0.0}; d.cp[3 * j + 1] = c64{d.gn[j] / d.gam[j], 0.0}; d.cp[3 * j + 2] = zero;
+    d.gam[j] = d.gn[j];
+}
+__global__ void cneg_kernel(int n, const c64* __restrict__ in, c64* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = -in[i];
+}
+
 namespace {
 
 // progress lines on stderr when OVDERIV_VERBOSE is set (long setup runs)
 bool verbose() {
     static const bool v = std::getenv("OVDERIV_VERBOSE") != nullptr;
     return v;
+}
+// seconds since the first call (time stamps of the verbose log)
+double vclock() {
+    static const auto t0 = std::chrono::steady_clock::now();
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ---------------------------------------------------------------------------
@@ -261,6 +365,25 @@ struct Ctx {
         C.resize((size_t)m * nr);
         if (!ok(hipMemcpyAsync(C.data(), small, sizeof(c64) * m * nr, hipMemcpyDeviceToHost, s), "copy")) return false;
         return ok(hipStreamSynchronize(s), "sync");
+    }
+    // Cd (device, m x nr) = A^dag B, no wait
+    // (reduction chunks of `chunk` elements, see launch_defl_proj)
+    bool proj_dev(const c64* A, int m, const c64* B, int nr, c64* Cd, long long chunk = 0) {
+        if (!ensure_scratch(m, nr)) return false;
+        launch_defl_proj(A, nf, m, B, nf, nr, nf, Cd, scr, s, chunk);
+        return ok(hipGetLastError(), "defl_proj");
+    }
+    // Y = Y0 + A Cd (Cd device, m x nr), no wait
+    bool comb_dev(const c64* A, int m, const c64* Cd, int nr, const c64* Y0, c64* Y) {
+        launch_defl_comb(A, nf, m, Cd, nr, Y, nf, nf, s, Y0, nf);
+        return ok(hipGetLastError(), "defl_comb");
+    }
+    // out_j = a_j X_j + b_j Y_j + c_j Z_j over nr columns, coefficients on the device
+    bool blincomb(int nr, const c64* coef, const c64* X, const c64* Y, const c64* Z, c64* out) {
+        long long nb = (nf + 255) / 256;
+        if (nb > 2048) nb = 2048;
+        blincomb_kernel<<<dim3((unsigned)nb, (unsigned)nr), 256, 0, s>>>(nf, nr, coef, X, Y, Z, out);
+        return ok(hipGetLastError(), "blincomb");
     }
     // Y += A C (C host, m x nr)
     bool comb(const c64* A, int m, const std::vector<cd>& C, int nr, c64* Y) {
@@ -473,14 +596,14 @@ bool arnoldi_side(Ctx& c, double mu, int m, int n, double tol, int max_cycles, u
             }
             sr.max_res = rmax;
             if (verbose()) {
-                std::fprintf(stderr, "eigs mu=%+.3f cycle %d: estimate %.2e, residual %.3e, |lambda_m| %.6f, %lld solves, %lld CG\n",
-                             mu, cyc, est, rmax, std::abs(sr.theta[m - 1]), sr.solves, sr.cg_iters);
+                std::fprintf(stderr, "[%.2f s] eigs mu=%+.3f cycle %d: estimate %.2e, residual %.3e, |lambda_m| %.6f, %lld solves, %lld CG\n",
+                             vclock(), mu, cyc, est, rmax, std::abs(sr.theta[m - 1]), sr.solves, sr.cg_iters);
                 std::fflush(stderr);
             }
             if (rmax <= tol || last) return true;
         } else if (verbose()) {
-            std::fprintf(stderr, "eigs mu=%+.3f cycle %d: estimate %.2e, |lambda_m| %.6f, %lld solves, %lld CG\n", mu,
-                         cyc, est, std::abs(1.0 / th[m - 1]), sr.solves, sr.cg_iters);
+            std::fprintf(stderr, "[%.2f s] eigs mu=%+.3f cycle %d: estimate %.2e, |lambda_m| %.6f, %lld solves, %lld CG\n",
+                         vclock(), mu, cyc, est, std::abs(1.0 / th[m - 1]), sr.solves, sr.cg_iters);
             std::fflush(stderr);
         }
         // thick restart: keep kk >= kkeep Ritz vectors, kk at the largest
@@ -553,7 +676,10 @@ bool arnoldi_side(Ctx& c, double mu, int m, int n, double tol, int max_cycles, u
 // converges monotonically there, where restarted GMRES stalls.  The nr systems
 // run side by side, each with its own CGLS scalars, so that one pass over the m
 // projector vectors serves all of them; a converged system is left as it is.
-// rhs, Z: nr fields; iters, relres: per system.
+// The scalars, the projection coefficients and the per-system combinations stay
+// on the device; the host reads which systems are still running every
+// kCgCheck iterations (the iterations past the last system's convergence
+// change nothing).  rhs, Z: nr fields; iters, relres: per system.
 bool cgls_shifted(Ctx& c, double mu, bool adjoint, const std::vector<cd>& shift, const c64* Rv, const c64* Lv, int m,
                   const c64* rhs, c64* Z, double tol, int max_it, std::vector<int>& iters,
                   std::vector<double>& relres) {
@@ -565,85 +691,108 @@ bool cgls_shifted(Ctx& c, double mu, bool adjoint, const std::vector<cd>& shift,
     if (!W) return false;
     const long long blk = (long long)nr * c.nf;
     c64 *r = W, *s = W + blk, *p = W + 2 * blk, *q = W + 3 * blk, *u = W + 4 * blk, *t = W + 5 * blk;
-    auto col = [&](c64* x, int j) { return x + (size_t)j * c.nf; };
-    auto ccol = [&](const c64* x, int j) { return x + (size_t)j * c.nf; };
-    // squared 2-norms of the nr columns of x
-    auto norms2 = [&](const c64* x, std::vector<double>& n2) -> bool {
-        std::vector<cd> G;
-        if (!c.proj(x, nr, x, nr, G)) return false;
-        n2.resize(nr);
-        for (int j = 0; j < nr; ++j) n2[j] = std::max(0.0, G[(size_t)j * nr + j].real());
-        return true;
+    // device state: 5 coefficient triples per system, two m x nr coefficient
+    // blocks, 6 nr doubles, the partial sums of the column norms and 2 nr ints
+    const size_t nsc = ((size_t)6 * nr + (size_t)kDotBlocks * nr) * sizeof(double) + (size_t)2 * nr * sizeof(int);
+    const size_t ncoef = (size_t)5 * 3 * nr, nmat = (size_t)2 * m * nr;
+    void* mem = nullptr;
+    if (!c.ok(hipMalloc(&mem, nsc + sizeof(c64) * (ncoef + nmat)), "hipMalloc")) return false;
+    c.owned.push_back(mem);
+    c64* cbase = (c64*)mem;
+    c64 *cop = cbase, *copd = cbase + 3 * nr;
+    CglsState d;
+    d.cz = cbase + 6 * nr;
+    d.cr = cbase + 9 * nr;
+    d.cp = cbase + 12 * nr;
+    c64* Cd = cbase + ncoef;                  // m x nr projection coefficients
+    c64* Cn = Cd + (size_t)m * nr;            // their negation
+    double* dd = (double*)(cbase + ncoef + nmat);
+    double* npart = dd + 6 * nr;              // [nr][kDotBlocks] partial norms
+    d.bn = dd;
+    d.gam = dd + nr;
+    d.qq = dd + 2 * nr;
+    d.rn = dd + 3 * nr;
+    d.gn = dd + 4 * nr;
+    d.relres = dd + 5 * nr;
+    d.active = (int*)(npart + (size_t)kDotBlocks * nr);
+    d.iters = d.active + nr;
+    const unsigned g1 = (unsigned)((nr + 63) / 64);
+    // the per-system coefficients of op and op^dag, fixed for the whole solve
+    {
+        std::vector<c64> h((size_t)6 * nr);
+        for (int j = 0; j < nr; ++j) {
+            const cd a = shift[j] - 1.0, ac = std::conj(shift[j]);
+            h[3 * j] = c64{a.real(), a.imag()};
+            h[3 * j + 1] = c64{-1.0, 0.0};
+            h[3 * j + 2] = c64{1.0, 0.0};
+            h[3 * nr + 3 * j] = c64{ac.real(), ac.imag()};
+            h[3 * nr + 3 * j + 1] = c64{-1.0, 0.0};
+            h[3 * nr + 3 * j + 2] = c64{0.0, 0.0};
+        }
+        if (!c.ok(hipMemcpyAsync(cop, h.data(), sizeof(c64) * h.size(), hipMemcpyHostToDevice, c.s), "copy") ||
+            !c.ok(hipStreamSynchronize(c.s), "sync"))   // h is released on return
+            return false;
+    }
+    if (!c.ensure_scratch(m, nr)) return false;
+    // squared 2-norms of the nr columns of x into n2 (device)
+    auto norms2 = [&](const c64* x, double* n2) -> bool {
+        colnorm2_partial_kernel<<<dim3(kDotBlocks, (unsigned)nr), 256, 0, c.s>>>(c.nf, x, npart);
+        colnorm2_final_kernel<<<(unsigned)nr, 256, 0, c.s>>>(kDotBlocks, npart, n2);
+        return c.ok(hipGetLastError(), "colnorm2");
     };
+    // the m-vector projections reduce over chunks of kCglsChunk elements
+    // (fewer partial sums than the default, which suits one-vector products)
+    constexpr long long kCglsChunk = 512;
     // out = op(zin): u = (1 - P) zin, out_j = shift_j u_j - A u_j + (zin_j - u_j)
     auto op = [&](const c64* zin, c64* out) -> bool {
-        std::vector<cd> pc;
-        if (!c.proj(Pa, m, zin, nr, pc)) return false;
-        if (!c.copy(u, zin, nr)) return false;
-        for (auto& v : pc) v = -v;
-        if (!c.comb(Pb, m, pc, nr, u)) return false;
+        if (!c.proj_dev(Pa, m, zin, nr, Cd, kCglsChunk)) return false;
+        cneg_kernel<<<(unsigned)((m * nr + 255) / 256), 256, 0, c.s>>>(m * nr, Cd, Cn);
+        if (!c.comb_dev(Pb, m, Cn, nr, zin, u)) return false;
         if (!c.apply(0, amu, u, out, nr)) return false;
-        for (int j = 0; j < nr; ++j)
-            if (!c.lincomb(c.nf, shift[j] - 1.0, ccol(u, j), -1.0, ccol(out, j), 1.0, ccol(zin, j), col(out, j)))
-                return false;
-        return true;
+        return c.blincomb(nr, cop, u, out, zin, out);
     };
     // out = op_j^dag(y) = (1 - P^dag)(conj(shift_j) y - A^dag y) + P^dag y = t + Pa (Pb^dag (y - t))
     auto opd = [&](const c64* y, c64* out) -> bool {
         if (!c.apply(0, -amu, y, t, nr)) return false;
-        for (int j = 0; j < nr; ++j)
-            if (!c.lincomb(c.nf, std::conj(shift[j]), ccol(y, j), -1.0, ccol(t, j), 0.0, nullptr, col(t, j)))
-                return false;
+        if (!c.blincomb(nr, copd, y, t, nullptr, t)) return false;
         if (!c.lincomb(blk, 1.0, y, -1.0, t, 0.0, nullptr, u)) return false;
-        std::vector<cd> pc;
-        if (!c.proj(Pb, m, u, nr, pc)) return false;
-        if (!c.copy(out, t, nr)) return false;
-        return c.comb(Pa, m, pc, nr, out);
+        if (!c.proj_dev(Pb, m, u, nr, Cd, kCglsChunk)) return false;
+        return c.comb_dev(Pa, m, Cd, nr, t, out);
     };
     iters.assign(nr, 0);
     relres.assign(nr, 0.0);
     if (!c.ok(hipMemsetAsync(Z, 0, sizeof(c64) * blk, c.s), "memset")) return false;
-    std::vector<double> bn, gam, qq, rn, gn;
-    if (!norms2(rhs, bn)) return false;
-    std::vector<char> active(nr, 0);
-    for (int j = 0; j < nr; ++j) {
-        bn[j] = std::sqrt(bn[j]);
-        active[j] = bn[j] > 0;
-        relres[j] = active[j] ? 1.0 : 0.0;
-    }
-    if (!c.copy(r, rhs, nr) || !opd(r, s) || !c.copy(p, s, nr) || !norms2(s, gam)) return false;
+    if (!norms2(rhs, d.bn)) return false;
+    cgls_init_kernel<<<g1, 64, 0, c.s>>>(nr, d);
+    if (!c.copy(r, rhs, nr) || !opd(r, s) || !c.copy(p, s, nr) || !norms2(s, d.gam)) return false;
+    std::vector<int> act(nr);
     for (int it = 0; it < max_it; ++it) {
-        if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
-        if (!op(p, q) || !norms2(q, qq)) return false;
-        for (int j = 0; j < nr; ++j) {
-            if (!active[j]) continue;
-            if (!(qq[j] > 0)) {
-                active[j] = 0;
-                continue;
-            }
-            const double alpha = gam[j] / qq[j];
-            if (!c.lincomb(c.nf, 1.0, col(Z, j), alpha, col(p, j), 0.0, nullptr, col(Z, j))) return false;
-            if (!c.lincomb(c.nf, 1.0, col(r, j), -alpha, col(q, j), 0.0, nullptr, col(r, j))) return false;
-            ++iters[j];
+        if (it % kCgCheck == 0) {
+            if (!c.ok(hipMemcpyAsync(act.data(), d.active, sizeof(int) * nr, hipMemcpyDeviceToHost, c.s), "copy") ||
+                !c.ok(hipStreamSynchronize(c.s), "sync"))
+                return false;
+            if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) break;
         }
-        if (!norms2(r, rn)) return false;
-        for (int j = 0; j < nr; ++j) {
-            if (!active[j]) continue;
-            relres[j] = std::sqrt(rn[j]) / bn[j];
-            if (relres[j] <= tol) active[j] = 0;
-        }
-        if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
-        if (!opd(r, s) || !norms2(s, gn)) return false;
-        for (int j = 0; j < nr; ++j) {
-            if (!active[j]) continue;
-            if (!c.lincomb(c.nf, 1.0, col(s, j), gn[j] / gam[j], col(p, j), 0.0, nullptr, col(p, j))) return false;
-            gam[j] = gn[j];
-        }
+        if (!op(p, q) || !norms2(q, d.qq)) return false;
+        cgls_alpha_kernel<<<g1, 64, 0, c.s>>>(nr, d);
+        if (!c.blincomb(nr, d.cz, Z, p, nullptr, Z) || !c.blincomb(nr, d.cr, r, q, nullptr, r)) return false;
+        if (!norms2(r, d.rn)) return false;
+        cgls_conv_kernel<<<g1, 64, 0, c.s>>>(nr, d, tol);
+        if (!opd(r, s) || !norms2(s, d.gn)) return false;
+        cgls_beta_kernel<<<g1, 64, 0, c.s>>>(nr, d);
+        if (!c.blincomb(nr, d.cp, s, p, nullptr, p)) return false;
+        if (!c.ok(hipGetLastError(), "cgls")) return false;
     }
+    if (!c.ok(hipMemcpyAsync(iters.data(), d.iters, sizeof(int) * nr, hipMemcpyDeviceToHost, c.s), "copy")) return false;
     // true residuals of the final iterates
+    std::vector<double> bn(nr), rn(nr);
     if (!op(Z, q)) return false;
     if (!c.lincomb(blk, 1.0, rhs, -1.0, q, 0.0, nullptr, r)) return false;
-    if (!norms2(r, rn)) return false;
+    if (!norms2(r, d.rn)) return false;
+    if (!c.ok(hipMemcpyAsync(bn.data(), d.bn, sizeof(double) * nr, hipMemcpyDeviceToHost, c.s), "copy") ||
+        !c.ok(hipMemcpyAsync(rn.data(), d.rn, sizeof(double) * nr, hipMemcpyDeviceToHost, c.s), "copy") ||
+        !c.ok(hipStreamSynchronize(c.s), "sync"))
+        return false;
     for (int j = 0; j < nr; ++j) relres[j] = bn[j] > 0 ? std::sqrt(rn[j]) / bn[j] : 0.0;
     return true;
 }
@@ -652,6 +801,7 @@ bool cgls_shifted(Ctx& c, double mu, bool adjoint, const std::vector<cd>& shift,
 
 int eigs_compute(const EigParams& P, EigResult& out) {
     const auto t0 = std::chrono::steady_clock::now();
+    if (verbose()) (void)vclock();
     Ctx c;
     c.g = P.g;
     c.U = P.U;
@@ -790,7 +940,8 @@ int eigs_compute(const EigParams& P, EigResult& out) {
         auto record = [&](const char* side, const std::vector<int>& its, const std::vector<double>& res) {
             for (int j = 0; j < l; ++j) {
                 if (verbose()) {
-                    std::fprintf(stderr, "eigs %s_%d: %d CGLS iterations, residual %.2e\n", side, j, its[j], res[j]);
+                    std::fprintf(stderr, "[%.2f s] eigs %s_%d: %d CGLS iterations, residual %.2e\n", vclock(), side, j, its[j],
+                                 res[j]);
                     std::fflush(stderr);
                 }
                 out.shift_iters += its[j];

@@ -93,15 +93,16 @@ __global__ __launch_bounds__(256) void defl_proj_reduce(int m, int nr, int nspli
 // still runs many independent waves
 constexpr long long kProjChunk = 256;
 
-size_t defl_proj_scratch(int m, int nr, long long nf) {
-    const long long nsplit = (nf + kProjChunk - 1) / kProjChunk;
+size_t defl_proj_scratch(int m, int nr, long long nf, long long chunk) {
+    if (chunk <= 0) chunk = kProjChunk;
+    const long long nsplit = (nf + chunk - 1) / chunk;
     return (size_t)nsplit * m * nr;
 }
 
 void launch_defl_proj(const c64* A, long long sA, int m, const c64* B, long long sB, int nr, long long nf,
-                      c64* C, c64* scratch, hipStream_t s) {
+                      c64* C, c64* scratch, hipStream_t s, long long chunk) {
     if (m <= 0 || nr <= 0) return;
-    const long long chunk = kProjChunk;
+    if (chunk <= 0) chunk = kProjChunk;
     const int nsplit = (int)((nf + chunk - 1) / chunk);
     dim3 grid((m + 15) / 16, (nr + 15) / 16, nsplit);
     defl_proj_kernel<<<grid, 64, 0, s>>>(A, sA, m, B, sB, nr, nf, chunk, scratch);
@@ -115,7 +116,8 @@ void launch_defl_proj(const c64* A, long long sA, int m, const c64* B, long long
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void defl_comb_kernel(const c64* __restrict__ A, long long sA, int m,
                                                        const c64* __restrict__ C, int nr,
-                                                       c64* __restrict__ Y, long long sY, long long nf) {
+                                                       c64* __restrict__ Y, long long sY, long long nf,
+                                                       const c64* __restrict__ Y0, long long sY0) {
     const int l = threadIdx.x;
     const long long n0 = (long long)blockIdx.x * 16;
     const int r0 = blockIdx.y * 16;
@@ -139,15 +141,16 @@ __global__ __launch_bounds__(64) void defl_comb_kernel(const c64* __restrict__ A
         const long long nn = n0 + 4 * v + (l >> 4);
         if (nn < nf) {
             c64* y = Y + (size_t)rr * sY + nn;
-            *y = *y + c64{yre[v], yim[v]};
+            const c64 y0 = Y0 ? Y0[(size_t)rr * sY0 + nn] : *y;
+            *y = y0 + c64{yre[v], yim[v]};
         }
     }
 }
 
 void launch_defl_comb(const c64* A, long long sA, int m, const c64* C, int nr, c64* Y, long long sY, long long nf,
-                      hipStream_t s) {
+                      hipStream_t s, const c64* Y0, long long sY0) {
     dim3 grid((unsigned)((nf + 15) / 16), (nr + 15) / 16);
-    defl_comb_kernel<<<grid, 64, 0, s>>>(A, sA, m, C, nr, Y, sY, nf);
+    defl_comb_kernel<<<grid, 64, 0, s>>>(A, sA, m, C, nr, Y, sY, nf, Y0, sY0);
 }
 
 // out[i][r] = sign * f[i] * in[i][r]

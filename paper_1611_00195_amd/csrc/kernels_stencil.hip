@@ -1392,30 +1392,16 @@ OVD_INST(float)
 // `first` starts from zero instead of Kacc, `last` turns K into the outputs
 // (else K is stored to Kacc).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64* __restrict__ Vb, long long sV,
-                                                        const c64* __restrict__ Zb, long long sZ,
-                                                        const c64* __restrict__ U, double emu,
-                                                        c64* __restrict__ F, c64* __restrict__ dU,
-                                                        c64* __restrict__ dUc, c64* __restrict__ trF,
-                                                        c64* __restrict__ dth, c64* __restrict__ Kacc, int first,
-                                                        int last) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 4 * g.V) return;
-    const size_t n4 = (size_t)4 * g.V;
+// Kf, Kb += the terms of basis pairs p0 <= p < p1 for thread t = 4 y + nu
+__device__ __forceinline__ void force_acc(const Geom& g, int t, int p0, int p1, const c64* __restrict__ Vb,
+                                          long long sV, const c64* __restrict__ Zb, long long sZ, c64 (&Kf)[9],
+                                          c64 (&Kb)[9]) {
     const int y = t >> 2, nu = t & 3;
     const int Vp = g.Vp;
     const Nbr N = neighbours(g, y);
     const int yp = nu == 0 ? N.f[0] : nu == 1 ? N.f[1] : nu == 2 ? N.f[2] : N.f[3];
-    const double sg = (nu == 3 && N.wf) ? double(g.bc_t) : 1.0;
-    const double cf = nu == 3 ? emu : 1.0, cb = nu == 3 ? 1.0 / emu : 1.0;
-    c64 Kf[9], Kb[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        Kf[i] = first ? c64{0.0, 0.0} : Kacc[(size_t)i * n4 + t];
-        Kb[i] = first ? c64{0.0, 0.0} : Kacc[(size_t)(9 + i) * n4 + t];
-    }
     const int cfw = kHop[2 * nu], cbw = kHop[2 * nu + 1];
-    for (int p = 0; p < k; ++p) {
+    for (int p = p0; p < p1; ++p) {
         const c64* Vp_ = Vb + (size_t)p * sV;
         const c64* Zp_ = Zb + (size_t)p * sZ;
 #pragma unroll
@@ -1442,17 +1428,20 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
             }
         }
     }
-    if (!last) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            Kacc[(size_t)i * n4 + t] = Kf[i];
-            Kacc[(size_t)(9 + i) * n4 + t] = Kb[i];
-        }
-        return;
-    }
+}
+
+// the outputs of link U_nu(y), t = 4 y + nu, from its finished Kf, Kb
+__device__ __forceinline__ void force_out(const Geom& g, int t, const c64 (&Kf)[9], const c64 (&Kb)[9],
+                                          const c64* __restrict__ U, double emu, c64* __restrict__ F,
+                                          c64* __restrict__ dU, c64* __restrict__ dUc, c64* __restrict__ trF,
+                                          c64* __restrict__ dth) {
+    const int y = t >> 2, nu = t & 3;
+    const Nbr N = neighbours(g, y);
+    const double sg = (nu == 3 && N.wf) ? double(g.bc_t) : 1.0;
+    const double cf = nu == 3 ? emu : 1.0, cb = nu == 3 ? 1.0 / emu : 1.0;
     // link U_nu(y) from the FP64 internal link field
     c64 u[9];
-    load_link(U, nu, y, Vp, u);
+    load_link(U, nu, y, g.Vp, u);
     const double af = -0.5 * cf * sg, ab = 0.5 * cb * sg;
     const size_t o = ((size_t)nu * g.V + y) * 9;
     c64 tr{0.0, 0.0};
@@ -1475,11 +1464,111 @@ __global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64
     if (dth) dth[(size_t)nu * g.V + y] = c64{-tr.im, tr.re};   // i tr F: the U(1) phase of this link
 }
 
+__global__ __launch_bounds__(256) void vjp_force_kernel(Geom g, int k, const c64* __restrict__ Vb, long long sV,
+                                                        const c64* __restrict__ Zb, long long sZ,
+                                                        const c64* __restrict__ U, double emu,
+                                                        c64* __restrict__ F, c64* __restrict__ dU,
+                                                        c64* __restrict__ dUc, c64* __restrict__ trF,
+                                                        c64* __restrict__ dth, c64* __restrict__ Kacc, int first,
+                                                        int last) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    const size_t n4 = (size_t)4 * g.V;
+    c64 Kf[9], Kb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        Kf[i] = first ? c64{0.0, 0.0} : Kacc[(size_t)i * n4 + t];
+        Kb[i] = first ? c64{0.0, 0.0} : Kacc[(size_t)(9 + i) * n4 + t];
+    }
+    force_acc(g, t, 0, k, Vb, sV, Zb, sZ, Kf, Kb);
+    if (!last) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            Kacc[(size_t)i * n4 + t] = Kf[i];
+            Kacc[(size_t)(9 + i) * n4 + t] = Kb[i];
+        }
+        return;
+    }
+    force_out(g, t, Kf, Kb, U, emu, F, dU, dUc, trF, dth);
+}
+
+// The sum over p split into nchunk consecutive ranges that run side by side
+// (blockIdx.y = range): each range's Kf, Kb go to Kpart [nchunk][18][4V];
+// vjp_force_fin_kernel then sums the ranges in order and writes the outputs.
+__global__ __launch_bounds__(256) void vjp_force_part_kernel(Geom g, int k, int nchunk, const c64* __restrict__ Vb,
+                                                             long long sV, const c64* __restrict__ Zb, long long sZ,
+                                                             c64* __restrict__ Kpart) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    const size_t n4 = (size_t)4 * g.V;
+    const int c = blockIdx.y;
+    const int p0 = (int)((long long)k * c / nchunk), p1 = (int)((long long)k * (c + 1) / nchunk);
+    c64 Kf[9], Kb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Kf[i] = Kb[i] = c64{0.0, 0.0};
+    force_acc(g, t, p0, p1, Vb, sV, Zb, sZ, Kf, Kb);
+    c64* Kc = Kpart + (size_t)c * 18 * n4;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        Kc[(size_t)i * n4 + t] = Kf[i];
+        Kc[(size_t)(9 + i) * n4 + t] = Kb[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void vjp_force_fin_kernel(Geom g, int nchunk, const c64* __restrict__ Kpart,
+                                                            const c64* __restrict__ U, double emu,
+                                                            c64* __restrict__ F, c64* __restrict__ dU,
+                                                            c64* __restrict__ dUc, c64* __restrict__ trF,
+                                                            c64* __restrict__ dth, c64* __restrict__ Kacc, int last) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    const size_t n4 = (size_t)4 * g.V;
+    c64 Kf[9], Kb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Kf[i] = Kb[i] = c64{0.0, 0.0};
+    for (int c = 0; c < nchunk; ++c) {
+        const c64* Kc = Kpart + (size_t)c * 18 * n4;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            Kf[i] += Kc[(size_t)i * n4 + t];
+            Kb[i] += Kc[(size_t)(9 + i) * n4 + t];
+        }
+    }
+    if (!last) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            Kacc[(size_t)i * n4 + t] = Kf[i];
+            Kacc[(size_t)(9 + i) * n4 + t] = Kb[i];
+        }
+        return;
+    }
+    force_out(g, t, Kf, Kb, U, emu, F, dU, dUc, trF, dth);
+}
+
+int vjp_force_chunks(const Geom& g, int k) {
+    const int nblk = (4 * g.V + 255) / 256;
+    int nc = (2048 + nblk - 1) / nblk;   // about 2048 blocks in all
+    nc = std::min(nc, 8);
+    nc = std::min(nc, k / 16);           // at least 16 basis pairs per range
+    return std::max(nc, 1);
+}
+
+size_t vjp_force_scratch_elems(const Geom& g, int nchunk) {
+    return nchunk > 1 ? (size_t)nchunk * 18 * 4 * g.V : 0;
+}
+
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
                       double emu, c64* F, c64* dU, c64* dUc, c64* trF, c64* dth, hipStream_t s, c64* Kacc, bool first,
-                      bool last) {
-    vjp_force_kernel<<<(4 * g.V + 255) / 256, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF, dth,
-                                                           Kacc, first ? 1 : 0, last ? 1 : 0);
+                      bool last, c64* Kpart, int nchunk) {
+    const unsigned nblk = (unsigned)((4 * g.V + 255) / 256);
+    if (nchunk > 1 && Kpart && first) {
+        vjp_force_part_kernel<<<dim3(nblk, (unsigned)nchunk), 256, 0, s>>>(g, k, nchunk, Vb, sV, Zb, sZ, Kpart);
+        vjp_force_fin_kernel<<<nblk, 256, 0, s>>>(g, nchunk, Kpart, U64, emu, F, dU, dUc, trF, dth, Kacc,
+                                                  last ? 1 : 0);
+        return;
+    }
+    vjp_force_kernel<<<nblk, 256, 0, s>>>(g, k, Vb, sV, Zb, sZ, U64, emu, F, dU, dUc, trF, dth, Kacc, first ? 1 : 0,
+                                          last ? 1 : 0);
 }
 
 // out = sum_y trF[y] (one block, fixed order)

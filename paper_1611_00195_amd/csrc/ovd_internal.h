@@ -249,11 +249,15 @@ void launch_scalar_dot(int nrhs, int k, const c64* c, const c64* proj, int ld,
 
 // deflation products (kernels_defl.hip), FP64 fields flattened to nf = 12 Vp
 // complex: C (m x nr, row-major) = A^dag B;  Y += A C
-size_t defl_proj_scratch(int m, int nr, long long nf);
+// The projection's reduction is split into chunks of `chunk` elements (a
+// multiple of 4; 0 = the default, short enough that a one-vector projection
+// runs many waves); its scratch depends on the chunk.
+size_t defl_proj_scratch(int m, int nr, long long nf, long long chunk = 0);
 void launch_defl_proj(const c64* A, long long sA, int m, const c64* B, long long sB, int nr, long long nf,
-                      c64* C, c64* scratch, hipStream_t s);
+                      c64* C, c64* scratch, hipStream_t s, long long chunk = 0);
+// Y += A C, or with Y0: Y = Y0 + A C (Y0 columns at stride sY0)
 void launch_defl_comb(const c64* A, long long sA, int m, const c64* C, int nr, c64* Y, long long sY, long long nf,
-                      hipStream_t s);
+                      hipStream_t s, const c64* Y0 = nullptr, long long sY0 = 0);
 // out[i][r] = sign * f[i] * in[i][r]
 void launch_defl_scale(int m, int nr, const double* f, const c64* in, c64* out, double sign, hipStream_t s);
 // out[r] += sum_i conj(P1[i][r]) sD[i][r] + conj(P2[i][r]) sC[i][r]
@@ -284,10 +288,15 @@ void launch_conj_c64(long long n, const c64* in, c64* out, hipStream_t s);
 void launch_vjp_scale_m(int k, TslCoeffs co, const c64* M, c64* Mp, hipStream_t s);
 // force of the gradient from the basis pairs p < k; the sum over p may be
 // split over launches that carry Kf, Kb in Kacc ([18][4V], needed unless
-// first && last): first starts from zero, last writes F, dU, dUc, trF
+// first && last): first starts from zero, last writes F, dU, dUc, trF.
+// With Kpart (vjp_force_scratch_elems(g, nchunk) elements) and nchunk > 1, a
+// first launch splits its sum over p into nchunk ranges run side by side and
+// summed in order (vjp_force_chunks: the number that fills the GPU).
 void launch_vjp_force(const Geom& g, int k, const c64* Vb, long long sV, const c64* Zb, long long sZ, const c64* U64,
                       double emu, c64* F, c64* dU, c64* dUc, c64* trF, c64* dth, hipStream_t s, c64* Kacc = nullptr,
-                      bool first = true, bool last = true);
+                      bool first = true, bool last = true, c64* Kpart = nullptr, int nchunk = 1);
+int vjp_force_chunks(const Geom& g, int k);
+size_t vjp_force_scratch_elems(const Geom& g, int nchunk);
 void launch_sum_c64(int n, const c64* v, c64* out, hipStream_t s);
 
 // eigenpairs of smallest |lambda| and eigenvector derivatives for deflation (eigs.hip)
