@@ -236,6 +236,12 @@ def run_gpu(args):
         },
         "update_kernel": {"bytes_per_launch": up_bytes, "us_per_launch": round(up_ms * 1e3, 2),
                           "gbs": round(up_bytes / (up_ms * 1e-3) / 1e9, 1)},
+        # the whole Lanczos path: the algorithmic bytes of k stencils and k - 1
+        # updates per call, over the call's wall time (deflation and sgn(T_k) included)
+        "path": {"bytes_per_eval": (args.k * bytes_launch + (args.k - 1) * up_bytes) / n,
+                 "gbs": round((args.k * bytes_launch + (args.k - 1) * up_bytes) / n * main["evals_per_s"] / 1e9, 1),
+                 "frac": round((args.k * bytes_launch + (args.k - 1) * up_bytes) / n * main["evals_per_s"] / 1e9
+                               / HBM_PEAK_GBS, 4)},
         "xdy0": [main["vals"][0].real, main["vals"][0].imag],
         "deflation": defl,
         "deflated": lat_d is not None or (defl is not None and "error" not in defl),
@@ -556,12 +562,12 @@ def _cpu_source_worker(job):
 
 def run_cpu_baseline(args, nsteps):
     """The oracle, as it stands, on a bounded sample of the benchmark's
-    workload on the host cores: the batch's sources run side by side, one
-    process per source (at most the machine's CPU share), each with BLAS held to
-    one thread; each does the deflation projections of its source and
-    `nsteps` of the k block Lanczos steps at the full lattice size.  One
-    k x k Schur sign is timed once.  Scaled to evaluations per second of the
-    whole batch."""
+    workload on all the host cores: one process per core (at most the box's
+    CPU share of 16), each with BLAS held to one thread and its own source
+    (the batch's sources first); each does the deflation projections of its
+    source and `nsteps` of the k block Lanczos steps at the full lattice
+    size.  One k x k Schur sign is timed once.  Scaled to evaluations per
+    second of all the processes together."""
     import multiprocessing as mp
 
     import numpy as np
@@ -571,7 +577,7 @@ def run_cpu_baseline(args, nsteps):
 
     dims = tuple(args.dims)
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    procs = max(1, min(args.nrhs, ncpu, 16))
+    procs = max(1, min(ncpu, 16))
     l = args.defl_l if args.deflation > 0 else 0
     jobs = [(dims, args.eps, args.mu, args.m0, nsteps, r, l) for r in range(procs)]
     t0 = time.perf_counter()
@@ -603,8 +609,8 @@ def run_cpu_baseline(args, nsteps):
         "cores": procs,
         "kind": "oracle",
         "cpu": model,
-        "sample": f"{procs} sources of the {args.nrhs}-source batch side by side, one process and one BLAS thread "
-                  f"each, on {model} ({ncpu} cores available): per source the projections of the {l}-pair "
+        "sample": f"{procs} sources side by side (the {args.nrhs} of the batch first), one process and one BLAS "
+                  f"thread each, on {model} ({ncpu} cores available): per source the projections of the {l}-pair "
                   f"generalised deflation ({t_defl:.2f} s) and {nsteps} of {args.k} block Lanczos steps at "
                   f"{'x'.join(map(str, dims))} ({t_step:.2f} s/step, slowest process), plus one {args.k}x{args.k} "
                   f"Schur sign ({t_sign:.2f} s); scaled to one evaluation per process ({wall:.0f} s wall)",
@@ -699,6 +705,7 @@ def main():
             "ms_lanczos_per_step": round(g["ms_lanczos_per_step"], 3),
             "ms_small_sign_per_step": round(g["ms_small_sign_per_step"], 3),
             "update_kernel": g["update_kernel"],
+            "path": g["path"],
             "copy_1gib_gbs": g.get("copy_gbs"),
             "forms": g["forms"],
             "mixed_vs_fp64": g.get("mixed_accuracy"),

@@ -52,22 +52,45 @@ __device__ __forceinline__ c64 tdiag(const TslCoeffs& co, int r, int i) { return
 __device__ __forceinline__ c64 tsup(const TslCoeffs& co, int r, int i) { return co.beta[(size_t)r * co.kmax + i + 1]; }
 __device__ __forceinline__ c64 tsub(const TslCoeffs& co, int r, int i) { return co.delta[(size_t)r * co.kmax + i + 1]; }
 
-// smin[r] = log(Gershgorin bound of T_r) - kLowSpan, one thread per rhs
-__global__ void small_sign_setup_kernel(int nrhs, int k, TslCoeffs co, double* __restrict__ smin) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// smin[r] = log(Gershgorin bound of T_r) - kLowSpan, one block of 256 per rhs
+// (the rows spread over the block, then a max over its threads)
+__global__ __launch_bounds__(256) void small_sign_setup_kernel(int nrhs, int k, TslCoeffs co,
+                                                               double* __restrict__ smin) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
     if (r >= nrhs) return;
     double m = 0.0;
-    for (int i = 0; i < k; ++i) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
         double a = sqrt(norm2(tdiag(co, r, i)));
         if (i + 1 < k) a += sqrt(norm2(tsup(co, r, i)));
         if (i > 0) a += sqrt(norm2(tsub(co, r, i - 1)));
         m = a > m ? a : m;
     }
-    smin[r] = log(m > 0.0 ? m : 1.0) - kLowSpan;
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) smin[r] = log(red[0] > 0.0 ? red[0] : 1.0) - kLowSpan;
+}
+
+// 1 / z, scaled against overflow as in Smith's division; written with selects
+// so that the lanes of a wave (different shifts) do not diverge
+__device__ __forceinline__ c64 crecip(c64 z) {
+    const bool big = fabs(z.re) >= fabs(z.im);
+    const double p = big ? z.re : z.im, q = big ? z.im : z.re;
+    const double r = q / p, d = 1.0 / (p + q * r);
+    return big ? c64{d, -r * d} : c64{r * d, -d};
 }
 
 // Solves for nodes s = smin[r] + (off + q) h, q in [q0, q0 + nq), both signs of
 // the shift; thread = (rhs, q, sign).  Writes e^s x into the B slot.
+// Each row is a short dependent chain, so the loads that feed it (the entries
+// of T in the elimination, the stored factor rows in the back substitution)
+// are issued a group of kPf rows ahead; the elimination stores the reciprocal
+// of each pivot, so the back substitution has no division on its chain.
+constexpr int kPf = 4;
 __global__ __launch_bounds__(64) void small_sign_solve_kernel(int nrhs, int k, TslCoeffs co,
                                                               const double* __restrict__ smin, double h,
                                                               double off, int q0, int nq,
@@ -80,46 +103,102 @@ __global__ __launch_bounds__(64) void small_sign_solve_kernel(int nrhs, int k, T
     const double sgn = (sol & 1) ? -1.0 : 1.0;
     const double y = exp(smin[r] + (off + q) * h);
     const c64 sigma{0.0, sgn * y};
-    c64* D = scr;                              // pivot row diagonal
+    const c64 zero{0.0, 0.0};
+    c64* IP = scr;                             // reciprocal of the pivot row's diagonal
     c64* DU = scr + (size_t)k * nsol;          // first superdiagonal
     c64* DU2 = scr + (size_t)2 * k * nsol;     // second superdiagonal (fill from pivoting)
     c64* B = scr + (size_t)3 * k * nsol;       // right-hand side, then solution
 #define AT(P, i) P[(size_t)(i) * nsol + sol]
+    // entries of row i + 1 of T + sigma (dl: its subdiagonal entry, dn: its
+    // diagonal, un: its superdiagonal), in the orientation of the solve
+    auto row = [&](int i, c64& dl, c64& dn, c64& un) {
+        dl = transpose ? tsup(co, r, i) : tsub(co, r, i);
+        dn = tdiag(co, r, i + 1) + sigma;
+        un = (i + 2 < k) ? (transpose ? tsub(co, r, i + 1) : tsup(co, r, i + 1)) : zero;
+    };
     // forward elimination with partial pivoting
     c64 cd = tdiag(co, r, 0) + sigma;
-    c64 cu = (k > 1) ? (transpose ? tsub(co, r, 0) : tsup(co, r, 0)) : c64{0.0, 0.0};
+    c64 cu = (k > 1) ? (transpose ? tsub(co, r, 0) : tsup(co, r, 0)) : zero;
     c64 cb{1.0, 0.0};
-    for (int i = 0; i + 1 < k; ++i) {
-        const c64 dl = transpose ? tsup(co, r, i) : tsub(co, r, i);
-        const c64 dn = tdiag(co, r, i + 1) + sigma;
-        const c64 un = (i + 2 < k) ? (transpose ? tsub(co, r, i + 1) : tsup(co, r, i + 1)) : c64{0.0, 0.0};
-        if (cabs1(cd) >= cabs1(dl)) {
-            const c64 f = cdiv(dl, cd);
-            AT(D, i) = cd; AT(DU, i) = cu; AT(DU2, i) = c64{0.0, 0.0}; AT(B, i) = cb;
-            cd = dn - f * cu;
-            cu = un;
-            cb = -(f * cb);
-        } else {
-            // swap rows i and i+1; the new row i+1 is the old row i minus f
-            // times the swapped-in row, whose right-hand side is zero
-            const c64 f = cdiv(cd, dl);
-            AT(D, i) = dl; AT(DU, i) = dn; AT(DU2, i) = un; AT(B, i) = c64{0.0, 0.0};
-            const c64 nd = cu - f * dn;
-            cu = -(f * un);
-            cd = nd;
+    c64 gl[kPf], gn[kPf], gu[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        gl[u] = gn[u] = gu[u] = zero;
+        if (u + 1 < k) row(u, gl[u], gn[u], gu[u]);
+    }
+    for (int i0 = 0; i0 + 1 < k; i0 += kPf) {
+        c64 nl[kPf], nn[kPf], nu[kPf];
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+            nl[u] = nn[u] = nu[u] = zero;
+            if (i0 + kPf + u + 1 < k) row(i0 + kPf + u, nl[u], nn[u], nu[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+            const int i = i0 + u;
+            if (i + 1 >= k) break;
+            const c64 dl = gl[u], dn = gn[u], un = gu[u];
+            // sw: swap rows i and i+1 (the subdiagonal entry is the larger); the
+            // new row i+1 is then the old row i minus f times the swapped-in
+            // row, whose right-hand side is zero.  Selects, not branches: the
+            // lanes choose their pivots independently.
+            const bool sw = !(cabs1(cd) >= cabs1(dl));
+            const c64 ip = crecip(sw ? dl : cd);
+            const c64 f = (sw ? cd : dl) * ip;
+            AT(IP, i) = ip;
+            AT(DU, i) = sw ? dn : cu;
+            AT(DU2, i) = sw ? un : zero;
+            AT(B, i) = sw ? zero : cb;
+            const c64 ncd = sw ? cu - f * dn : dn - f * cu;
+            cu = sw ? -(f * un) : un;
+            cb = sw ? cb : -(f * cb);
+            cd = ncd;
+        }
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+            gl[u] = nl[u];
+            gn[u] = nn[u];
+            gu[u] = nu[u];
         }
     }
     if (cabs1(cd) == 0.0) cd = c64{1e-300, 0.0};
     // back substitution, scaled by the node weight e^s when asked
     const double wgt = scale ? y : 1.0;
-    c64 x1 = cdiv(cb, cd);
+    c64 x1 = cb * crecip(cd);
     AT(B, k - 1) = wgt * x1;
-    c64 x2{0.0, 0.0};
-    for (int i = k - 2; i >= 0; --i) {
-        const c64 xi = cdiv(AT(B, i) - AT(DU, i) * x1 - AT(DU2, i) * x2, AT(D, i));
-        AT(B, i) = wgt * xi;
-        x2 = x1;
-        x1 = xi;
+    c64 x2 = zero;
+    c64 fb[kPf], fu[kPf], fu2[kPf], fp[kPf];
+    auto fetch = [&](int i, c64& b, c64& du, c64& du2, c64& ip) {
+        b = AT(B, i); du = AT(DU, i); du2 = AT(DU2, i); ip = AT(IP, i);
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        fb[u] = fu[u] = fu2[u] = fp[u] = zero;
+        if (k - 2 - u >= 0) fetch(k - 2 - u, fb[u], fu[u], fu2[u], fp[u]);
+    }
+    for (int i0 = k - 2; i0 >= 0; i0 -= kPf) {
+        c64 nb[kPf], nu[kPf], nu2[kPf], np[kPf];
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+            nb[u] = nu[u] = nu2[u] = np[u] = zero;
+            if (i0 - kPf - u >= 0) fetch(i0 - kPf - u, nb[u], nu[u], nu2[u], np[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+            const int i = i0 - u;
+            if (i < 0) break;
+            const c64 xi = (fb[u] - fu[u] * x1 - fu2[u] * x2) * fp[u];
+            AT(B, i) = wgt * xi;
+            x2 = x1;
+            x1 = xi;
+        }
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) {
+            fb[u] = nb[u];
+            fu[u] = nu[u];
+            fu2[u] = nu2[u];
+            fp[u] = np[u];
+        }
     }
 #undef AT
 }
@@ -207,7 +286,7 @@ int launch_small_sign(int nrhs, int k, TslCoeffs co, const SmallSignCfg& cfg, c6
     double* diff = smin + nrhs;
     hipError_t e = hipMemsetAsync(acc, 0, sizeof(c64) * 2 * nrhs * k, s);
     if (e != hipSuccess) return -(int)e;
-    small_sign_setup_kernel<<<(nrhs + 63) / 64, 64, 0, s>>>(nrhs, k, co, smin);
+    small_sign_setup_kernel<<<nrhs, 256, 0, s>>>(nrhs, k, co, smin);
     const double h0 = 2.0 * cfg.quad_step;
     const int Q0 = (int)ceil((kLowSpan + kHighSpan) / h0) + 1;
     const int chunk = chunk_solves / (2 * nrhs) > 0 ? chunk_solves / (2 * nrhs) : 1;
@@ -288,9 +367,14 @@ __global__ __launch_bounds__(64) void frechet_accum_kernel(int k, int nsol, cons
 }
 
 // Mout = -(h/pi) Msum + tail; diff = max |Mout - Mprev|; Mprev <- Mout   (one block)
-__global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __restrict__ smin, double h, long long qlast,
-                                        const c64* __restrict__ Msum, c64* __restrict__ Mout,
-                                        c64* __restrict__ Mprev, double* __restrict__ diff) {
+// M = -(h/pi) Msum + tail, elementwise over kFinBlocks blocks; each block's
+// largest change against the previous level goes to part[block] (the max over
+// blocks, taken by fin_max_kernel, is independent of the order)
+constexpr int kFinBlocks = 64;
+__global__ __launch_bounds__(256) void frechet_finalize_kernel(int k, TslCoeffs co, const double* __restrict__ smin,
+                                                               double h, long long qlast,
+                                                               const c64* __restrict__ Msum, c64* __restrict__ Mout,
+                                                               c64* __restrict__ Mprev, double* __restrict__ part) {
     __shared__ double red[256];
     __shared__ c64 T2[3][3], Tm[3][3];
     __shared__ double w1s, w3s;
@@ -317,7 +401,7 @@ __global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __res
     }
     __syncthreads();
     double dmax = 0.0;
-    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k * k; t += gridDim.x * blockDim.x) {
         const int i = t / k, j = t % k;
         c64 m = (-h / M_PI) * Msum[t];
         // tail: w1 E - w3 (E T^2 + T E T + T^2 E), E = e_1 e_1^T
@@ -339,11 +423,18 @@ __global__ void frechet_finalize_kernel(int k, TslCoeffs co, const double* __res
         if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + s] ? red[threadIdx.x] : red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) diff[0] = red[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void fin_max_kernel(int n, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = part[i] > m ? part[i] : m;
+    *out = m;
 }
 
 size_t small_frechet_scratch_elems(int k) {
-    return 2 * (4 * (size_t)k * kDefaultChunkSolves) + 3 * (size_t)k * k + 4;
+    return 2 * (4 * (size_t)k * kDefaultChunkSolves) + 3 * (size_t)k * k + 4 + kFinBlocks;
 }
 
 // M (k x k, row-major) = L_sgn(T, e_1 e_1^T) for one tridiagonal (rhs 0 of co);
@@ -357,9 +448,10 @@ int launch_small_frechet(int k, TslCoeffs co, const SmallSignCfg& cfg, c64* scra
     c64* Mprev = Msum + (size_t)k * k;
     double* smin = (double*)(Mprev + (size_t)k * k);
     double* diff = smin + 2;
+    double* fpart = smin + 8;   // kFinBlocks partial maxima
     hipError_t e = hipMemsetAsync(Msum, 0, sizeof(c64) * 2 * k * k, s);
     if (e != hipSuccess) return -(int)e;
-    small_sign_setup_kernel<<<1, 64, 0, s>>>(1, k, co, smin);
+    small_sign_setup_kernel<<<1, 256, 0, s>>>(1, k, co, smin);
     const double h0 = 2.0 * cfg.quad_step;
     const int Q0 = (int)ceil((kLowSpan + kHighSpan) / h0) + 1;
     const int chunk = kDefaultChunkSolves / 2;
@@ -381,7 +473,8 @@ int launch_small_frechet(int k, TslCoeffs co, const SmallSignCfg& cfg, c64* scra
         }
         const double hl = h0 / (double)(1LL << lev);
         const long long qlast = (long long)(Q0 - 1) * (1LL << lev);
-        frechet_finalize_kernel<<<1, 256, 0, s>>>(k, co, smin, hl, qlast, Msum, M_out, Mprev, diff);
+        frechet_finalize_kernel<<<kFinBlocks, 256, 0, s>>>(k, co, smin, hl, qlast, Msum, M_out, Mprev, fpart);
+        fin_max_kernel<<<1, 64, 0, s>>>(kFinBlocks, fpart, diff);
         if (lev == 0) continue;
         if ((e = hipMemcpyAsync(&hd, diff, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return -(int)e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return -(int)e;
