@@ -95,7 +95,10 @@ typedef struct {
                                finishes one of its two outputs before the other: half the
                                live accumulators, twice the waves per SIMD in FP64), 0 the
                                paired form (both outputs at once, every link loaded once);
-                               -1 (default): tuned, else paired */
+                               2 (plain sgn(H) and the gradient only, 1 or 2 groups per
+                               block) the split form (the two outputs of a site in two
+                               waves: twice the waves of the paired form, for launches too
+                               small to fill the GPU); -1 (default): tuned, else paired */
     int shape_rp;           /* ovd_apply_op with OVD_OP_H or OVD_OP_DW on an even number of
                                right-hand sides: 2 forces two per thread (each link loaded
                                once for both), 1 one per thread; 0 (default): tuned */

@@ -192,20 +192,26 @@ bool forced_shape(ovd_h h, int nrhs, int def_gpb, StencilVariant* v) {
     v->map = h->opt.shape_map >= 0 ? h->opt.shape_map : default_map(nrhs);
     if (v->map == 0 && nrhs % 8 != 0) v->map = 1;
     v->gpb = h->opt.shape_gpb > 0 ? h->opt.shape_gpb : def_gpb;
-    v->seq = h->opt.shape_seq > 0 ? 1 : 0;
+    v->seq = h->opt.shape_seq == 2 ? 2 : h->opt.shape_seq > 0 ? 1 : 0;
     v->rp = h->opt.shape_rp == 2 ? 2 : 1;
     return true;
 }
 
-// launch shapes to time: both work orders, the given groups per block, and
-// with seq_too the sequential form of each (the LDS-plane shape has none)
-std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& gpbs, bool seq_too = false) {
+// launch shapes to time: both work orders, the given groups per block, with
+// seq_too the sequential form of each (the LDS-plane shape has none), and with
+// split_too the split form of DIR 0 with 1 and 2 groups per block
+std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& gpbs, bool seq_too = false,
+                                             bool split_too = false) {
     std::vector<StencilVariant> c;
     for (int map : {1, 0}) {
         if (map == 0 && nrhs % 8 != 0) continue;
         for (int gpb : gpbs) {
             c.push_back(StencilVariant{map, gpb, 0});
             if (seq_too && gpb != 8) c.push_back(StencilVariant{map, gpb, 1});
+        }
+        if (split_too) {
+            c.push_back(StencilVariant{map, 1, 2});
+            c.push_back(StencilVariant{map, 2, 2});
         }
     }
     return c;
@@ -541,7 +547,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
     const long long fsz = (long long)halves * 12 * g.Vp;
     const cpx<T>* U = std::is_same<T, double>::value ? (const cpx<T>*)h->U64 : (const cpx<T>*)h->U32;
     const cpx<T>* dU = std::is_same<T, double>::value ? (const cpx<T>*)h->dU64 : (const cpx<T>*)h->dU32;
-    const int nb = tsl_stencil_blocks(g, dir, dir == 0 ? 2 : 1);   // the most blocks of any launch shape
+    const int nb = tsl_stencil_blocks(g, dir, 1);   // the most blocks of any launch shape
 
     WS(ring, cpx<T>, "tsl_ring", (size_t)10 * nrhs * fsz);
     WS(st, TslState, "tsl_state", nrhs);
@@ -599,7 +605,12 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         auto it = h->tuned.find(key);
         if (forced_shape(h, nrhs, dir == 0 ? 4 : 2, &var)) {
             if (var.gpb == 8 && !tsl_plane_ok(g)) var.gpb = 0;
-            if (dir == 0 && var.gpb != 2 && var.gpb != 8) var.gpb = 4;
+            if (var.seq == 2 && (dir != 0 || var.gpb == 8)) var.seq = 0;   // the split form: DIR 0, 1 or 2 groups
+            if (dir == 0 && var.seq == 2) {
+                if (var.gpb != 1) var.gpb = 2;
+            } else if (dir == 0 && var.gpb != 2 && var.gpb != 8) {
+                var.gpb = 4;
+            }
             if (dir != 0 && var.gpb != 1 && var.gpb != 8) var.gpb = 2;
             if (dir == 2 || var.gpb == 8) var.seq = 0;
             h->tuned[key] = var;
@@ -624,7 +635,7 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
                 shape_candidates(nrhs,
                                  tsl_plane_ok(g) ? (dir == 0 ? std::vector<int>{4, 2, 8} : std::vector<int>{2, 1, 8})
                                                  : (dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1}),
-                                 dir != 2),
+                                 dir != 2, dir == 0),
                 [&](StencilVariant v) {
                     launch_tsl_stencil<T>(g, dir, nrhs, p0, U, dU, md, tst, tco, tpart, tcnt, 0, h->opt.breakdown_tol,
                                           h->stream, v);
@@ -1432,7 +1443,7 @@ ovd_status ovd_get_tuned(ovd_h h, char* buf, int len) {
     std::string out;
     for (const auto& kv : h->tuned)
         out += kv.first + "=map" + std::to_string(kv.second.map) + ",gpb" + std::to_string(kv.second.gpb) +
-               (kv.second.seq ? ",seq" : "") + (kv.second.rp == 2 ? ",rp2;" : ";");
+               (kv.second.seq == 2 ? ",split" : kv.second.seq ? ",seq" : "") + (kv.second.rp == 2 ? ",rp2;" : ";");
     std::strncpy(buf, out.c_str(), (size_t)len - 1);
     buf[len - 1] = 0;
     return OVD_OK;

@@ -900,14 +900,22 @@ constexpr int PLANE_GPB = 8;
 // The body of one launch's block `bid` of `nblocks` (blocks per rhs = nblocks / nrhs);
 // a standalone launch passes its own grid, a multi-lattice launch the block's
 // place inside its lattice's range of blocks.
-template <typename T, int DIR, int GPB, bool SEQ>
+// FORM 0: paired (one thread computes both outputs of its pair, loading each
+// link once for both); 1: sequential (one output after the other in the same
+// thread, one accumulator live); 2: split (DIR 0 only: the two outputs of a
+// site in the two waves of a (v, w) wave pair, twice the waves of the paired
+// form for a launch too small to fill the GPU).
+template <typename T, int DIR, int GPB, int FORM>
 __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblocks, Geom g, StepPtrs p,
                                                  const cpx<T>* __restrict__ U, const cpx<T>* __restrict__ dU, T mdiag,
                                                  TslState* __restrict__ st, TslCoeffs co,
                                                  double* __restrict__ partials, unsigned* __restrict__ counters, int j,
                                                  double tau, int ngroups, int nrhs, int map) {
     constexpr bool PLANE = GPB == PLANE_GPB;
+    constexpr bool SEQ = FORM != 0;              // the sequential body, whole or split over two waves
+    constexpr bool SPLIT = FORM == 2;
     static_assert(!SEQ || (!PLANE && DIR != 2), "sequential form: DIR 0/1 without the plane in LDS");
+    static_assert(!SPLIT || DIR == 0, "split form: DIR 0 only");
     constexpr int NQ = sizeof(T) == 8 ? 12 : 6;     // 16-byte entries per site
     extern __shared__ float4 plane_lds[];           // PLANE: [2][NQ][P]
     __shared__ double lds[16 * 8];
@@ -929,8 +937,10 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
         s = plane * P + (int)threadIdx.x;
         active = plane < g.V / P && (int)threadIdx.x < P;
     } else {
-        vside = (DIR == 0) || (wave & 1) == 0;
-        const int grp = (DIR == 0) ? wk.grp * GPB + wave : wk.grp * GPB + (wave >> 1);
+        // DIR 0: one pair per wave; DIR 1/2 and the split form: (v, w) wave pairs
+        constexpr bool VW = DIR != 0 || SPLIT;
+        vside = !VW || (wave & 1) == 0;
+        const int grp = VW ? wk.grp * GPB + (wave >> 1) : wk.grp * GPB + wave;
         s = grp * 64 + (threadIdx.x & 63);
         active = (grp < ngroups) && (s < g.V);
     }
@@ -996,11 +1006,14 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
     if constexpr (SEQ) {
         // the two outputs one after the other, each with its own-site terms,
         // eight hops, store and gamma contribution; one straight-line body per
-        // side (VS: the v side; DIR 0 has one side)
-        auto body = [&](auto vs_tag) {
+        // side (VS: the v side; DIR 0 has one side).  PARTS: 1 the first
+        // output, 2 the second, 3 both (the split form gives each to one wave).
+        auto body = [&](auto vs_tag, auto parts_tag) {
             constexpr bool VS = decltype(vs_tag)::value;
+            constexpr int PARTS = decltype(parts_tag)::value;
             const Nbr N = neighbours(g, s);
             cpx<T> acc[12];
+            if constexpr ((PARTS & 1) != 0) {
             {
                 cpx<T> a[12];
                 ld_site<T>(Ab, Vp16, so, a);
@@ -1033,6 +1046,8 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
                 dot_acc(part, 2, w, acc);
             }
             __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr ((PARTS & 2) != 0) {
             {
                 cpx<T> b[12];
                 ld_site<T>(Bb, Vp16, so, b);
@@ -1060,10 +1075,18 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
                 ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
                 dot_acc(part, 2, w, acc);
             }
+            }
         };
+        using both = std::integral_constant<int, 3>;
         if (active) {
-            if (DIR == 0 || vside) body(std::integral_constant<bool, true>{});
-            else body(std::integral_constant<bool, false>{});
+            if constexpr (SPLIT) {   // DIR 0: the v wave H vhat, the w wave H^dag what
+                if (vside) body(std::integral_constant<bool, true>{}, std::integral_constant<int, 1>{});
+                else body(std::integral_constant<bool, true>{}, std::integral_constant<int, 2>{});
+            } else if (DIR == 0 || vside) {
+                body(std::integral_constant<bool, true>{}, both{});
+            } else {
+                body(std::integral_constant<bool, false>{}, both{});
+            }
         }
     } else {
         cpx<T> accA[12], accB[12];
@@ -1238,8 +1261,21 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_kernel(Geom g, Ste
                                                           double* __restrict__ partials,
                                                           unsigned* __restrict__ counters, int j, double tau,
                                                           int ngroups, int nrhs, int map) {
-    tsl_stencil_body<T, DIR, GPB, SEQ>((int)blockIdx.x, (int)gridDim.x, g, p, U, dU, mdiag, st, co, partials,
+    tsl_stencil_body<T, DIR, GPB, SEQ ? 1 : 0>((int)blockIdx.x, (int)gridDim.x, g, p, U, dU, mdiag, st, co, partials,
                                        counters, j, tau, ngroups, nrhs, map);
+}
+
+// The split form of the plain pair (DIR 0): GPB site groups per block, each
+// with a v wave (H vhat) and a w wave (H^dag what).
+template <typename T, int GPB>
+__global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_split_kernel(Geom g, StepPtrs p,
+                                                                           const cpx<T>* __restrict__ U, T mdiag,
+                                                                           TslState* __restrict__ st, TslCoeffs co,
+                                                                           double* __restrict__ partials,
+                                                                           unsigned* __restrict__ counters, int j,
+                                                                           double tau, int ngroups, int nrhs, int map) {
+    tsl_stencil_body<T, 0, GPB, 2>((int)blockIdx.x, (int)gridDim.x, g, p, U, U, mdiag, st, co, partials, counters, j,
+                                   tau, ngroups, nrhs, map);
 }
 
 // One Lanczos step of several lattices in one launch: the blocks are split
@@ -1254,7 +1290,7 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_multi_kernel(const
     for (int q = 1; q < nseg; ++q)
         if ((int)blockIdx.x >= seg[q].block0) i = q;
     const TslSegment& S = seg[i];
-    tsl_stencil_body<T, DIR, GPB, SEQ>((int)blockIdx.x - S.block0, S.nblocks, S.g, S.p, (const cpx<T>*)S.U,
+    tsl_stencil_body<T, DIR, GPB, SEQ ? 1 : 0>((int)blockIdx.x - S.block0, S.nblocks, S.g, S.p, (const cpx<T>*)S.U,
                                          (const cpx<T>*)S.dU, T(S.mdiag), S.st, S.co, S.partials, S.counters, j, S.tau,
                                          S.ngroups, S.nrhs, S.map);
 }
@@ -1314,9 +1350,17 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
         OVD_TSL(D, PLANE_GPB, 256, plds, false);                                                           \
     } while (0)
     if (v.gpb == PLANE_GPB && !tsl_plane_ok(g)) v.gpb = dir == 0 ? 4 : 2;
-    const bool seq = v.seq && dir != 2 && v.gpb != PLANE_GPB;
+    const bool split = dir == 0 && v.seq == 2 && (v.gpb == 1 || v.gpb == 2);
+    const bool seq = v.seq == 1 && dir != 2 && v.gpb != PLANE_GPB;
     grid = dim3(tsl_stencil_blocks(g, dir, v.gpb) * nrhs);
-    if (dir == 0) {
+    if (split) {
+        if (v.gpb == 1)
+            tsl_stencil_split_kernel<T, 1><<<grid, 128, 0, s>>>(g, p, U, md, st, co, partials, counters, j, tau,
+                                                                ngroups, nrhs, v.map);
+        else
+            tsl_stencil_split_kernel<T, 2><<<grid, 256, 0, s>>>(g, p, U, md, st, co, partials, counters, j, tau,
+                                                                ngroups, nrhs, v.map);
+    } else if (dir == 0) {
         if (v.gpb == PLANE_GPB) OVD_TSL_PLANE(0);
         else if (v.gpb == 2) {
             if (seq) OVD_TSL(0, 2, 128, 0, true);

@@ -140,7 +140,8 @@ void launch_unpack_spinor(const Geom& g, int n, const cpx<T>* in, long long stri
 struct StencilVariant {
     int map = -1;
     int gpb = 0;
-    int seq = 0;   // 1: the two outputs of a pair one after the other (DIR 0/1, not the plane shape)
+    int seq = 0;   // 1: the two outputs of a pair one after the other (DIR 0/1, not the plane shape);
+                   // 2: split, the two outputs of a site in two waves (DIR 0, 1 or 2 groups per block)
     int rp = 1;    // Dw.v (H, Dw): right-hand sides per thread, 1 or 2 (2 needs an even count)
 };
 inline int default_map(int nrhs) { return (nrhs >= 16 && nrhs % 8 == 0) ? 0 : 1; }

@@ -40,6 +40,49 @@ def test_forced_shapes_deriv_and_sign(shape):
             assert rel(out[r], dirac.flat(dirac.apply_h(U, b[r].ravel(), dims, mu))) < 1e-14
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 2), (1, 2, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_split_form_of_the_plain_pair(shape, prec):
+    """The split form of the plain pair (H vhat and H^dag what of a site in two
+    waves), forced, against the oracle on a lattice whose volume is not a
+    multiple of the 64-site group: sgn(H)b for three sources (FP64 to 1e-10,
+    mixed to 5e-5 as the paired form) and, in FP64, the gradient's bilinear
+    run (s, ds/dmu and the force to 1e-10).  The split form computes each
+    output as the sequential form does; with 2 groups per block (the same
+    blocks and partial sums) it matches that form bit for bit."""
+    import numpy as np
+
+    from paper_1611_00195_amd import ovderiv
+    from oracle import vjp
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k, nrhs, mu = (5, 3, 4, 3), 24, 3, 0.25
+    print_case(test="split_form", shape=shape, prec=prec, dims=dims, nrhs=nrhs)
+    p = ovderiv.FP64 if prec == "fp64" else ovderiv.MIXED
+    U = synth.make_links(dims, 0.5, 911)
+    b = synth.make_sources(dims, nrhs, 912)
+    x = synth.make_source(dims, 913)
+    h, hd, _, _ = ops(U, dims, mu)
+    lat = ovderiv.Lattice(dims, precision=p, shape=shape)
+    lat.set_links(dev(U))
+    y = host(lat.sign_apply(dev(b), mu, k))
+    assert ",split" in lat.tuned_shapes()
+    tol = 1e-10 if prec == "fp64" else 5e-5
+    for r in range(nrhs):
+        ref, _ = tsl.krylov_sign(h, hd, b[r].ravel(), b[r].ravel(), k)
+        assert rel(y[r], ref) < tol
+    if shape[1] == 2:   # the same blocks and partial sums as the sequential form
+        seq = ovderiv.Lattice(dims, precision=p, shape=(shape[0], 2, 1))
+        seq.set_links(dev(U))
+        assert np.array_equal(host(seq.sign_apply(dev(b), mu, k)), y)
+        seq.close()
+    if prec == "fp64":
+        s, dm, F = lat.sign_apply_vjp(dev(x[None]), dev(b[:1]), mu, k, force=True)[:3]
+        s_r, dm_r, F_r, _ = vjp.krylov_vjp(U, dims, mu, x, b[0], k)
+        assert abs(s - s_r) < 1e-10 * abs(s_r) and abs(dm - dm_r) < 1e-10 * abs(dm_r)
+        assert rel(host(F), F_r) < 1e-10
+    lat.close()
+
+
 def test_autotuner_records_a_shape():
     from paper_1611_00195_amd import ovderiv
     from gpu_helpers import dev, print_case
