@@ -168,18 +168,28 @@ StencilVariant autotune(ovd_h h, const std::vector<StencilVariant>& cands, Launc
         (void)hipEventDestroy(a);
         return best;
     }
-    for (const auto& v : cands) {
-        reset();
-        launch(v);
-        (void)hipEventRecord(a, h->stream);
-        for (int r = 0; r < 3; ++r) launch(v);
-        (void)hipEventRecord(b, h->stream);
-        float ms = 0.f;
-        if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = v;
+    // three rounds over the candidates (each: a warm-up launch, then three timed
+    // launches), the best of its rounds per candidate: shapes within a few per
+    // cent of each other are then ranked by more than one sample, and drift
+    // over the rounds does not favour one of them
+    std::vector<float> tmin(cands.size(), 1e30f);
+    for (int round = 0; round < 3; ++round)
+        for (size_t i = 0; i < cands.size(); ++i) {
+            const auto& v = cands[i];
+            reset();
+            launch(v);
+            (void)hipEventRecord(a, h->stream);
+            for (int r = 0; r < 3; ++r) launch(v);
+            (void)hipEventRecord(b, h->stream);
+            float ms = 0.f;
+            if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess)
+                tmin[i] = std::min(tmin[i], ms);
         }
-    }
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (tmin[i] < best_ms) {
+            best_ms = tmin[i];
+            best = cands[i];
+        }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     (void)hipGetLastError();
