@@ -243,6 +243,44 @@ __global__ void cneg_kernel(int n, const c64* __restrict__ in, c64* __restrict__
     if (i < n) out[i] = -in[i];
 }
 
+// One CG step's vector updates and the next residual norm in one pass:
+//   z += f d,  r -= f t  (f = num / den from device scalars, 0 when den = 0),
+// and the kDotBlocks block partial sums of r^dag r for the new r, with the
+// same element-to-thread map and arithmetic as axpy_ratio_kernel and
+// dot_partial_kernel (dot_final_kernel then adds them in order): the results
+// are those of the three separate launches.
+__global__ __launch_bounds__(256) void cg_update_kernel(long long n_elem, c64* z, const c64* __restrict__ d, c64* r,
+                                                        const c64* __restrict__ t, const c64* __restrict__ num,
+                                                        const c64* __restrict__ den, c64* __restrict__ part) {
+    __shared__ double lds[8];
+    const c64 a = *num, b = *den;
+    const double bb = b.re * b.re + b.im * b.im;
+    const c64 fz = bb > 0 ? c64{1.0 * (a.re * b.re + a.im * b.im) / bb, 1.0 * (a.im * b.re - a.re * b.im) / bb}
+                          : c64{0.0, 0.0};
+    const c64 fr = bb > 0 ? c64{-1.0 * (a.re * b.re + a.im * b.im) / bb, -1.0 * (a.im * b.re - a.re * b.im) / bb}
+                          : c64{0.0, 0.0};
+    double re = 0.0, im = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem; e += stride) {
+        {
+            const c64 y = d[e];
+            c64 v = z[e];
+            v.re += fz.re * y.re - fz.im * y.im;
+            v.im += fz.re * y.im + fz.im * y.re;
+            z[e] = v;
+        }
+        const c64 y = t[e];
+        c64 v = r[e];
+        v.re += fr.re * y.re - fr.im * y.im;
+        v.im += fr.re * y.im + fr.im * y.re;
+        r[e] = v;
+        re += v.re * v.re + v.im * v.im;
+        im += v.re * v.im - v.im * v.re;
+    }
+    block_sum2(re, im, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = c64{re, im};
+}
+
 namespace {
 
 // progress lines on stderr when OVDERIV_VERBOSE is set (long setup runs)
@@ -413,6 +451,18 @@ struct Ctx {
         dot_final_kernel<<<1, 256, 0, s>>>(kDotBlocks, dot_part, dst);
         return ok(hipGetLastError(), "dot");
     }
+    // z += (num/den) d, r -= (num/den) t, dst = r^dag r of the new r (device scalars)
+    bool cg_update(c64* z, const c64* d, c64* r, const c64* t, const c64* num, const c64* den, c64* dst) {
+        if (!dot_part) {
+            void* p = nullptr;
+            if (!ok(hipMalloc(&p, kDotBlocks * sizeof(c64)), "hipMalloc")) return false;
+            owned.push_back(p);
+            dot_part = (c64*)p;
+        }
+        cg_update_kernel<<<kDotBlocks, 256, 0, s>>>(nf, z, d, r, t, num, den, dot_part);
+        dot_final_kernel<<<1, 256, 0, s>>>(kDotBlocks, dot_part, dst);
+        return ok(hipGetLastError(), "cg_update");
+    }
     bool axpy_ratio(const c64* X, double sgn, const c64* num, const c64* den, const c64* Y, c64* out) {
         long long nb = (nf + 255) / 256;
         if (nb > 8192) nb = 8192;
@@ -490,8 +540,7 @@ bool solve_h(Ctx& c, double mu, const c64* v, c64* z, c64* r, c64* d, c64* q, c6
     for (int it = 0; it < max_it; ++it) {
         if (!c.apply(0, mu, d, q, 1) || !c.apply(0, -mu, q, t, 1)) return false;   // t = H^dag H d
         if (!c.dot_dev(q, q, qq)) return false;
-        if (!c.axpy_ratio(z, 1.0, rr, qq, d, z) || !c.axpy_ratio(r, -1.0, rr, qq, t, r)) return false;
-        if (!c.dot_dev(r, r, rn)) return false;
+        if (!c.cg_update(z, d, r, t, rr, qq, rn)) return false;   // z += a d, r -= a t, rn = r^dag r
         ++iters;
         if ((it + 1) % kCgCheck == 0 || it + 1 == max_it) {
             if (!c.read_scalar(rn, h)) return false;
