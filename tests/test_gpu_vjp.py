@@ -226,10 +226,10 @@ def test_vjp_recomputed_basis_matches_stored(prec, k):
         assert lat.last_stats.basis_recomputed == rc
         lat.close()
     (s0, d0, F0, U0, C0), (s1, d1, F1, U1, C1) = out[0], out[1]
-    assert abs(s1 - s0) <= 1e-13 * abs(s0)
-    assert abs(d1 - d0) <= 1e-13 * abs(d0)
-    for a, c in ((F1, F0), (U1, U0), (C1, C0)):
-        assert rel(host(a), host(c)) < 1e-13
+    devs = [abs(s1 - s0) / abs(s0), abs(d1 - d0) / abs(d0)] + \
+        [rel(host(a), host(c)) for a, c in ((F1, F0), (U1, U0), (C1, C0))]
+    print(f"  prec {prec} k {k}: regenerated against stored " + " ".join(f"{e:.1e}" for e in devs), flush=True)
+    assert max(devs) < 1e-13
     if prec == 0:
         s_r, dm_r, F_r, _ = vjp.krylov_vjp(U, dims, MU, x, b, k)
         assert abs(s0 - s_r) < 1e-10 * abs(s_r) and abs(d0 - dm_r) < 1e-10 * abs(dm_r)
