@@ -259,13 +259,21 @@ def run_gpu(args):
         ref = main["vals"] if prec == ovderiv.FP64 else oth["vals"]
         mix = oth["vals"] if prec == ovderiv.FP64 else main["vals"]
         err = max(abs(a - b) / abs(b) for a, b in zip(mix, ref))
+        # the batched mixed form at 32 sources (4 sources per XCD), against the
+        # plain single-source FP64 path
+        m32 = time_form(args, U, ovderiv.MIXED, 32, 2, 1, V)
+        mixed_n = oth["evals_per_s"] if other == ovderiv.MIXED else main["evals_per_s"]
         forms = {
             "fp64_single_evals_per_s": round(single["evals_per_s"], 3),
             "mixed_single_evals_per_s": round(msingle["evals_per_s"], 3),
             ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}_evals_per_s": round(oth["evals_per_s"], 3),
+            "mixed_batched32_evals_per_s": round(m32["evals_per_s"], 3),
+            "mixed_batched_over_fp64_single": {str(n): round(mixed_n / single["evals_per_s"], 3),
+                                               "32": round(m32["evals_per_s"] / single["evals_per_s"], 3)},
             "mixed_vs_fp64_max_rel_err_xdy": err,
             "launch_shapes": {"fp64_single": single["shapes"], "mixed_single": msingle["shapes"],
-                              ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}": oth["shapes"]},
+                              ("mixed" if other == ovderiv.MIXED else "fp64") + f"_batched{n}": oth["shapes"],
+                              "mixed_batched32": m32["shapes"]},
         }
     out["forms"] = forms
     if not args.skip_forms:
