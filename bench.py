@@ -658,6 +658,8 @@ def main():
     ap.add_argument("--uneven-only", action="store_true",
                     help="only the uneven batch (48 solves on 6^4 .. 20x20^3, shared and separate forms); "
                          "prints its JSON record")
+    ap.add_argument("--vjp-only", action="store_true",
+                    help="only the gradient of <x|sgn(H)|b> (FP64 and mixed, bases stored); prints its JSON record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU form "
@@ -674,6 +676,20 @@ def main():
         torch.cuda.set_device(0)
         rec = time_uneven(args)
         rec.pop("vals", None)
+        print(json.dumps(rec), flush=True)
+        return
+    if args.vjp_only:
+        import synth
+        import torch
+        torch.cuda.set_device(0)
+        dims = tuple(args.dims)
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        U = torch.from_numpy(synth.make_links(dims, args.eps, 1611)).cuda()
+        rec = {}
+        for name, prec in (("fp64", 0), ("mixed", 1)):
+            r = time_vjp(args, U, V, prec=prec)
+            r.pop("F", None)
+            rec[name] = r
         print(json.dumps(rec), flush=True)
         return
     g = run_gpu(args)
