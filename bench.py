@@ -69,13 +69,20 @@ def measured_traffic(pb: int, nrhs: int, shapes: str = ""):
         if ":" in line:
             a, b = line.split(":", 1)
             kv[a.strip()] = b.strip()
-    # the tuned entry "tsl:d:1:<nrhs>=map<m>,gpb<G>[,seq];" of this run
-    run = re.search(rf"tsl:{'d' if pb == 8 else 'f'}:1:{nrhs}=map(\d+),gpb(\d+)(,seq)?;", shapes)
+    # the tuned entry "tsl:d:1:<nrhs>=map<m>,gpb<G>[,seq|,march];" of this run
+    run = re.search(rf"tsl:{'d' if pb == 8 else 'f'}:1:{nrhs}=map(\d+),gpb(\d+)(,seq|,march)?;", shapes)
     if kv.get("kernels_stencil_sha256_16") != digest or run is None:
         return None
     key = (f"bytes_per_launch_{'fp64' if pb == 8 else 'fp32'}_nrhs{nrhs}_map{run.group(1)}_gpb{run.group(2)}"
-           f"{'_seq' if run.group(3) else ''}")
+           f"{'_' + run.group(3)[1:] if run.group(3) else ''}")
     return float(kv[key]) if key in kv else None
+
+
+def tuned_entry(shapes: str, pb: int, nrhs: int) -> str:
+    """The d/dmu stencil's entry "tsl:<d|f>:1:<nrhs>=...;" of the tuned shapes, or ""."""
+    import re
+    m = re.search(rf"tsl:{'d' if pb == 8 else 'f'}:1:{nrhs}=[^;]*;", shapes)
+    return m.group(0) if m else ""
 
 
 def dwv_bytes_per_site(prec_bytes: int) -> float:
@@ -229,7 +236,7 @@ def run_gpu(args):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(pb, n, prof["shapes"]),
-            "kernel": "tsl_stencil_kernel",
+            "kernel": "tsl_march_kernel" if ",march;" in tuned_entry(prof["shapes"], pb, n) else "tsl_stencil_kernel",
             "launch_shape": prof["shapes"],
             "bytes_per_launch": bytes_launch,
             "us_per_launch": round(st_ms * 1e3, 2),
@@ -490,8 +497,9 @@ def error_vs_k(args):
 
 
 # the stencil launch shapes the autotuner chooses among at 14^4 with 8 sources
-# (groups per block, sequential form); each is run in both XCD orders
-COUNTER_SHAPES = ((8, 0), (1, 0), (2, 0), (1, 1), (2, 1))
+# (groups per block, form: 0 paired, 1 sequential; with form 3, the
+# time-marching form, the number of time segments); each in both XCD orders
+COUNTER_SHAPES = ((8, 0), (1, 0), (2, 0), (1, 1), (2, 1), (1, 3), (2, 3), (4, 3))
 
 
 def counters_run(args):

@@ -88,7 +88,8 @@ typedef struct {
                                ranges per XCD); -1 (default): tuned or default */
     int shape_gpb;          /* > 0: force the site groups per block (Lanczos stencil: 1 or 2
                                for derivatives, 2 or 4 otherwise, or 8: one block per
-                               xy-plane staged in LDS, when 128 <= Lx Ly <= 256; Dw.v: 2 or 4);
+                               xy-plane staged in LDS, when 128 <= Lx Ly <= 256; Dw.v: 2 or 4;
+                               with shape_seq 3 the number of time segments, at most Lt);
                                0: tuned */
     int shape_seq;          /* Lanczos stencil without the derivative of a link field, not the
                                LDS-plane shape: 1 forces the sequential form (each thread
@@ -98,7 +99,12 @@ typedef struct {
                                2 (plain sgn(H) and the gradient only, 1 or 2 groups per
                                block) the split form (the two outputs of a site in two
                                waves: twice the waves of the paired form, for launches too
-                               small to fill the GPU); -1 (default): tuned, else paired */
+                               small to fill the GPU); 3 (the mu derivative only, when the
+                               LDS-plane shape applies and two planes of both input fields
+                               fit the LDS) the time-marching form (one block per xy-plane
+                               column of shape_gpb time segments, walking its time slices
+                               in order and reusing each loaded plane from LDS);
+                               -1 (default): tuned, else paired */
     int shape_rp;           /* ovd_apply_op with OVD_OP_H or OVD_OP_DW on an even number of
                                right-hand sides: 2 forces two per thread (each link loaded
                                once for both), 1 one per thread; 0 (default): tuned */

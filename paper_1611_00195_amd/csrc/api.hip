@@ -202,7 +202,7 @@ bool forced_shape(ovd_h h, int nrhs, int def_gpb, StencilVariant* v) {
     v->map = h->opt.shape_map >= 0 ? h->opt.shape_map : default_map(nrhs);
     if (v->map == 0 && nrhs % 8 != 0) v->map = 1;
     v->gpb = h->opt.shape_gpb > 0 ? h->opt.shape_gpb : def_gpb;
-    v->seq = h->opt.shape_seq == 2 ? 2 : h->opt.shape_seq > 0 ? 1 : 0;
+    v->seq = h->opt.shape_seq == 2 ? 2 : h->opt.shape_seq == 3 ? 3 : h->opt.shape_seq > 0 ? 1 : 0;
     v->rp = h->opt.shape_rp == 2 ? 2 : 1;
     return true;
 }
@@ -463,7 +463,7 @@ void multi_lead(MultiCoord& C) {
     int gpb = 1, seq = P[0]->dir == 1 ? 1 : 0;
     for (const MultiPlan* q : P) {
         if (q->var.gpb != 1) gpb = 2;
-        if (!q->var.seq || (q->var.gpb != 1 && q->var.gpb != 2)) seq = 0;
+        if (q->var.seq != 1 || (q->var.gpb != 1 && q->var.gpb != 2)) seq = 0;
     }
     int maxk = 0, maxr = 0;
     for (MultiPlan* q : P) {
@@ -613,7 +613,12 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
         const std::string key = std::string("tsl:") + (sizeof(T) == 8 ? "d" : "f") + ":" + std::to_string(dir) + ":" +
                                 std::to_string(nrhs);
         auto it = h->tuned.find(key);
-        if (forced_shape(h, nrhs, dir == 0 ? 4 : 2, &var)) {
+        if (forced_shape(h, nrhs, dir == 0 ? 4 : 2, &var) && var.seq == 3 && dir == 1 &&
+            tsl_march_ok(g, (int)sizeof(T))) {
+            if (var.gpb > g.L[3]) var.gpb = g.L[3];   // time segments
+            h->tuned[key] = var;
+        } else if (forced_shape(h, nrhs, dir == 0 ? 4 : 2, &var)) {
+            if (var.seq == 3) var.seq = 0;   // the time-marching form does not apply: paired
             if (var.gpb == 8 && !tsl_plane_ok(g)) var.gpb = 0;
             if (var.seq == 2 && (dir != 0 || var.gpb == 8)) var.seq = 0;   // the split form: DIR 0, 1 or 2 groups
             if (dir == 0 && var.seq == 2) {
@@ -640,12 +645,19 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
             p0.outZ = Zs(1); p0.sZ = fsz;
             p0.xproj = xproj;
             p0.sx = (long long)12 * g.Vp;
-            var = autotune(
-                h,
+            std::vector<StencilVariant> cands =
                 shape_candidates(nrhs,
                                  tsl_plane_ok(g) ? (dir == 0 ? std::vector<int>{4, 2, 8} : std::vector<int>{2, 1, 8})
                                                  : (dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1}),
-                                 dir != 2, dir == 0),
+                                 dir != 2, dir == 0);
+            if (dir == 1 && tsl_march_ok(g, (int)sizeof(T)))   // the time-marching form, 1, 2 or 4 time segments
+                for (int map : {1, 0}) {
+                    if (map == 0 && nrhs % 8 != 0) continue;
+                    for (int ns : {1, 2, 4})
+                        if (ns <= g.L[3]) cands.push_back(StencilVariant{map, ns, 3});
+                }
+            var = autotune(
+                h, cands,
                 [&](StencilVariant v) {
                     launch_tsl_stencil<T>(g, dir, nrhs, p0, U, dU, md, tst, tco, tpart, tcnt, 0, h->opt.breakdown_tol,
                                           h->stream, v);
@@ -1453,7 +1465,8 @@ ovd_status ovd_get_tuned(ovd_h h, char* buf, int len) {
     std::string out;
     for (const auto& kv : h->tuned)
         out += kv.first + "=map" + std::to_string(kv.second.map) + ",gpb" + std::to_string(kv.second.gpb) +
-               (kv.second.seq == 2 ? ",split" : kv.second.seq ? ",seq" : "") + (kv.second.rp == 2 ? ",rp2;" : ";");
+               (kv.second.seq == 3 ? ",march" : kv.second.seq == 2 ? ",split" : kv.second.seq ? ",seq" : "") +
+               (kv.second.rp == 2 ? ",rp2;" : ";");
     std::strncpy(buf, out.c_str(), (size_t)len - 1);
     buf[len - 1] = 0;
     return OVD_OK;

@@ -41,6 +41,11 @@
 #define OVD_SEQ_FENCE __builtin_amdgcn_sched_barrier(0)
 #endif
 
+// scheduling fence between the hops of the time-marching form; empty = none
+#ifndef OVD_MARCH_FENCE
+#define OVD_MARCH_FENCE __builtin_amdgcn_sched_barrier(0)
+#endif
+
 // occupancy hint for the stencil kernels (waves per SIMD), by precision T;
 // empty = compiler's choice
 #ifndef OVD_OCC
@@ -897,6 +902,81 @@ __device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[1
 // fields staged in LDS for the x and y hops.
 constexpr int PLANE_GPB = 8;
 
+// The end of a stencil block: its partial sums into the step's grid reduction,
+// and in the last block of the rhs the step's scalars and the coefficients of
+// the next update.
+__device__ __forceinline__ void tsl_step_tail(double (&part)[8], double* lds, int* am_last, TslState* S,
+                                              TslCoeffs co, double* __restrict__ partials,
+                                              unsigned* __restrict__ counters, int rhs, int nb, int grp, int j,
+                                              double tau) {
+    // Grid reduction without a device-wide fence.  The block's partial sums are
+    // stored with device-scope relaxed atomic stores, which are written through
+    // to the level that all XCDs see; the wait for those stores to complete
+    // orders them before the counter increment; the last block reads the
+    // partials with device-scope loads from that same level.  A full fence
+    // (__threadfence) here would write back and invalidate the XCD's L2 at the
+    // end of every block, costing the stencil a third of its time.
+    block_reduce<8>(part, lds);
+    if (threadIdx.x == 0) {
+        double* dst = partials + ((size_t)rhs * nb + grp) * 8;
+        for (int i = 0; i < 8; ++i) __hip_atomic_store(dst + i, part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);   // the partials have reached the device-coherent level
+        const unsigned prev = __hip_atomic_fetch_add(counters + rhs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *am_last = (prev == (unsigned)(nb - 1));
+    }
+    __syncthreads();
+    if (!*am_last) return;
+    double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double* src = partials + ((size_t)rhs * nb + b) * 8;
+        for (int i = 0; i < 8; ++i) tot[i] += __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_reduce<8>(tot, lds);
+    if (threadIdx.x != 0) return;
+    __hip_atomic_store(counters + rhs, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const c64 omega{tot[0], tot[1]}, gam{tot[2], tot[3]}, pr{tot[4], tot[5]};
+    const double nv = tot[6], nw = tot[7];
+    const double aom = sqrt(norm2(omega));
+    const double margin = aom / sqrt(nv * nw);
+    const size_t ci = (size_t)rhs * co.kmax + j;
+    if (!(margin == margin) || !(nv < 1e300) || !(nw < 1e300) || !(norm2(gam) < 1e300)) {
+        S->flag = 2;
+        S->bstep = j;
+        return;
+    }
+    if (margin < S->min_margin) S->min_margin = margin;
+    if (margin <= tau) {
+        S->flag = 1;
+        S->bstep = j;
+        return;
+    }
+    // j = 0: v_1 = psi/|psi|, w_1 = phi/conj(phi^dag v_1); later delta = sqrt|omega|
+    const double delta = (j == 0) ? sqrt(nv) : sqrt(aom);
+    const c64 beta = (1.0 / delta) * omega;
+    const c64 alpha = cdiv(gam, omega);
+    co.alpha[ci] = alpha;
+    co.beta[ci] = beta;
+    co.delta[ci] = c64{delta, 0.0};
+    co.proj[ci] = (1.0 / delta) * pr;
+    // next update: vhat = (A vhat - alpha vhat)/delta - beta vhat_prev/delta_prev,
+    //              what = (A^dag what - conj(alpha) what)/conj(beta) - delta what_prev/conj(beta_prev)
+    const c64 one{1.0, 0.0};
+    S->av = c64{1.0 / delta, 0.0};
+    S->bv = -((1.0 / delta) * alpha);
+    S->aw = cdiv(one, conj(beta));
+    S->bw = -cdiv(conj(alpha), conj(beta));
+    if (j == 0) {
+        S->cv = c64{0.0, 0.0};
+        S->cw = c64{0.0, 0.0};
+    } else {
+        S->cv = -((1.0 / S->delta_prev) * beta);
+        S->cw = -cdiv(c64{delta, 0.0}, conj(S->beta_prev));
+    }
+    S->delta_prev = delta;
+    S->beta_prev = beta;
+    S->step = j + 1;
+}
+
 // The body of one launch's block `bid` of `nblocks` (blocks per rhs = nblocks / nrhs);
 // a standalone launch passes its own grid, a multi-lattice launch the block's
 // place inside its lattice's range of blocks.
@@ -1186,72 +1266,7 @@ __device__ __forceinline__ void tsl_stencil_body(const int bid, const int nblock
 
     }
 
-    // Grid reduction without a device-wide fence.  The block's partial sums are
-    // stored with device-scope relaxed atomic stores, which are written through
-    // to the level that all XCDs see; the wait for those stores to complete
-    // orders them before the counter increment; the last block reads the
-    // partials with device-scope loads from that same level.  A full fence
-    // (__threadfence) here would write back and invalidate the XCD's L2 at the
-    // end of every block, costing the stencil a third of its time.
-    block_reduce<8>(part, lds);
-    if (threadIdx.x == 0) {
-        double* dst = partials + ((size_t)rhs * nb + wk.grp) * 8;
-        for (int i = 0; i < 8; ++i) __hip_atomic_store(dst + i, part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(0);   // the partials have reached the device-coherent level
-        const unsigned prev = __hip_atomic_fetch_add(counters + rhs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (prev == (unsigned)(nb - 1));
-    }
-    __syncthreads();
-    if (!am_last) return;
-    double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const double* src = partials + ((size_t)rhs * nb + b) * 8;
-        for (int i = 0; i < 8; ++i) tot[i] += __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_reduce<8>(tot, lds);
-    if (threadIdx.x != 0) return;
-    __hip_atomic_store(counters + rhs, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const c64 omega{tot[0], tot[1]}, gam{tot[2], tot[3]}, pr{tot[4], tot[5]};
-    const double nv = tot[6], nw = tot[7];
-    const double aom = sqrt(norm2(omega));
-    const double margin = aom / sqrt(nv * nw);
-    const size_t ci = (size_t)rhs * co.kmax + j;
-    if (!(margin == margin) || !(nv < 1e300) || !(nw < 1e300) || !(norm2(gam) < 1e300)) {
-        S->flag = 2;
-        S->bstep = j;
-        return;
-    }
-    if (margin < S->min_margin) S->min_margin = margin;
-    if (margin <= tau) {
-        S->flag = 1;
-        S->bstep = j;
-        return;
-    }
-    // j = 0: v_1 = psi/|psi|, w_1 = phi/conj(phi^dag v_1); later delta = sqrt|omega|
-    const double delta = (j == 0) ? sqrt(nv) : sqrt(aom);
-    const c64 beta = (1.0 / delta) * omega;
-    const c64 alpha = cdiv(gam, omega);
-    co.alpha[ci] = alpha;
-    co.beta[ci] = beta;
-    co.delta[ci] = c64{delta, 0.0};
-    co.proj[ci] = (1.0 / delta) * pr;
-    // next update: vhat = (A vhat - alpha vhat)/delta - beta vhat_prev/delta_prev,
-    //              what = (A^dag what - conj(alpha) what)/conj(beta) - delta what_prev/conj(beta_prev)
-    const c64 one{1.0, 0.0};
-    S->av = c64{1.0 / delta, 0.0};
-    S->bv = -((1.0 / delta) * alpha);
-    S->aw = cdiv(one, conj(beta));
-    S->bw = -cdiv(conj(alpha), conj(beta));
-    if (j == 0) {
-        S->cv = c64{0.0, 0.0};
-        S->cw = c64{0.0, 0.0};
-    } else {
-        S->cv = -((1.0 / S->delta_prev) * beta);
-        S->cw = -cdiv(c64{delta, 0.0}, conj(S->beta_prev));
-    }
-    S->delta_prev = delta;
-    S->beta_prev = beta;
-    S->step = j + 1;
+    tsl_step_tail(part, lds, &am_last, S, co, partials, counters, rhs, nb, wk.grp, j, tau);
 }
 
 template <typename T, int DIR, int GPB, bool SEQ>
@@ -1276,6 +1291,258 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void tsl_stencil_split_kernel(Geom 
                                                                            double tau, int ngroups, int nrhs, int map) {
     tsl_stencil_body<T, 0, GPB, 2>((int)blockIdx.x, (int)gridDim.x, g, p, U, U, mdiag, st, co, partials, counters, j,
                                    tau, ngroups, nrhs, map);
+}
+
+// The time-marching form of the d/dmu block stencil (DIR 1).  One block per
+// (rhs, side, z, segment of time slices); thread t holds site t of the
+// xy-plane (Lx Ly <= 256) and the block walks its slices in time order.  The
+// plane of slice t + 1, loaded for the forward time hop of slice t, goes into
+// the second LDS buffer and serves as slice t + 1's own plane (own-site terms,
+// x and y hops).  The backward time hop into slice t + 1 is formed at slice t
+// from the own plane and the link U_4 of the forward hop, and carried in
+// registers (the half spinors after the link, before reconstruction).  A
+// slice thus reads from memory the next plane, the two z neighbour planes, the
+// x field, the other side's own site and the links; the plane shape also reads
+// both time neighbours, a whole time slice (Lx Ly Lz sites) away, which an
+// XCD's L2 does not keep.  The hops are those of the plane shape, with the
+// backward time hop added first (the carry is then dead before the other
+// hops' loads), so the outputs agree with that shape to rounding.
+// Blocks per rhs: 2 Lz nseg, padded to a multiple of 8 (padding blocks and
+// empty segments run no slice but take part in the reduction).
+template <typename T>
+__global__ __launch_bounds__(256) void tsl_march_kernel(Geom g, StepPtrs p, const cpx<T>* __restrict__ U, T mdiag,
+                                                        TslState* __restrict__ st, TslCoeffs co,
+                                                        double* __restrict__ partials, unsigned* __restrict__ counters,
+                                                        int j, double tau, int nseg, int nrhs, int map) {
+    constexpr int NQ = sizeof(T) == 8 ? 12 : 6;   // 16-byte entries per site
+    extern __shared__ float4 plane_lds[];          // [buffer 2][field 2][NQ][P]
+    __shared__ double lds[16 * 8];
+    __shared__ int am_last;
+    const int nb = (int)(gridDim.x / (unsigned)nrhs);
+    const Work wk = xcd_work((int)blockIdx.x, nb, nrhs, map);
+    const int rhs = wk.rhs;
+    TslState* S = st + rhs;
+    if (S->flag) return;   // uniform over the rhs: breakdown in an earlier step
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const int P = Lx * Ly, Vp = g.Vp;
+    const int tid = (int)threadIdx.x;
+    const bool vside = (wk.grp & 1) == 0;
+    const int zz = (wk.grp >> 1) % Lz, seg = (wk.grp >> 1) / Lz;
+    const int tlen = (Lt + nseg - 1) / nseg;
+    const int t0 = seg * tlen, t1 = min(Lt, t0 + tlen);   // no slice when t0 >= t1
+    const bool act = tid < P;
+    const T ep = T(S->emu), em = T(S->emu_inv);
+    const size_t HALF = (size_t)12 * Vp;
+    const cpx<T>* Vf = (const cpx<T>*)p.outV + rhs * p.sV;
+    const cpx<T>* Wf = (const cpx<T>*)p.outW + rhs * p.sW;
+    const cpx<T>* Ain = vside ? Vf : Wf;
+    cpx<T>* Aout = vside ? (cpx<T>*)p.outU + rhs * p.sU : (cpx<T>*)p.outZ + rhs * p.sZ;
+    const char* Ab = reinterpret_cast<const char*>(Ain);
+    const char* Bb = reinterpret_cast<const char*>(Ain + HALF);
+    char* Ao = reinterpret_cast<char*>(Aout);
+    char* Bo = reinterpret_cast<char*>(Aout + HALF);
+    const char* Xb = p.xproj ? reinterpret_cast<const char*>((const cpx<T>*)p.xproj + rhs * p.sx) : nullptr;
+    const char* W = reinterpret_cast<const char*>(U);
+    // hop factors (v side H(mu), w side H(-mu)) and the mix factors of the time hops
+    const T cf = vside ? ep : em, cb = vside ? em : ep;
+    const T xfAB = vside ? T(1) : T(0), xbAB = vside ? T(-1) : T(0);
+    const T xfBA = vside ? T(0) : T(-1), xbBA = vside ? T(0) : T(1);
+    const uint32_t Vp16 = (uint32_t)Vp * 16u;
+    const T h = T(-0.5), zr = T(0);
+    const int x = tid % Lx, y = tid / Lx;
+    const int txf = y * Lx + (x == Lx - 1 ? 0 : x + 1), txb = y * Lx + (x == 0 ? Lx - 1 : x - 1);
+    const int tyf = (y == Ly - 1 ? 0 : y + 1) * Lx + x, tyb = (y == 0 ? Ly - 1 : y - 1) * Lx + x;
+
+    auto lds_at = [&](int b, int f, int q, int t) -> float4& {
+        return plane_lds[(((size_t)b * 2 + f) * NQ + q) * P + t];
+    };
+    auto to_lds = [&](int b, int f, int t, const cpx<T> (&v)[12]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float4 e;
+            if constexpr (sizeof(T) == 8) {
+                const double2 d{(double)v[q].re, (double)v[q].im};
+                e = *reinterpret_cast<const float4*>(&d);
+            } else {
+                e = float4{(float)v[2 * q].re, (float)v[2 * q].im, (float)v[2 * q + 1].re, (float)v[2 * q + 1].im};
+            }
+            lds_at(b, f, q, t) = e;
+        }
+    };
+    auto from_lds = [&](int b, int f, int t, cpx<T> (&v)[12]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float4 e = lds_at(b, f, q, t);
+            if constexpr (sizeof(T) == 8) {
+                const double2 d = *reinterpret_cast<const double2*>(&e);
+                v[q] = cpx<T>{(T)d.x, (T)d.y};
+            } else {
+                v[2 * q] = cpx<T>{(T)e.x, (T)e.y};
+                v[2 * q + 1] = cpx<T>{(T)e.z, (T)e.w};
+            }
+        }
+    };
+    // carry: the backward time hop into the next slice, U_4(s)^dag applied
+    // to the projected own fields of site s (as the plane shape's hop 7 does
+    // at the next slice); sb: the boundary factor of that hop
+    cpx<T> kA0[3], kA1[3], kB0[3], kB1[3];
+    auto make_carry = [&](const cpx<T> (&a)[12], const cpx<T> (&b)[12], uint32_t loff, T sb) {
+        cpx<T> u[9];
+        ld_link<T>(W, Vp16, 3, loff, u);
+        cpx<T> a0[3], a1[3], b0[3], b1[3], h0[3], h1[3];
+        proj_ct<T, 7>(a, a0, a1);
+        proj_ct<T, 7>(b, b0, b1);
+        const T cA = h * cb * sb;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = cA * a0[c] + (cA * xbAB) * b0[c];
+            h1[c] = cA * a1[c] + (cA * xbAB) * b1[c];
+        }
+        link_mul<T, false>(u, h0, h1, kA0, kA1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = cA * b0[c] + (cA * xbBA) * a0[c];
+            h1[c] = cA * b1[c] + (cA * xbBA) * a1[c];
+        }
+        link_mul<T, false>(u, h0, h1, kB0, kB1);
+    };
+
+    double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int buf = 0;
+    if (t0 < t1 && act) {   // the first slice's own plane, and the carry into it
+        const uint32_t s0 = (uint32_t)((t0 * Lz + zz) * P + tid) * 16u;
+        const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+        const uint32_t sp = (uint32_t)((tp * Lz + zz) * P + tid) * 16u;
+        cpx<T> a[12], b[12];
+        ld_site<T>(Ab, Vp16, s0, a);
+        to_lds(0, 0, tid, a);
+        ld_site<T>(Bb, Vp16, s0, b);
+        to_lds(0, 1, tid, b);
+        __builtin_amdgcn_sched_barrier(0);
+        ld_site<T>(Ab, Vp16, sp, a);
+        ld_site<T>(Bb, Vp16, sp, b);
+        make_carry(a, b, sp, t0 == 0 ? T(g.bc_t) : T(1));
+    }
+    for (int tt = t0; tt < t1; ++tt) {
+        __syncthreads();   // slice tt's plane is in buffer buf; buffer buf ^ 1 is free
+        if (act) {
+            const int s = (tt * Lz + zz) * P + tid;
+            const uint32_t so = (uint32_t)s * 16u;
+            const Nbr N = neighbours(g, s);
+            const bool keep = tt + 1 < t1;   // the next slice is this block's
+            cpx<T> accA[12], accB[12];
+            {
+                cpx<T> a[12];
+                from_lds(buf, 0, tid, a);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) accA[c] = mdiag * a[c];
+                nrm_acc(part, vside ? 6 : 7, a);
+                if (vside && Xb) {                         // p = x^dag vhat_top
+                    cpx<T> xv[12];
+                    if constexpr (sizeof(T) == 8) ld_site_nt<T>(Xb, Vp16, so, xv);
+                    else ld_site<T>(Xb, Vp16, so, xv);
+                    dot_acc(part, 4, xv, a);
+                }
+                if (!vside) {                              // omega, top halves: wt^dag vt
+                    cpx<T> v[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Vf), Vp16, so, v);
+                    dot_acc(part, 0, a, v);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                cpx<T> b[12];
+                from_lds(buf, 1, tid, b);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) accB[c] = mdiag * b[c];
+                nrm_acc(part, vside ? 6 : 7, b);
+                if (!vside) {                              // omega, bottom halves: wb^dag vb
+                    cpx<T> v[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Vf + HALF), Vp16, so, v);
+                    dot_acc(part, 0, b, v);
+                }
+            }
+            // backward time hop: the carry formed at the previous slice
+            recon_add<T, 7>(accA, kA0, kA1);
+            recon_add<T, 7>(accB, kB0, kB1);
+            __builtin_amdgcn_sched_barrier(0);
+            // x and y hops from the plane in LDS
+#define OVD_ML(I, TN, LS)                                                                                  \
+    pair_hop<T, I, 1>(                                                                                     \
+        accA, accB, [&](cpx<T>(&v)[12]) { from_lds(buf, 0, TN, v); },                                      \
+        [&](cpx<T>(&v)[12]) { from_lds(buf, 1, TN, v); }, W, W, Vp16, (uint32_t)(LS) * 16u, h, h, zr, zr, \
+        vside);                                                                                            \
+    OVD_MARCH_FENCE;
+            OVD_ML(0, txf, s)
+            OVD_ML(1, txb, N.b[0])
+            OVD_ML(2, tyf, s)
+            OVD_ML(3, tyb, N.b[1])
+#undef OVD_ML
+            // z hops from memory
+            {
+                const uint32_t nf = (uint32_t)N.f[2] * 16u, nbk = (uint32_t)N.b[2] * 16u;
+                pair_hop<T, 4, 1>(
+                    accA, accB, [&](cpx<T>(&v)[12]) { ld_site<T>(Ab, Vp16, nf, v); },
+                    [&](cpx<T>(&v)[12]) { ld_site<T>(Bb, Vp16, nf, v); }, W, W, Vp16, so, h, h, zr, zr, vside);
+                OVD_MARCH_FENCE;
+                pair_hop<T, 5, 1>(
+                    accA, accB, [&](cpx<T>(&v)[12]) { ld_site<T>(Ab, Vp16, nbk, v); },
+                    [&](cpx<T>(&v)[12]) { ld_site<T>(Bb, Vp16, nbk, v); }, W, W, Vp16, nbk, h, h, zr, zr, vside);
+                OVD_MARCH_FENCE;
+            }
+            // forward time hop; its neighbour plane is the next slice's own plane
+            {
+                const uint32_t nf = (uint32_t)N.f[3] * 16u;
+                const T sf = N.wf ? T(g.bc_t) : T(1);
+                const int nbuf = buf ^ 1;   // free in this slice; on the last slice the store is unused
+                {
+                    cpx<T> v[12];
+                    ld_site<T>(Ab, Vp16, nf, v);
+                    to_lds(nbuf, 0, tid, v);
+                }
+                {
+                    cpx<T> v[12];
+                    ld_site<T>(Bb, Vp16, nf, v);
+                    to_lds(nbuf, 1, tid, v);
+                }
+                // the thread reads back its own entries: no barrier needed
+                pair_hop<T, 6, 1>(
+                    accA, accB, [&](cpx<T>(&v)[12]) { from_lds(nbuf, 0, tid, v); },
+                    [&](cpx<T>(&v)[12]) { from_lds(nbuf, 1, tid, v); }, W, W, Vp16, so, h * cf * sf, h * cf * sf,
+                    xfAB, xfBA, vside);
+                OVD_MARCH_FENCE;
+            }
+#pragma unroll
+            for (int c = 6; c < 12; ++c) {   // gamma5
+                accA[c] = -accA[c];
+                accB[c] = -accB[c];
+            }
+            store_site<T>(Ao, Vp16, so, accA);
+            store_site<T>(Bo, Vp16, so, accB);
+            if (vside) {   // gamma: wt^dag (A vhat)_top + wb^dag (A vhat)_bottom
+                {
+                    cpx<T> w[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Wf), Vp16, so, w);
+                    dot_acc(part, 2, w, accA);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    cpx<T> w[12];
+                    ld_site<T>(reinterpret_cast<const char*>(Wf + HALF), Vp16, so, w);
+                    dot_acc(part, 2, w, accB);
+                }
+            }
+            if (keep) {   // the carry into the next slice (its backward hop crosses no boundary)
+                __builtin_amdgcn_sched_barrier(0);
+                cpx<T> a[12], b[12];
+                from_lds(buf, 0, tid, a);
+                from_lds(buf, 1, tid, b);
+                make_carry(a, b, so, T(1));
+            }
+        }
+        buf ^= 1;
+    }
+    tsl_step_tail(part, lds, &am_last, S, co, partials, counters, rhs, nb, wk.grp, j, tau);
 }
 
 // One Lanczos step of several lattices in one launch: the blocks are split
@@ -1325,6 +1592,23 @@ bool tsl_plane_ok(const Geom& g) {
     return P >= 128 && P <= 256;
 }
 
+// the time-marching form: two LDS buffers of the plane's two input fields
+static size_t march_lds_bytes(const Geom& g, size_t real_bytes) {
+    return (size_t)2 * 2 * 12 * g.L[0] * g.L[1] * 2 * real_bytes;
+}
+
+bool tsl_march_ok(const Geom& g, int real_bytes) {
+    return tsl_plane_ok(g) && march_lds_bytes(g, (size_t)real_bytes) + 2048 <= 160 * 1024;
+}
+
+static int march_segments(const Geom& g, int nseg) {
+    return nseg < 1 ? 1 : nseg > g.L[3] ? g.L[3] : nseg;
+}
+
+int tsl_march_blocks(const Geom& g, int nseg) {
+    return (2 * g.L[2] * march_segments(g, nseg) + 7) / 8 * 8;
+}
+
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,
@@ -1349,6 +1633,18 @@ void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, con
         }                                                                                                  \
         OVD_TSL(D, PLANE_GPB, 256, plds, false);                                                           \
     } while (0)
+    if (dir == 1 && v.seq == 3 && tsl_march_ok(g, (int)sizeof(T))) {
+        const int nseg = march_segments(g, v.gpb);
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void*)tsl_march_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      160 * 1024 - 2048);
+            attr = true;
+        }
+        tsl_march_kernel<T><<<dim3(tsl_march_blocks(g, nseg) * nrhs), dim3(256), march_lds_bytes(g, sizeof(T)), s>>>(
+            g, p, U, md, st, co, partials, counters, j, tau, nseg, nrhs, v.map);
+        return;
+    }
     if (v.gpb == PLANE_GPB && !tsl_plane_ok(g)) v.gpb = dir == 0 ? 4 : 2;
     const bool split = dir == 0 && v.seq == 2 && (v.gpb == 1 || v.gpb == 2);
     const bool seq = v.seq == 1 && dir != 2 && v.gpb != PLANE_GPB;

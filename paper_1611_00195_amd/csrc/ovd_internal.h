@@ -141,7 +141,8 @@ struct StencilVariant {
     int map = -1;
     int gpb = 0;
     int seq = 0;   // 1: the two outputs of a pair one after the other (DIR 0/1, not the plane shape);
-                   // 2: split, the two outputs of a site in two waves (DIR 0, 1 or 2 groups per block)
+                   // 2: split, the two outputs of a site in two waves (DIR 0, 1 or 2 groups per block);
+                   // 3: time-marching (DIR 1, plane shape applies; gpb = number of time segments)
     int rp = 1;    // Dw.v (H, Dw): right-hand sides per thread, 1 or 2 (2 needs an even count)
 };
 inline int default_map(int nrhs) { return (nrhs >= 16 && nrhs % 8 == 0) ? 0 : 1; }
@@ -163,6 +164,12 @@ void launch_tsl_update(int nrhs, int nterms, long long fsz, const StepPtrs& p, c
 int tsl_stencil_blocks(const Geom& g, int dir, int gpb = 0);
 // the plane-in-LDS launch shape (gpb 8) applies: 128 <= Lx Ly <= 256
 bool tsl_plane_ok(const Geom& g);
+// the time-marching form (seq 3, d/dmu only) applies at this precision
+// (bytes per real): the plane shape applies and two planes of both input
+// fields fit the LDS
+bool tsl_march_ok(const Geom& g, int real_bytes);
+// blocks per right-hand side of the time-marching form with nseg time segments
+int tsl_march_blocks(const Geom& g, int nseg);
 template <typename T>
 void launch_tsl_stencil(const Geom& g, int dir, int nrhs, const StepPtrs& p, const cpx<T>* U,
                         const cpx<T>* dU, double m_diag, TslState* st, TslCoeffs co, double* partials,

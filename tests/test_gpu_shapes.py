@@ -165,3 +165,57 @@ def test_dwv_two_rhs_per_thread(prec, nrhs):
             assert rel(out[r], dirac.flat(ref(U, b[r].ravel(), dims, mu))) < tol, (op, r)
     assert ("rp2" in lat.tuned_shapes()) == (nrhs % 2 == 0)
     lat.close()
+
+
+@pytest.mark.parametrize("nseg", [1, 2, 4])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_time_marching_form(prec, order, nseg):
+    """The time-marching form of the d/dmu stencil, forced (XCD order, 1, 2 or
+    4 time segments), against the oracle on a 12 x 11 x 3 x 5 lattice.  Its 5
+    time slices split into segments of 5, of 3 + 2, and of 2 + 2 + 1 with an
+    empty fourth; the first slice of each segment takes its backward time hop
+    from the slice before (across the time boundary for the first segment),
+    and the last slice its forward hop across the boundary.  sgn(H)b, d/dmu
+    sgn(H)b and <x|dy> for the first and last of 8 sources: FP64 to 1e-10,
+    mixed to 3e-4 (the bound of the paired and sequential forms).  In FP64 the
+    result also agrees with the plane-in-LDS shape to 1e-11 (the two sum the
+    hops and the partial sums in different orders).  The seeds give a field
+    on which the oracle's own result moves by at most 6e-14 under
+    rounding-level noise (with links of seed 921 the last source moves by
+    3.8e-10, and no two FP64 summation orders agree to 1e-10 there)."""
+    import numpy as np
+
+    from paper_1611_00195_amd import ovderiv
+    from gpu_helpers import dev, host, ops, print_case, rel
+    dims, k, nrhs, mu = (12, 11, 3, 5), 32, 8, 0.3
+    print_case(test="time_marching", prec=prec, order=order, nseg=nseg, dims=dims, nrhs=nrhs)
+    p = ovderiv.FP64 if prec == "fp64" else ovderiv.MIXED
+    Uh = synth.make_links(dims, 0.5, 931)
+    bh = synth.make_sources(dims, nrhs, 932)
+    xh = synth.make_sources(dims, nrhs, 933)
+    U, b, x = dev(Uh), dev(bh), dev(xh)
+    lat = ovderiv.Lattice(dims, precision=p, shape=(order, nseg, 3))
+    lat.set_links(U)
+    y, dy, s = lat.sign_apply_deriv(b, mu, k, x=x)
+    assert f"map{order},gpb{nseg},march" in lat.tuned_shapes()
+    lat.close()
+    y, dy = host(y), host(dy)
+    h, hd, dh, dhd = ops(Uh, dims, mu)
+    tol = 1e-10 if prec == "fp64" else 3e-4
+    err = 0.0
+    for r in (0, nrhs - 1):
+        dref, yref, _ = tsl.krylov_sign_deriv(h, hd, dh, dhd, bh[r].ravel(), k)
+        sx = np.vdot(xh[r].ravel(), dref)
+        err = max(err, rel(y[r], yref), rel(dy[r], dref),
+                  abs(complex(s[r]) - sx) / (np.linalg.norm(xh[r]) * np.linalg.norm(dref)))
+    print(f"{prec} order {order}, {nseg} segments: {err:.2e} from the oracle")
+    assert err < tol
+    if prec == "fp64":
+        pl = ovderiv.Lattice(dims, precision=p, shape=(order, 8))
+        pl.set_links(U)
+        yp, dyp, sp = pl.sign_apply_deriv(b, mu, k, x=x)
+        pl.close()
+        d = max(rel(y, host(yp)), rel(dy, host(dyp)))
+        print(f"  from the plane shape: {d:.2e}")
+        assert d < 1e-11
