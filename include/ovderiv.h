@@ -88,7 +88,8 @@ typedef struct {
                                ranges per XCD); -1 (default): tuned or default */
     int shape_gpb;          /* > 0: force the site groups per block (Lanczos stencil: 1 or 2
                                for derivatives, 2 or 4 otherwise, or 8: one block per
-                               xy-plane staged in LDS, when 128 <= Lx Ly <= 256; Dw.v: 2 or 4;
+                               xy-plane staged in LDS, when 128 <= Lx Ly <= 256; Dw.v: 2 or 4,
+                               or 8 with shape_rp 2 under the same condition;
                                with shape_seq 3 the number of time segments, at most Lt);
                                0: tuned */
     int shape_seq;          /* Lanczos stencil without the derivative of a link field, not the

@@ -228,8 +228,9 @@ std::vector<StencilVariant> shape_candidates(int nrhs, const std::vector<int>& g
 }
 
 // Dw.v launch shapes: the stencil shapes, and for H and Dw on an even number
-// of right-hand sides each of them also with two right-hand sides per thread
-std::vector<StencilVariant> op_candidates(int nrhs, int op) {
+// of right-hand sides each of them also with two right-hand sides per thread,
+// and (plane: the xy-plane fits a block) two per thread with the plane in LDS
+std::vector<StencilVariant> op_candidates(int nrhs, int op, bool plane) {
     std::vector<StencilVariant> c = shape_candidates(nrhs, {4, 2});
     if ((op == 0 || op == 1) && nrhs % 2 == 0) {
         const size_t n = c.size();
@@ -239,8 +240,20 @@ std::vector<StencilVariant> op_candidates(int nrhs, int op) {
             if (v.map == 0 && (nrhs / 2) % 8 != 0) continue;   // the XCD order over pairs
             c.push_back(v);
         }
+        if (plane)
+            for (int map : {1, 0})
+                if (map == 1 || (nrhs / 2) % 8 == 0) c.push_back(StencilVariant{map, 8, 0, 2});
     }
     return c;
+}
+
+// a forced Dw.v shape made valid: 2 or 4 groups per block, or the plane in
+// LDS (8) with two right-hand sides per thread where that applies
+void op_shape_sanitize(StencilVariant& fv, int op, int nrhs, const Geom& g) {
+    fv.seq = 0;
+    if (!(op == 0 || op == 1) || nrhs % 2 != 0) fv.rp = 1;
+    if (fv.gpb == 8 && fv.rp == 2 && tsl_plane_ok(g)) return;
+    if (fv.gpb != 2) fv.gpb = 4;
 }
 
 // Whether a call keeps its Krylov basis (need bytes) or regenerates it:
@@ -1272,12 +1285,10 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
         };
         StencilVariant fv;
         if (forced_shape(h, nrhs, 4, &fv)) {
-            if (fv.gpb != 2) fv.gpb = 4;
-            fv.seq = 0;
-            if (!(op == 0 || op == 1) || nrhs % 2 != 0) fv.rp = 1;
+            op_shape_sanitize(fv, op, nrhs, g);
             h->tuned[key] = fv;
         } else if (!h->tuned.count(key)) {
-            h->tuned[key] = h->opt.autotune ? autotune(h, op_candidates(nrhs, op), launch, [] {})
+            h->tuned[key] = h->opt.autotune ? autotune(h, op_candidates(nrhs, op, tsl_plane_ok(g)), launch, [] {})
                                             : StencilVariant{default_map(nrhs), 4};
         }
         t.start(h->stream);
@@ -1293,12 +1304,10 @@ ovd_status ovd_apply_op(ovd_h h, int op, double mu, const ovd_dir* dir, int nrhs
         };
         StencilVariant fv;
         if (forced_shape(h, nrhs, 4, &fv)) {
-            if (fv.gpb != 2) fv.gpb = 4;
-            fv.seq = 0;
-            if (!(op == 0 || op == 1) || nrhs % 2 != 0) fv.rp = 1;
+            op_shape_sanitize(fv, op, nrhs, g);
             h->tuned[key] = fv;
         } else if (!h->tuned.count(key)) {
-            h->tuned[key] = h->opt.autotune ? autotune(h, op_candidates(nrhs, op), launch, [] {})
+            h->tuned[key] = h->opt.autotune ? autotune(h, op_candidates(nrhs, op, tsl_plane_ok(g)), launch, [] {})
                                             : StencilVariant{default_map(nrhs), 4};
         }
         t.start(h->stream);

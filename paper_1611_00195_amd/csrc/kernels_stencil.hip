@@ -403,6 +403,18 @@ __device__ __forceinline__ Work xcd_work(int bid, int nb, int nrhs, int map) {
     return w;
 }
 
+// GPB site groups (of 64) per block: DIR 0 has one pair per site (GPB waves),
+// DIR 1/2 two pairs per site (GPB groups x (v, w) waves)
+// GPB == PLANE_GPB: one block per (xy-plane, rhs, side) (DIR 0: (xy-plane,
+// rhs)), thread t at site t of the plane (Lx Ly <= 256), the plane's two input
+// fields staged in LDS for the x and y hops.
+constexpr int PLANE_GPB = 8;
+
+template <typename T, int I, int DIR, typename LoadA, typename LoadB>
+__device__ __forceinline__ void pair_hop(cpx<T> (&accA)[12], cpx<T> (&accB)[12], LoadA loadA, LoadB loadB,
+                                         const char* __restrict__ W, const char* __restrict__ W2, uint32_t Vp16,
+                                         uint32_t loff, T cA, T cB, T xAB, T xBA, bool vside);
+
 // ---------------------------------------------------------------------------
 // standalone operator
 // ---------------------------------------------------------------------------
@@ -492,6 +504,100 @@ __global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_pair_kernel(Geom g, c
     store12(out + (size_t)(r0 + 1) * 12 * Vp, s, Vp, accB);
 }
 
+// H or Dw on two right-hand sides per thread with the xy-plane in LDS: one
+// block per (xy-plane, pair), thread t at site t of the plane (Lx Ly <= 256).
+// The block stages the plane's two input fields in LDS; the x and y hops read
+// their neighbours there and the z and t hops from memory.  Hops, order and
+// arithmetic are those of apply_op_pair_kernel, so the outputs are the same.
+template <typename T, int OP>
+__global__ __launch_bounds__(256) OVD_OCC(T) void apply_op_plane_kernel(Geom g, const double* __restrict__ emu,
+                                                             const cpx<T>* __restrict__ U, T mdiag,
+                                                             const cpx<T>* __restrict__ in,
+                                                             cpx<T>* __restrict__ out, int npairs, int map) {
+    static_assert(OP == 0 || OP == 1, "paired form: H or Dw");
+    constexpr int NQ = sizeof(T) == 8 ? 12 : 6;   // 16-byte entries per site
+    extern __shared__ float4 plane_lds[];          // [field 2][NQ][P]
+    const int nb = (int)(gridDim.x / (unsigned)npairs);
+    const Work w = xcd_work((int)blockIdx.x, nb, npairs, map);
+    const int r0 = 2 * w.rhs;
+    const int Lx = g.L[0], Ly = g.L[1], P = Lx * Ly, Vp = g.Vp;
+    const int tid = (int)threadIdx.x;
+    const bool act = w.grp < g.V / P && tid < P;
+    const int s = w.grp * P + tid;
+    const cpx<T>* A = in + (size_t)r0 * 12 * Vp;
+    const cpx<T>* B = A + (size_t)12 * Vp;
+    auto lds_at = [&](int f, int q, int t) -> float4& { return plane_lds[((size_t)f * NQ + q) * P + t]; };
+    auto to_lds = [&](int f, int t, const cpx<T> (&v)[12]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float4 e;
+            if constexpr (sizeof(T) == 8) {
+                const double2 d{(double)v[q].re, (double)v[q].im};
+                e = *reinterpret_cast<const float4*>(&d);
+            } else {
+                e = float4{(float)v[2 * q].re, (float)v[2 * q].im, (float)v[2 * q + 1].re, (float)v[2 * q + 1].im};
+            }
+            lds_at(f, q, t) = e;
+        }
+    };
+    auto from_lds = [&](int f, int t, cpx<T> (&v)[12]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float4 e = lds_at(f, q, t);
+            if constexpr (sizeof(T) == 8) {
+                const double2 d = *reinterpret_cast<const double2*>(&e);
+                v[q] = cpx<T>{(T)d.x, (T)d.y};
+            } else {
+                v[2 * q] = cpx<T>{(T)e.x, (T)e.y};
+                v[2 * q + 1] = cpx<T>{(T)e.z, (T)e.w};
+            }
+        }
+    };
+    cpx<T> accA[12], accB[12];
+    if (act) {
+        load12(A, s, Vp, accA);
+        to_lds(0, tid, accA);
+        load12(B, s, Vp, accB);
+        to_lds(1, tid, accB);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            accA[c] = mdiag * accA[c];
+            accB[c] = mdiag * accB[c];
+        }
+    }
+    __syncthreads();   // the plane's inputs are in LDS (the block's only barrier)
+    if (!act) return;
+    const T epA = T(emu[2 * r0]), emA = T(emu[2 * r0 + 1]);
+    const T epB = T(emu[2 * r0 + 2]), emB = T(emu[2 * r0 + 3]);
+    const Nbr N = neighbours(g, s);
+    const char* W = reinterpret_cast<const char*>(U);
+    const uint32_t Vp16 = (uint32_t)Vp * 16u;
+    const int x = tid % Lx, y = tid / Lx;
+    const int txf = y * Lx + (x == Lx - 1 ? 0 : x + 1), txb = y * Lx + (x == 0 ? Lx - 1 : x - 1);
+    const int tyf = (y == Ly - 1 ? 0 : y + 1) * Lx + x, tyb = (y == 0 ? Ly - 1 : y - 1) * Lx + x;
+    const T h = T(-0.5), z = T(0);
+#define OVD_PO(I, TN, LS)                                                                                  \
+    pair_hop<T, I, 0>(                                                                                     \
+        accA, accB, [&](cpx<T>(&v)[12]) { from_lds(0, TN, v); }, [&](cpx<T>(&v)[12]) { from_lds(1, TN, v); }, \
+        W, W, Vp16, (uint32_t)(LS) * 16u, h, h, z, z, true);                                               \
+    OVD_HOP_FENCE;
+    OVD_PO(0, txf, s)
+    OVD_PO(1, txb, N.b[0])
+    OVD_PO(2, tyf, s)
+    OVD_PO(3, tyb, N.b[1])
+#undef OVD_PO
+    pair_hops<T, 0, true>(accA, accB, A, B, U, U, N, s, Vp, epA, emA, epB, emB, z, z, z, z, g.bc_t, true);
+    if (OP == 0) {
+#pragma unroll
+        for (int c = 6; c < 12; ++c) {   // gamma5
+            accA[c] = -accA[c];
+            accB[c] = -accB[c];
+        }
+    }
+    store12(out + (size_t)r0 * 12 * Vp, s, Vp, accA);
+    store12(out + (size_t)(r0 + 1) * 12 * Vp, s, Vp, accB);
+}
+
 template <typename T, int OP>
 static void launch_apply_op_v(const Geom& g, int nrhs, const double* d_emu, const cpx<T>* U, const cpx<T>* dU, T md,
                               const cpx<T>* in, cpx<T>* out, StencilVariant v, hipStream_t s) {
@@ -499,6 +605,21 @@ static void launch_apply_op_v(const Geom& g, int nrhs, const double* d_emu, cons
     const int gpb = v.gpb == 2 ? 2 : 4;
     const int nq = ((ngroups + gpb - 1) / gpb + 7) / 8 * 8;   // blocks of gpb site groups, padded to 8
     if constexpr (OP == 0 || OP == 1) {
+        if (v.rp == 2 && nrhs % 2 == 0 && v.gpb == PLANE_GPB && tsl_plane_ok(g)) {
+            const int np = nrhs / 2;
+            const int map = (v.map == 0 && np % 8 != 0) ? 1 : v.map;
+            const int planes = g.V / (g.L[0] * g.L[1]);
+            static bool attr = false;
+            if (!attr) {
+                (void)hipFuncSetAttribute((const void*)apply_op_plane_kernel<T, OP>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+                attr = true;
+            }
+            apply_op_plane_kernel<T, OP><<<dim3((planes + 7) / 8 * 8 * np), dim3(256),
+                                           (size_t)2 * 12 * g.L[0] * g.L[1] * sizeof(cpx<T>), s>>>(
+                g, d_emu, U, md, in, out, np, map);
+            return;
+        }
         if (v.rp == 2 && nrhs % 2 == 0) {
             const int np = nrhs / 2;
             const int map = (v.map == 0 && np % 8 != 0) ? 1 : v.map;
@@ -895,12 +1016,6 @@ __device__ __forceinline__ void nrm_acc(double* part, int i, const cpx<T> (&a)[1
     for (int c = 0; c < 12; ++c) part[i] += norm2(cast<double>(a[c]));
 }
 
-// GPB site groups (of 64) per block: DIR 0 has one pair per site (GPB waves),
-// DIR 1/2 two pairs per site (GPB groups x (v, w) waves)
-// GPB == PLANE_GPB: one block per (xy-plane, rhs, side) (DIR 0: (xy-plane,
-// rhs)), thread t at site t of the plane (Lx Ly <= 256), the plane's two input
-// fields staged in LDS for the x and y hops.
-constexpr int PLANE_GPB = 8;
 
 // The end of a stencil block: its partial sums into the step's grid reduction,
 // and in the last block of the rhs the step's scalars and the coefficients of

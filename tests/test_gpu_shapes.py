@@ -219,3 +219,41 @@ def test_time_marching_form(prec, order, nseg):
         d = max(rel(y, host(yp)), rel(dy, host(dyp)))
         print(f"  from the plane shape: {d:.2e}")
         assert d < 1e-11
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dwv_plane_in_lds(prec, order):
+    """Dw.v with two right-hand sides per thread and the xy-plane in LDS
+    (forced; a 12 x 11 x 3 x 5 lattice, 16 sources: 8 pairs, so both XCD
+    orders apply) against the oracle's H and Dw (FP64 to 1e-14, FP32 to 1e-6),
+    and against the paired form without LDS, which applies the same hops with
+    the same arithmetic up to the compiler's choice of fused multiply-adds
+    (to 1e-15 in FP64 and 4e-7 in FP32, relative to the largest element; at
+    14^4 the two differ by 3.0e-16 and 1.5e-7)."""
+    import numpy as np
+
+    from paper_1611_00195_amd import ovderiv
+    from oracle import dirac
+    from gpu_helpers import dev, host, print_case, rel
+    dims, mu, nrhs = (12, 11, 3, 5), 0.35, 16
+    print_case(test="dwv_plane", prec=prec, order=order, nrhs=nrhs, dims=dims)
+    p = ovderiv.FP64 if prec == "fp64" else ovderiv.MIXED
+    U = synth.make_links(dims, 0.5, 941)
+    b = synth.make_sources(dims, nrhs, 942)
+    lat = ovderiv.Lattice(dims, precision=p, shape=(order, 8, 0, 2))
+    lat.set_links(dev(U))
+    pair = ovderiv.Lattice(dims, precision=p, shape=(order, 4, 0, 2))
+    pair.set_links(dev(U))
+    tol, tpair = (1e-14, 1e-15) if prec == "fp64" else (1e-6, 4e-7)
+    for op, ref in ((ovderiv.OP_H, dirac.apply_h), (ovderiv.OP_DW, dirac.apply_dw)):
+        out = host(lat.apply_op(op, mu, dev(b)))
+        outp = host(pair.apply_op(op, mu, dev(b)))
+        d = np.abs(out - outp).max() / np.abs(outp).max()
+        print(f"{prec} order {order} op {op}: {d:.2e} from the paired form")
+        assert d < tpair
+        for r in (0, 7, nrhs - 1):
+            assert rel(out[r], dirac.flat(ref(U, b[r].ravel(), dims, mu))) < tol, (op, r)
+    assert f"map{order},gpb8,rp2" in lat.tuned_shapes()
+    lat.close()
+    pair.close()
