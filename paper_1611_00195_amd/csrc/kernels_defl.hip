@@ -49,7 +49,30 @@ __global__ __launch_bounds__(64) void defl_proj_kernel(const c64* __restrict__ A
     const c64* Ap = A + (va ? ia : 0) * sA;
     const c64* Bp = B + (vb ? rb : 0) * sB;
     v4d cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-    for (long long k = k0; k < k1; k += 4) {
+    // groups of 8 steps: the 16 loads of a group are issued before its first
+    // product, so a wave has them in flight together instead of waiting on one
+    // load per step; the products run in the same order as in the tail loop
+    // (an invalid row or column loads row 0 and uses zero)
+    long long k = k0;
+    const long long kg = k0 + (k1 - k0) / 32 * 32;
+    for (; k < kg; k += 32) {
+        c64 a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = Ap[k + 4 * u + kk];
+            b[u] = Bp[k + 4 * u + kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const c64 au = va ? a[u] : c64{0.0, 0.0};
+            const c64 bu = vb ? b[u] : c64{0.0, 0.0};
+            cre = mfma(au.re, bu.re, cre);
+            cre = mfma(au.im, bu.im, cre);
+            cim = mfma(au.re, bu.im, cim);
+            cim = mfma(-au.im, bu.re, cim);
+        }
+    }
+    for (; k < k1; k += 4) {
         const long long kl = k + kk;
         c64 a{0.0, 0.0}, b{0.0, 0.0};
         if (va && kl < k1) a = Ap[kl];
@@ -125,7 +148,31 @@ __global__ __launch_bounds__(64) void defl_comb_kernel(const c64* __restrict__ A
     const int rb = r0 + (l & 15);         // C column (rhs) of this lane
     const int kk = l >> 4;
     v4d yre = {0, 0, 0, 0}, yim = {0, 0, 0, 0};
-    for (int i = 0; i < m; i += 4) {
+    // groups of 8 steps with their loads issued first (as in the projection);
+    // an element or column past the end loads index 0 and uses zero
+    int i = 0;
+    const bool van = na < nf, vcr = rb < nr;
+    const long long nac = van ? na : 0;
+    const int rbc = vcr ? rb : 0;
+    for (; i + 32 <= m; i += 32) {
+        c64 a[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ik = i + 4 * u + kk;
+            a[u] = A[(size_t)ik * sA + nac];
+            c[u] = C[(size_t)ik * nr + rbc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const c64 au = van ? a[u] : c64{0.0, 0.0};
+            const c64 cu = vcr ? c[u] : c64{0.0, 0.0};
+            yre = mfma(au.re, cu.re, yre);
+            yre = mfma(-au.im, cu.im, yre);
+            yim = mfma(au.re, cu.im, yim);
+            yim = mfma(au.im, cu.re, yim);
+        }
+    }
+    for (; i < m; i += 4) {
         const int ik = i + kk;
         c64 a{0.0, 0.0}, c{0.0, 0.0};
         if (ik < m && na < nf) a = A[(size_t)ik * sA + na];
