@@ -148,31 +148,7 @@ __global__ __launch_bounds__(64) void defl_comb_kernel(const c64* __restrict__ A
     const int rb = r0 + (l & 15);         // C column (rhs) of this lane
     const int kk = l >> 4;
     v4d yre = {0, 0, 0, 0}, yim = {0, 0, 0, 0};
-    // groups of 8 steps with their loads issued first (as in the projection);
-    // an element or column past the end loads index 0 and uses zero
-    int i = 0;
-    const bool van = na < nf, vcr = rb < nr;
-    const long long nac = van ? na : 0;
-    const int rbc = vcr ? rb : 0;
-    for (; i + 32 <= m; i += 32) {
-        c64 a[8], c[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int ik = i + 4 * u + kk;
-            a[u] = A[(size_t)ik * sA + nac];
-            c[u] = C[(size_t)ik * nr + rbc];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const c64 au = van ? a[u] : c64{0.0, 0.0};
-            const c64 cu = vcr ? c[u] : c64{0.0, 0.0};
-            yre = mfma(au.re, cu.re, yre);
-            yre = mfma(-au.im, cu.im, yre);
-            yim = mfma(au.re, cu.im, yim);
-            yim = mfma(au.im, cu.re, yim);
-        }
-    }
-    for (; i < m; i += 4) {
+    for (int i = 0; i < m; i += 4) {
         const int ik = i + kk;
         c64 a{0.0, 0.0}, c{0.0, 0.0};
         if (ik < m && na < nf) a = A[(size_t)ik * sA + na];
