@@ -663,7 +663,10 @@ ovd_status run_tsl(ovd_h h, int nrhs, int k, int dir, const double* mu, const cp
                                  tsl_plane_ok(g) ? (dir == 0 ? std::vector<int>{4, 2, 8} : std::vector<int>{2, 1, 8})
                                                  : (dir == 0 ? std::vector<int>{4, 2} : std::vector<int>{2, 1}),
                                  dir != 2, dir == 0);
-            if (dir == 1 && tsl_march_ok(g, (int)sizeof(T)))   // the time-marching form, 1, 2 or 4 time segments
+            // the time-marching form (1, 2 or 4 time segments) from 16 right-hand
+            // sides on: at 8 the timing of single launches favoured it by a margin
+            // that the replayed steps did not show
+            if (dir == 1 && nrhs >= 16 && tsl_march_ok(g, (int)sizeof(T)))
                 for (int map : {1, 0}) {
                     if (map == 0 && nrhs % 8 != 0) continue;
                     for (int ns : {1, 2, 4})
